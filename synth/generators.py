@@ -1,0 +1,191 @@
+"""Seeded synthetic discrete-distribution workloads.
+
+This module only draws random inputs: ragged discrete distributions
+(support points + probability weights) stored in the concatenated layout of
+the paper's notation (Sec. 2: X = (x^(1), ..., x^(N)) in R^{d x n},
+n = sum_k m_k), plus initial-centroid member choices.  It contains none of
+the method's arithmetic and is shared by the FP64 oracle, the tests and the
+benchmark so that both sides consume bit-identical inputs.
+
+Layout of a workload (a plain dict of numpy arrays):
+  offsets : int64[N+1]   instance k owns support rows offsets[k]:offsets[k+1]
+  X       : float64[n, d] support points, row-major (one row per point)
+  W       : float64[n]    weights, each instance's weights sum to 1
+  classes : int64[N]      latent generating class (for information only)
+The paper's datasets (pixel-colour distributions, 20newsgroups word-vector
+bags, the Table 2 synthetic set) are not available; these generators stand
+in for them with the shapes listed in each function.
+
+Draw order (all from one numpy Generator(PCG64(seed))), per workload:
+  1. mixture/topic centres, 2. per-instance support sizes, 3. per-instance
+  latent class, 4. per-point component choice, 5. per-point noise,
+  6. per-point weight draws.  Changing any of these changes every later draw.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+__all__ = [
+    "WORKLOADS",
+    "make_workload",
+    "gaussian_mixture_workload",
+    "topic_sphere_workload",
+    "pick_init_members",
+    "round_to_bf16",
+]
+
+
+def _rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(int(seed)))
+
+
+def _ragged_dirichlet(rng, sizes, alpha):
+    """Dirichlet(alpha * 1_{m_k}) draws for every instance, concatenated."""
+    n = int(sizes.sum())
+    g = rng.gamma(alpha, 1.0, size=n)
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+    # guard against an all-underflowed instance (possible for tiny alpha)
+    sums = np.add.reduceat(g, offs[:-1])
+    bad = sums <= 0.0
+    if np.any(bad):
+        for k in np.nonzero(bad)[0]:
+            g[offs[k]:offs[k + 1]] = 1.0
+        sums = np.add.reduceat(g, offs[:-1])
+    return g / np.repeat(sums, sizes)
+
+
+def gaussian_mixture_workload(seed, N, d, mk_lo, mk_hi, n_comp, n_class,
+                              sigma, alpha, fixed_mk=None):
+    """Instances whose support points come from an isotropic Gaussian mixture.
+
+    Component means ~ U[0,1]^d.  Latent class l owns the contiguous block of
+    n_comp // n_class components; an instance picks its class uniformly, and
+    each of its points picks one of the class's components uniformly, then
+    x = mean + sigma * N(0, I_d).  Support sizes are uniform integers in
+    [mk_lo, mk_hi] (or all equal to fixed_mk).  Weights ~ Dirichlet(alpha).
+    """
+    rng = _rng(seed)
+    means = rng.uniform(0.0, 1.0, size=(n_comp, d))
+    if fixed_mk is not None:
+        sizes = np.full(N, int(fixed_mk), dtype=np.int64)
+    else:
+        sizes = rng.integers(mk_lo, mk_hi + 1, size=N).astype(np.int64)
+    classes = rng.integers(0, n_class, size=N).astype(np.int64)
+    per_class = n_comp // n_class
+    n = int(sizes.sum())
+    pt_class = np.repeat(classes, sizes)
+    comp = pt_class * per_class + rng.integers(0, per_class, size=n)
+    X = means[comp] + sigma * rng.standard_normal(size=(n, d))
+    W = _ragged_dirichlet(rng, sizes, alpha)
+    offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    return {"offsets": offsets, "X": np.ascontiguousarray(X, dtype=np.float64),
+            "W": W.astype(np.float64), "classes": classes, "d": d}
+
+
+def round_to_bf16(a):
+    """Round float64 values to the nearest bfloat16 value (ties to even).
+
+    The result is returned as float64 holding exactly representable bf16
+    values, so FP64, FP32 and BF16 consumers all see the same numbers.
+    """
+    f = np.asarray(a, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    lsb = (u >> np.uint64(16)) & np.uint64(1)
+    u = (u + np.uint64(0x7FFF) + lsb) >> np.uint64(16) << np.uint64(16)
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _zipf_bounded(rng, a, hi, size):
+    """Zipf(a) draws (support 1, 2, ...) redrawn until <= hi."""
+    out = rng.zipf(a, size=size).astype(np.int64)
+    bad = out > hi
+    while np.any(bad):
+        out[bad] = rng.zipf(a, size=int(bad.sum()))
+        bad = out > hi
+    return out
+
+
+def topic_sphere_workload(seed, N, d=64, n_topic=512, n_class=64, noise=0.3,
+                          zipf_a=1.2, mk_base=7, mk_max=64, count_max=1000,
+                          bf16=True):
+    """Bag-of-word-vector style instances on the unit sphere.
+
+    Topic centres are normalised N(0, I_d) vectors; class l owns topics
+    [l*t, (l+1)*t) with t = n_topic // n_class.  A point takes a topic of its
+    instance's class uniformly and is normalise(t + (noise/sqrt(d)) N(0,I_d)),
+    i.e. about `noise` radians of angular spread.  Support sizes are
+    mk_base + Z with Z ~ Zipf(zipf_a) redrawn until the size is <= mk_max;
+    weights are Zipf(zipf_a) counts (redrawn until <= count_max), normalised.
+    Points are rounded once to bf16 (so every consumer sees the same values).
+    """
+    rng = _rng(seed)
+    topics = rng.standard_normal(size=(n_topic, d))
+    topics /= np.linalg.norm(topics, axis=1, keepdims=True)
+    sizes = mk_base + _zipf_bounded(rng, zipf_a, mk_max - mk_base, N)
+    classes = rng.integers(0, n_class, size=N).astype(np.int64)
+    per_class = n_topic // n_class
+    n = int(sizes.sum())
+    pt_class = np.repeat(classes, sizes)
+    top = pt_class * per_class + rng.integers(0, per_class, size=n)
+    X = topics[top] + (noise / np.sqrt(d)) * rng.standard_normal(size=(n, d))
+    X /= np.linalg.norm(X, axis=1, keepdims=True)
+    if bf16:
+        X = round_to_bf16(X)
+    counts = _zipf_bounded(rng, zipf_a, count_max, n).astype(np.float64)
+    offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    sums = np.add.reduceat(counts, offsets[:-1])
+    W = counts / np.repeat(sums, sizes)
+    return {"offsets": offsets, "X": np.ascontiguousarray(X, dtype=np.float64),
+            "W": W, "classes": classes, "d": d}
+
+
+# The paper's workloads as parameter sets.  N can be overridden to get a
+# smaller instance of the same distribution (tests use this).
+WORKLOADS = {
+    # pixel-colour-like, one cluster (Sec. 4 pilot shapes): d=3, m_k=8
+    "cfg1": dict(kind="gmm", N=256, d=3, mk_lo=8, mk_hi=8, n_comp=4, n_class=1,
+                 sigma=0.1, alpha=1.0, K=1, m=8, T=200, rounds=0),
+    # full clustering loop, colour-like: d=3, m_k in [4,16]
+    "cfg2": dict(kind="gmm", N=65536, d=3, mk_lo=4, mk_hi=16, n_comp=32,
+                 n_class=16, sigma=0.05, alpha=0.5, K=16, m=16, T=100,
+                 rounds=10),
+    # word-vector bags: d=64, heavy-tailed m_k in [8,64]
+    "cfg3": dict(kind="topic", N=200000, d=64, K=64, m=32, T=100, rounds=1),
+    # Table 2 synthetic scale: d=16, m_k in [4,32]
+    "cfg4": dict(kind="gmm", N=2000000, d=16, mk_lo=4, mk_hi=32, n_comp=1024,
+                 n_class=256, sigma=0.1, alpha=1.0, K=256, m=16, T=50,
+                 rounds=5),
+}
+
+
+def make_workload(name, seed=None, N=None, replicate=0):
+    """Build a named workload; seed defaults to 1000*cfg_index + replicate."""
+    p = dict(WORKLOADS[name])
+    if seed is None:
+        seed = 1000 * int(name[-1]) + int(replicate)
+    if N is None:
+        N = p["N"]
+    if p["kind"] == "gmm":
+        wl = gaussian_mixture_workload(seed, N, p["d"], p["mk_lo"], p["mk_hi"],
+                                       p["n_comp"], p["n_class"], p["sigma"],
+                                       p["alpha"])
+    else:
+        wl = topic_sphere_workload(seed, N, d=p["d"])
+    wl.update(K=p["K"], m=p["m"], T=p["T"], rounds=p["rounds"], name=name,
+              seed=seed)
+    return wl
+
+
+def pick_init_members(offsets, K, m, seed):
+    """Choose K distinct instances with at least m support points.
+
+    These are the random members that seed the K initial centroids (the
+    paper initialises a centroid from a randomly chosen cluster member with at
+    least m support points, Sec. 5).  Returned as int64[K] instance indices.
+    """
+    sizes = np.diff(np.asarray(offsets))
+    elig = np.nonzero(sizes >= m)[0]
+    if len(elig) < K:
+        raise ValueError(f"only {len(elig)} instances have >= {m} points; need {K}")
+    rng = _rng(int(seed) + 7777777)
+    return np.sort(rng.choice(elig, size=K, replace=False)).astype(np.int64)
