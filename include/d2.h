@@ -1,0 +1,185 @@
+/*
+ * d2.h -- C ABI of the MI355X (gfx950) library for sparse-support
+ * Wasserstein barycenters by the modified Bregman ADMM and the D2-clustering
+ * loop built on them.
+ *
+ * Paper: Ye, Wu, Wang, Li, "Fast Discrete Distribution Clustering Using
+ * Wasserstein Barycenter with Sparse Support" (IEEE TSP 2017).  Passages
+ * are cited by section / equation label / algorithm name.
+ *
+ * Problem statement (Sec. 2): N instances P^(k) = {(w^(k)_j, x^(k)_j)},
+ * j < m_k, with x^(k)_j in R^d and w^(k) in the simplex; K centroids
+ * Q^(c) = {(w_i, x_i)}, i < m, one support size m for all centroids.
+ *
+ * Conventions for every call:
+ *  - Host arrays are plain C arrays owned by the caller; the library copies
+ *    what it keeps.  Host floating-point inputs/outputs are double; the
+ *    device computes in the dtype chosen at d2_create.
+ *  - Ragged instances use the paper's concatenated layout (Sec. 2, item 7):
+ *    offsets[N+1] (int64, offsets[0] = 0, non-decreasing), instance k owns
+ *    rows offsets[k] .. offsets[k+1]-1 of X (n x d, row-major) and W (n).
+ *  - Plans (coupling matrices, Sec. 2 items 8-9) of instance k are m x m_k,
+ *    column-major: entry (i, j) at m*offsets[k] + j*m + i of an m x n array.
+ *  - Every call returns a d2_status; on error the outputs are untouched and
+ *    d2_last_error() describes the failure.  No exception crosses the ABI.
+ *  - A context is used by one host thread at a time.  All device work runs
+ *    on the context's stream; calls that return host data synchronise it.
+ *  - Library limits: 1 <= m <= 64, 1 <= m_k <= 64 with m_k * pad(m) <= 2048
+ *    (pad(m) = next power of two >= max(m, 8)), d >= 1, K >= 1.
+ */
+#ifndef D2_H_
+#define D2_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  D2_OK = 0,
+  D2_EINVAL = 1,   /* bad argument or input data                          */
+  D2_ENOMEM = 2,   /* device or host allocation failed                   */
+  D2_EDEVICE = 3,  /* a HIP runtime call or kernel launch failed         */
+  D2_ENUMERIC = 4, /* a non-finite value appeared in centroids or objective */
+  D2_ESTATE = 5    /* call out of order (e.g. barycenter before labels)   */
+} d2_status;
+
+typedef enum { D2_F32 = 0, D2_F64 = 1 } d2_dtype;
+
+typedef enum {
+  D2_INIT_PRODUCT = 0, /* Pi2^0 = w_i w^(k)_j for every member (Sec. 5)     */
+  D2_INIT_CACHED = 1   /* cached Pi2 where the label did not change, else
+                          the product (Sec. 5 warm start)                   */
+} d2_init;
+
+/* Parameters of one B-ADMM centroid update (Sec. 3.2, Algorithm "Centroid
+ * Update with B-ADMM").  Defaults: rho0 2, tau 10, iters 100, eps 1e-16,
+ * rule 1, xplan 0, init D2_INIT_CACHED.  rho = rho0 * mean cost of the
+ * cluster at the call's initial support (Eq. (rho)); the support is updated
+ * by Eq. (updatex) after every iteration n with (n+1) % tau == 0. */
+typedef struct {
+  double rho0;
+  double eps;     /* added after each exponential product (Eq. badmmc0b/c1b) */
+  int32_t tau;    /* support-update period; >= 1                           */
+  int32_t iters;  /* B-ADMM iterations; >= 1                               */
+  int32_t rule;   /* 1: R1, Eq. (badmmw); 2: R2, Eq. (badmmw2)             */
+  int32_t xplan;  /* plan used by Eq. (updatex): 0 = Pi2 (only value)      */
+  int32_t init;   /* d2_init                                               */
+  int32_t fixed_support; /* 1: never update x (fixed-support barycenter)   */
+} d2_badmm_params;
+
+/* Parameters of the assignment distance: B-ADMM on one transport problem
+ * with both marginals fixed (the updates of Sec. 3.2 without the weight
+ * step), Pi2^0 = product coupling, rho = rho0 * mean cost of the pair. */
+typedef struct {
+  double rho0;
+  double eps;
+  int32_t iters;
+} d2_ot_params;
+
+typedef struct {
+  int32_t iters;        /* iterations run                                 */
+  int32_t n_empty;      /* clusters without members (centroid kept)       */
+  int32_t launches;     /* kernel launches issued                         */
+  int32_t graph;        /* 1 if the call replayed a captured HIP graph    */
+  double ms;            /* device time of the call (HIP events)           */
+} d2_badmm_stats;
+
+typedef struct d2_ctx d2_ctx;
+
+/* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t
+ * to run on (NULL: the library creates its own default-priority stream).
+ * dtype selects the device arithmetic (plans, costs, exponentials). */
+d2_status d2_create(d2_ctx** out, int device, d2_dtype dtype, void* hip_stream);
+/* Free every device buffer and graph of the context.  NULL is a no-op. */
+void d2_destroy(d2_ctx* ctx);
+/* Last error message of the context ("" if none). */
+const char* d2_last_error(const d2_ctx* ctx);
+
+/* Copy N ragged instances to the device (Sec. 2 notation).  Validates:
+ * offsets[0] = 0 and non-decreasing, 1 <= m_k within the library limits,
+ * finite X, W >= 0 and |sum_j w^(k)_j - 1| <= 1e-6 (each instance is then
+ * renormalised in double).  Any earlier instances, labels and plans are
+ * dropped.  Error D2_EINVAL names the first offending instance. */
+d2_status d2_load_instances(d2_ctx* ctx, int64_t N, int32_t d,
+                            const int64_t* offsets, const double* X,
+                            const double* W);
+
+/* Set the K centroids: Xc is K x m x d, Wc is K x m (rows in the simplex,
+ * |sum - 1| <= 1e-6, renormalised).  Requires loaded instances. */
+d2_status d2_centroids_set(d2_ctx* ctx, int32_t K, int32_t m,
+                           const double* Xc, const double* Wc);
+/* Copy the centroids out (Xc: K x m x d, Wc: K x m). */
+d2_status d2_centroids_get(d2_ctx* ctx, double* Xc, double* Wc);
+/* Initialise centroid c from instance members[c] (Sec. 5): its support is
+ * merged pairwise by Eq. (merge) -- the pair minimising
+ * w_a w_b ||x_a - x_b||^2 / (w_a + w_b), ties to the smallest (a, b), the
+ * merged point taking slot a -- until m points remain.  Each chosen member
+ * needs m_k >= m.  The random choice of members is the caller's. */
+d2_status d2_centroids_init(d2_ctx* ctx, int32_t K, int32_t m,
+                            const int64_t* members);
+
+/* Set / get the cluster label of every instance (values in [0, K)). */
+d2_status d2_labels_set(d2_ctx* ctx, const int32_t* labels);
+d2_status d2_labels_get(d2_ctx* ctx, int32_t* labels);
+
+/* Assignment step (Algorithm "D2 Clustering"): l^(k) = argmin_c D(Q^(c),
+ * P^(k)), D the B-ADMM transport value <C, Pi1> of `p`; ties go to the
+ * lowest c.  Updates the context's labels (the previous labels are kept to
+ * decide the warm start).  labels_out (N), dist_out (N, the minimal D) and
+ * n_changed may be NULL. */
+d2_status d2_assign(d2_ctx* ctx, const d2_ot_params* p, int32_t* labels_out,
+                    double* dist_out, int64_t* n_changed);
+
+/* Centroid update (Sec. 3.2, Algorithm "Centroid Update with B-ADMM") for
+ * all K clusters of the current labels in one batched pass: Lambda = 0,
+ * Pi2^0 per p->init, `iters` iterations of Eq. (badmmc0b)-(badmmc1),
+ * R1/R2 and Eq. (badmm2), support updates every tau.  Empty clusters keep
+ * their centroid.  The final Pi2 is cached for the next call's warm start.
+ * stats may be NULL. */
+d2_status d2_barycenter(d2_ctx* ctx, const d2_badmm_params* p,
+                        d2_badmm_stats* stats);
+
+/* Eq. (updatex) for every non-empty cluster from the cached Pi2 plans:
+ * x_i = sum_k sum_j Pi2_ij x^(k)_j / sum_k sum_j Pi2_ij.  Requires a
+ * previous d2_barycenter on the current labels. */
+d2_status d2_support_update(d2_ctx* ctx);
+
+/* Per-round record passed to the d2_cluster callback. */
+typedef struct {
+  int32_t round;
+  int64_t n_changed;     /* labels changed by this round's assignment      */
+  double assign_obj;     /* mean over instances of the minimal D           */
+  double ms_assign;      /* device time of the assignment                  */
+  double ms_barycenter;  /* device time of the centroid update             */
+} d2_round_info;
+
+typedef void (*d2_round_cb)(const d2_round_info* info, void* user);
+
+/* D2-clustering (Algorithm "D2 Clustering") for `rounds` rounds from the
+ * current centroids: assignment, then d2_barycenter with the cached-plan
+ * warm start (Sec. 5).  cb may be NULL. */
+d2_status d2_cluster(d2_ctx* ctx, int32_t rounds, const d2_badmm_params* bp,
+                     const d2_ot_params* op, d2_round_cb cb, void* user);
+
+/* Objective trace of the last d2_barycenter: trace[n*K + c] =
+ * (1/N_c) sum_k <C^(k), Pi1^(k)> of iteration n (0 for empty clusters);
+ * `max_iters` bounds the rows written.  rho (K, may be NULL) gets each
+ * cluster's rho. */
+d2_status d2_objective(d2_ctx* ctx, double* trace, int32_t max_iters,
+                       double* rho);
+
+/* Plans of instance k after the last d2_barycenter, each m x m_k
+ * column-major (Pi1, Pi2, Lambda); any pointer may be NULL. */
+d2_status d2_plans_get(d2_ctx* ctx, int64_t k, double* P1, double* P2,
+                       double* L);
+
+/* Sizes: N, n, d, K, m of the context (any pointer may be NULL). */
+d2_status d2_sizes(const d2_ctx* ctx, int64_t* N, int64_t* n, int32_t* d,
+                   int32_t* K, int32_t* m);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* D2_H_ */

@@ -1,0 +1,962 @@
+// C ABI implementation (include/d2.h): context, validation, work lists, the
+// B-ADMM launch schedule, centroid initialisation and the clustering loop.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/d2.h"
+#include "d2_kernels.hpp"
+
+namespace {
+
+int ilog2(int v) {
+  int r = 0;
+  while ((1 << r) < v) ++r;
+  return r;
+}
+int pad_rows(int m) { return 1 << std::max(3, ilog2(m)); }
+
+// ---------------------------------------------------------------------------
+// kernel tables indexed by [log2(MP) - 3][log2(R)]
+// ---------------------------------------------------------------------------
+template <typename T> struct Kern {
+  using BA = void (*)(d2k::Args<T>);
+  using AX = void (*)(d2k::Args<T>, int);
+  using AS = void (*)(d2k::AssignArgs<T>);
+  BA ba[4][6] = {};
+  AX aux[4][6] = {};
+  AS asg[4][6] = {};
+  template <int MP, int R> void add() {
+    ba[ilog2(MP) - 3][ilog2(R)] = &d2k::k_iter_ba<T, MP, R>;
+    aux[ilog2(MP) - 3][ilog2(R)] = &d2k::k_aux<T, MP, R>;
+    asg[ilog2(MP) - 3][ilog2(R)] = &d2k::k_assign<T, MP, R>;
+  }
+  Kern() {
+    add<8, 1>(); add<8, 2>(); add<8, 4>(); add<8, 8>();
+    add<16, 1>(); add<16, 2>(); add<16, 4>(); add<16, 8>(); add<16, 16>();
+    add<32, 1>(); add<32, 2>(); add<32, 4>(); add<32, 8>(); add<32, 16>();
+    add<32, 32>();
+    add<64, 1>(); add<64, 2>(); add<64, 4>(); add<64, 8>(); add<64, 16>();
+    add<64, 32>();
+  }
+};
+
+template <typename T> const Kern<T>& kern() {
+  static Kern<T> k;
+  return k;
+}
+
+}  // namespace
+
+struct d2_ctx {
+  int device = 0;
+  d2_dtype dt = D2_F32;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::string err;
+  // instances
+  int64_t N = 0, n = 0;
+  int d = 0, mk_max = 0;
+  std::vector<int64_t> h_off;
+  int64_t* d_off = nullptr;
+  void* d_X = nullptr;
+  void* d_W = nullptr;
+  // centroids (double on device, rows padded to MP)
+  int K = 0, m = 0, MP = 0, R = 0;
+  double* d_xc = nullptr;
+  double* d_wc = nullptr;
+  double* d_wbuf = nullptr;  // 2 x K x MP
+  double* d_rho = nullptr;
+  int* d_cnt = nullptr;
+  // labels
+  std::vector<int32_t> h_labels, h_cache_labels;
+  bool have_labels = false, have_cache = false;
+  int32_t* d_labels = nullptr;
+  double* d_best = nullptr;
+  // plans
+  void* d_P1 = nullptr;
+  void* d_P2 = nullptr;
+  void* d_L = nullptr;
+  void* d_C = nullptr;
+  bool onfly = true;
+  // work lists
+  int chunk_inst = 32;  // instances per chunk
+  int waves = 4;        // wavefronts per workgroup
+  int nchunks = 0, nch_cap = 0;
+  int32_t* d_work = nullptr;
+  d2k::Chunk* d_chunks = nullptr;
+  int2* d_ctab = nullptr;
+  double* d_ninv = nullptr;
+  double* d_cinv = nullptr;
+  uint8_t* d_warm = nullptr;
+  double* d_part = nullptr;
+  double* d_partx = nullptr;
+  std::vector<int2> h_ctab;
+  bool lists_valid = false;
+  // objective trace of the last barycenter
+  double* d_trace = nullptr;
+  int trace_cap = 0, trace_rows = 0;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+
+  d2_status fail(d2_status s, const std::string& msg) {
+    err = msg;
+    return s;
+  }
+  size_t esz() const { return dt == D2_F64 ? 8 : 4; }
+};
+
+#define HIPCHK(ctx, call)                                                 \
+  do {                                                                    \
+    hipError_t e_ = (call);                                               \
+    if (e_ != hipSuccess)                                                 \
+      return (ctx)->fail(D2_EDEVICE, std::string(#call) + ": " +          \
+                                         hipGetErrorString(e_));          \
+  } while (0)
+
+namespace {
+
+template <typename P> void dfree(P*& p) {
+  if (p) (void)hipFree((void*)p);
+  p = nullptr;
+}
+
+d2_status dalloc(d2_ctx* c, void** p, size_t bytes) {
+  *p = nullptr;
+  if (bytes == 0) bytes = 8;
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return c->fail(D2_ENOMEM, "hipMalloc(" + std::to_string(bytes) +
+                                  "): " + hipGetErrorString(e));
+  }
+  return D2_OK;
+}
+
+void free_plans(d2_ctx* c) {
+  dfree(c->d_P1);
+  dfree(c->d_P2);
+  dfree(c->d_L);
+  dfree(c->d_C);
+  c->have_cache = false;
+}
+
+void free_lists(d2_ctx* c) {
+  dfree(c->d_work);
+  dfree(c->d_chunks);
+  dfree(c->d_ctab);
+  dfree(c->d_ninv);
+  dfree(c->d_cinv);
+  dfree(c->d_warm);
+  dfree(c->d_part);
+  dfree(c->d_partx);
+  c->nch_cap = 0;
+  c->lists_valid = false;
+}
+
+void free_centroids(d2_ctx* c) {
+  dfree(c->d_xc);
+  dfree(c->d_wc);
+  dfree(c->d_wbuf);
+  dfree(c->d_rho);
+  dfree(c->d_cnt);
+  c->K = c->m = c->MP = 0;
+}
+
+void free_instances(d2_ctx* c) {
+  dfree(c->d_off);
+  dfree(c->d_X);
+  dfree(c->d_W);
+  dfree(c->d_labels);
+  dfree(c->d_best);
+  dfree(c->d_trace);
+  c->trace_cap = 0;
+  c->N = c->n = 0;
+  c->have_labels = false;
+  free_plans(c);
+  free_lists(c);
+}
+
+template <typename T>
+d2_status upload_conv(d2_ctx* c, void* dst, const double* src, size_t count) {
+  std::vector<T> tmp(count);
+  for (size_t q = 0; q < count; ++q) tmp[q] = (T)src[q];
+  HIPCHK(c, hipMemcpy(dst, tmp.data(), count * sizeof(T),
+                      hipMemcpyHostToDevice));
+  return D2_OK;
+}
+
+template <typename T>
+d2_status download_conv(d2_ctx* c, double* dst, const void* src,
+                        size_t count) {
+  std::vector<T> tmp(count);
+  HIPCHK(c, hipMemcpy(tmp.data(), src, count * sizeof(T),
+                      hipMemcpyDeviceToHost));
+  for (size_t q = 0; q < count; ++q) dst[q] = (double)tmp[q];
+  return D2_OK;
+}
+
+// Sec. 5, Eq. (merge): pairwise merge down to m points.  Ties go to the
+// lexicographically smallest pair; the merged point keeps the first slot.
+void merge_support(int mk, int d, const double* y, const double* wy, int m,
+                   double* x, double* w) {
+  std::vector<double> px(y, y + (size_t)mk * d), pw(wy, wy + mk);
+  int cnt = mk;
+  while (cnt > m) {
+    int ba = 0, bb = 1;
+    double best = INFINITY;
+    for (int p = 0; p < cnt; ++p)
+      for (int q = p + 1; q < cnt; ++q) {
+        double s = 0.0;
+        for (int t = 0; t < d; ++t) {
+          double df = px[(size_t)p * d + t] - px[(size_t)q * d + t];
+          s += df * df;
+        }
+        double ws = pw[p] + pw[q];
+        double cr = ws > 0.0 ? pw[p] * pw[q] * s / ws : 0.0;
+        if (cr < best) {
+          best = cr;
+          ba = p;
+          bb = q;
+        }
+      }
+    double ws = pw[ba] + pw[bb];
+    for (int t = 0; t < d; ++t) {
+      double v = ws > 0.0 ? (pw[ba] * px[(size_t)ba * d + t] +
+                             pw[bb] * px[(size_t)bb * d + t]) /
+                                ws
+                          : px[(size_t)ba * d + t];
+      px[(size_t)ba * d + t] = v;
+    }
+    pw[ba] = ws;
+    px.erase(px.begin() + (size_t)bb * d, px.begin() + (size_t)(bb + 1) * d);
+    pw.erase(pw.begin() + bb);
+    --cnt;
+  }
+  std::copy(px.begin(), px.begin() + (size_t)m * d, x);
+  std::copy(pw.begin(), pw.begin() + m, w);
+}
+
+d2_status ensure_centroid_bufs(d2_ctx* c, int K, int m) {
+  if (c->K == K && c->m == m && c->d_xc) return D2_OK;
+  free_centroids(c);
+  free_plans(c);
+  free_lists(c);
+  c->K = K;
+  c->m = m;
+  c->MP = pad_rows(m);
+  d2_status s;
+  if ((s = dalloc(c, (void**)&c->d_xc, sizeof(double) * K * c->MP * c->d)))
+    return s;
+  if ((s = dalloc(c, (void**)&c->d_wc, sizeof(double) * K * c->MP))) return s;
+  if ((s = dalloc(c, (void**)&c->d_wbuf, sizeof(double) * 2 * K * c->MP)))
+    return s;
+  if ((s = dalloc(c, (void**)&c->d_rho, sizeof(double) * K))) return s;
+  if ((s = dalloc(c, (void**)&c->d_cnt, sizeof(int) * K))) return s;
+  HIPCHK(c, hipMemset(c->d_cnt, 0, sizeof(int) * K));
+  HIPCHK(c, hipMemset(c->d_xc, 0, sizeof(double) * K * c->MP * c->d));
+  HIPCHK(c, hipMemset(c->d_wc, 0, sizeof(double) * K * c->MP));
+  return D2_OK;
+}
+
+d2_status check_limits(d2_ctx* c, int m) {
+  if (m < 1 || m > 64) return c->fail(D2_EINVAL, "m must be in [1, 64]");
+  int MP = pad_rows(m);
+  int cps = 64 / MP;
+  int slots = (c->mk_max + cps - 1) / cps;
+  if (slots > 32)
+    return c->fail(D2_EINVAL, "m_k * pad(m) exceeds 2048 entries (m_k max " +
+                                  std::to_string(c->mk_max) + ")");
+  if ((int64_t)MP * (c->d + 1) > 8192)
+    return c->fail(D2_EINVAL, "pad(m) * (d + 1) exceeds 8192");
+  return D2_OK;
+}
+
+d2_status set_centroids_host(d2_ctx* c, int K, int m, const double* Xc,
+                             const double* Wc) {
+  d2_status s = ensure_centroid_bufs(c, K, m);
+  if (s) return s;
+  const int MP = c->MP, d = c->d;
+  std::vector<double> hx((size_t)K * MP * d, 0.0), hw((size_t)K * MP, 0.0);
+  for (int q = 0; q < K; ++q) {
+    double sum = 0.0;
+    for (int i = 0; i < m; ++i) sum += Wc[(size_t)q * m + i];
+    for (int i = 0; i < m; ++i) {
+      hw[(size_t)q * MP + i] = Wc[(size_t)q * m + i] / sum;
+      for (int t = 0; t < d; ++t)
+        hx[((size_t)q * MP + i) * d + t] = Xc[((size_t)q * m + i) * d + t];
+    }
+  }
+  HIPCHK(c, hipMemcpy(c->d_xc, hx.data(), hx.size() * 8,
+                      hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->d_wc, hw.data(), hw.size() * 8,
+                      hipMemcpyHostToDevice));
+  return D2_OK;
+}
+
+// Cluster-sorted work list, chunks and per-cluster tables for the labels.
+d2_status build_lists(d2_ctx* c, bool warm_start) {
+  const int K = c->K;
+  const int64_t N = c->N;
+  std::vector<int64_t> cnt(K, 0), ncols(K, 0);
+  for (int64_t k = 0; k < N; ++k) {
+    int l = c->h_labels[k];
+    cnt[l]++;
+    ncols[l] += c->h_off[k + 1] - c->h_off[k];
+  }
+  std::vector<int64_t> start(K + 1, 0);
+  for (int q = 0; q < K; ++q) start[q + 1] = start[q] + cnt[q];
+  std::vector<int32_t> work(N);
+  {
+    std::vector<int64_t> pos(start.begin(), start.end() - 1);
+    for (int64_t k = 0; k < N; ++k) work[pos[c->h_labels[k]]++] = (int32_t)k;
+  }
+  std::vector<d2k::Chunk> chunks;
+  c->h_ctab.assign(K, make_int2(0, 0));
+  std::vector<double> ninv(K, 0.0), cinv(K, 0.0);
+  const int CH = c->chunk_inst;
+  for (int q = 0; q < K; ++q) {
+    c->h_ctab[q].x = (int)chunks.size();
+    for (int64_t b = start[q]; b < start[q + 1]; b += CH) {
+      d2k::Chunk ck;
+      ck.cluster = q;
+      ck.begin = (int32_t)b;
+      ck.end = (int32_t)std::min<int64_t>(b + CH, start[q + 1]);
+      ck.pad = 0;
+      chunks.push_back(ck);
+    }
+    c->h_ctab[q].y = (int)chunks.size() - c->h_ctab[q].x;
+    if (cnt[q] > 0) {
+      ninv[q] = 1.0 / (double)cnt[q];
+      cinv[q] = 1.0 / ((double)c->m * (double)ncols[q]);
+    }
+  }
+  c->nchunks = (int)chunks.size();
+  int cap = (int)((N + CH - 1) / CH) + K;
+  if (cap > c->nch_cap || !c->d_work) {
+    free_lists(c);
+    d2_status s;
+    c->nch_cap = cap;
+    if ((s = dalloc(c, (void**)&c->d_work, sizeof(int32_t) * N))) return s;
+    if ((s = dalloc(c, (void**)&c->d_chunks, sizeof(d2k::Chunk) * cap)))
+      return s;
+    if ((s = dalloc(c, (void**)&c->d_ctab, sizeof(int2) * K))) return s;
+    if ((s = dalloc(c, (void**)&c->d_ninv, sizeof(double) * K))) return s;
+    if ((s = dalloc(c, (void**)&c->d_cinv, sizeof(double) * K))) return s;
+    if ((s = dalloc(c, (void**)&c->d_warm, N))) return s;
+    if ((s = dalloc(c, (void**)&c->d_part,
+                    sizeof(double) * cap * (c->MP + 2))))
+      return s;
+    if ((s = dalloc(c, (void**)&c->d_partx,
+                    sizeof(double) * cap * c->MP * (c->d + 1))))
+      return s;
+  }
+  std::vector<uint8_t> warm(N, 0);
+  if (warm_start && c->have_cache)
+    for (int64_t k = 0; k < N; ++k)
+      warm[k] = c->h_labels[k] == c->h_cache_labels[k];
+  HIPCHK(c, hipMemcpy(c->d_work, work.data(), sizeof(int32_t) * N,
+                      hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->d_chunks, chunks.data(),
+                      sizeof(d2k::Chunk) * std::max<size_t>(1, chunks.size()),
+                      hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->d_ctab, c->h_ctab.data(), sizeof(int2) * K,
+                      hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->d_ninv, ninv.data(), sizeof(double) * K,
+                      hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->d_cinv, cinv.data(), sizeof(double) * K,
+                      hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->d_warm, warm.data(), N, hipMemcpyHostToDevice));
+  c->lists_valid = true;
+  return D2_OK;
+}
+
+d2_status ensure_plans(d2_ctx* c) {
+  if (c->d_P1) return D2_OK;
+  size_t bytes = (size_t)c->m * c->n * c->esz();
+  d2_status s;
+  if ((s = dalloc(c, &c->d_P1, bytes))) return s;
+  if ((s = dalloc(c, &c->d_P2, bytes))) return s;
+  if ((s = dalloc(c, &c->d_L, bytes))) return s;
+  c->onfly = c->d <= 4;
+  if (!c->onfly && (s = dalloc(c, &c->d_C, bytes))) return s;
+  return D2_OK;
+}
+
+template <typename T>
+d2k::Args<T> make_args(d2_ctx* c, const d2_badmm_params* p) {
+  d2k::Args<T> a;
+  a.off = c->d_off;
+  a.X = (const T*)c->d_X;
+  a.W = (const T*)c->d_W;
+  a.work = c->d_work;
+  a.chunks = c->d_chunks;
+  a.ctab = c->d_ctab;
+  a.ninv = c->d_ninv;
+  a.cinv = c->d_cinv;
+  a.P1 = (T*)c->d_P1;
+  a.P2 = (T*)c->d_P2;
+  a.L = (T*)c->d_L;
+  a.Cc = (T*)c->d_C;
+  a.warm = c->d_warm;
+  a.xc = c->d_xc;
+  a.w_in = c->d_wbuf;
+  a.w_out = c->d_wbuf;
+  a.rho = c->d_rho;
+  a.part = c->d_part;
+  a.partx = c->d_partx;
+  a.cnt = c->d_cnt;
+  a.trace = nullptr;
+  a.rho0 = p ? p->rho0 : 2.0;
+  a.eps = p ? p->eps : 1e-16;
+  a.m = c->m;
+  a.d = c->d;
+  a.rule = p ? p->rule : 1;
+  a.ps = c->MP + 2;
+  a.onfly = c->onfly ? 1 : 0;
+  a.nchunks = c->nchunks;
+  return a;
+}
+
+template <typename T>
+d2_status launch_aux(d2_ctx* c, const d2k::Args<T>& a, int mode, int& nl) {
+  const auto& kt = kern<T>();
+  auto fn = kt.aux[ilog2(c->MP) - 3][ilog2(c->R)];
+  if (!fn) return c->fail(D2_EINVAL, "no kernel for this tile shape");
+  int waves = c->waves;
+  size_t per_wave = sizeof(double) * c->MP * (c->d + 1);
+  bool xnum = (mode == d2k::kBX || mode == d2k::kXO);
+  if (xnum)
+    while (waves > 1 && per_wave * waves > 64 * 1024) --waves;
+  size_t shm = xnum ? per_wave * waves : 0;
+  hipLaunchKernelGGL(fn, dim3(c->nchunks), dim3(64 * waves), shm, c->stream,
+                     a, mode);
+  HIPCHK(c, hipGetLastError());
+  ++nl;
+  return D2_OK;
+}
+
+template <typename T>
+d2_status launch_ba(d2_ctx* c, const d2k::Args<T>& a, int& nl) {
+  const auto& kt = kern<T>();
+  auto fn = kt.ba[ilog2(c->MP) - 3][ilog2(c->R)];
+  if (!fn) return c->fail(D2_EINVAL, "no kernel for this tile shape");
+  hipLaunchKernelGGL(fn, dim3(c->nchunks), dim3(64 * c->waves), 0, c->stream,
+                     a);
+  HIPCHK(c, hipGetLastError());
+  ++nl;
+  return D2_OK;
+}
+
+template <typename T>
+d2_status run_barycenter(d2_ctx* c, const d2_badmm_params* p,
+                         d2_badmm_stats* st) {
+  const int K = c->K, MP = c->MP, T_ = p->iters, tau = p->tau;
+  if (T_ > c->trace_cap) {
+    dfree(c->d_trace);
+    d2_status s = dalloc(c, (void**)&c->d_trace, sizeof(double) * T_ * K);
+    if (s) return s;
+    c->trace_cap = T_;
+  }
+  HIPCHK(c, hipMemsetAsync(c->d_trace, 0, sizeof(double) * T_ * K,
+                           c->stream));
+  // both weight buffers start at the current weights (empty clusters keep
+  // them through the call)
+  HIPCHK(c, hipMemcpyAsync(c->d_wbuf, c->d_wc, sizeof(double) * K * MP,
+                           hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->d_wbuf + K * MP, c->d_wc,
+                           sizeof(double) * K * MP, hipMemcpyDeviceToDevice,
+                           c->stream));
+  HIPCHK(c, hipEventRecord(c->ev0, c->stream));
+  int nl = 0;
+  d2k::Args<T> a = make_args<T>(c, p);
+  double* wb0 = c->d_wbuf;
+  double* wb1 = c->d_wbuf + K * MP;
+  auto wbuf = [&](int q) { return (q & 1) ? wb1 : wb0; };
+  d2_status s;
+  if ((s = launch_aux<T>(c, a, d2k::kRho, nl))) return s;
+  a.w_in = wbuf(0);
+  a.w_out = wbuf(1);
+  a.trace = c->d_trace;
+  if ((s = launch_aux<T>(c, a, d2k::kA0, nl))) return s;
+  for (int n = 0; n < T_; ++n) {
+    bool xupd = !p->fixed_support && ((n + 1) % tau == 0);
+    a.w_in = wbuf(n + 1);
+    a.w_out = wbuf(n + 2);
+    a.trace = c->d_trace + (size_t)(n + 1) * K;
+    if (n == T_ - 1) {
+      if ((s = launch_aux<T>(c, a, xupd ? d2k::kBX : d2k::kBF, nl))) return s;
+    } else if (xupd) {
+      if ((s = launch_aux<T>(c, a, d2k::kBX, nl))) return s;
+      if ((s = launch_aux<T>(c, a, d2k::kAP, nl))) return s;
+    } else {
+      if ((s = launch_ba<T>(c, a, nl))) return s;
+    }
+  }
+  HIPCHK(c, hipEventRecord(c->ev1, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->d_wc, wbuf(T_), sizeof(double) * K * MP,
+                           hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  float ms = 0.f;
+  HIPCHK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+  c->trace_rows = T_;
+  c->h_cache_labels = c->h_labels;
+  c->have_cache = true;
+  // non-finite guard on the new centroids
+  std::vector<double> hx((size_t)K * MP * c->d), hw((size_t)K * MP);
+  HIPCHK(c, hipMemcpy(hx.data(), c->d_xc, hx.size() * 8,
+                      hipMemcpyDeviceToHost));
+  HIPCHK(c, hipMemcpy(hw.data(), c->d_wc, hw.size() * 8,
+                      hipMemcpyDeviceToHost));
+  for (double v : hx)
+    if (!std::isfinite(v))
+      return c->fail(D2_ENUMERIC, "non-finite centroid support");
+  for (double v : hw)
+    if (!std::isfinite(v))
+      return c->fail(D2_ENUMERIC, "non-finite centroid weights");
+  if (st) {
+    st->iters = T_;
+    int ne = 0;
+    for (int q = 0; q < K; ++q) ne += c->h_ctab[q].y == 0;
+    st->n_empty = ne;
+    st->launches = nl;
+    st->graph = 0;
+    st->ms = ms;
+  }
+  return D2_OK;
+}
+
+int slots_for(const d2_ctx* c) {
+  int cps = 64 / c->MP;
+  int need = (c->mk_max + cps - 1) / cps;
+  return 1 << ilog2(std::max(1, need));
+}
+
+template <typename T>
+d2_status run_assign(d2_ctx* c, const d2_ot_params* p, float* ms_out) {
+  const auto& kt = kern<T>();
+  auto fn = kt.asg[ilog2(c->MP) - 3][ilog2(c->R)];
+  if (!fn) return c->fail(D2_EINVAL, "no kernel for this tile shape");
+  d2k::AssignArgs<T> a;
+  a.off = c->d_off;
+  a.X = (const T*)c->d_X;
+  a.W = (const T*)c->d_W;
+  a.xc = c->d_xc;
+  a.wc = c->d_wc;
+  a.labels = c->d_labels;
+  a.best = c->d_best;
+  a.N = c->N;
+  a.rho0 = p->rho0;
+  a.eps = p->eps;
+  a.m = c->m;
+  a.d = c->d;
+  a.K = c->K;
+  a.iters = p->iters;
+  const int wpb = 4;
+  int64_t blocks = (c->N + wpb - 1) / wpb;
+  HIPCHK(c, hipEventRecord(c->ev0, c->stream));
+  hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(64 * wpb), 0, c->stream,
+                     a);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipEventRecord(c->ev1, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  float ms = 0.f;
+  HIPCHK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+  if (ms_out) *ms_out = ms;
+  return D2_OK;
+}
+
+bool finite_all(const double* p, size_t n) {
+  for (size_t q = 0; q < n; ++q)
+    if (!std::isfinite(p[q])) return false;
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+d2_status d2_create(d2_ctx** out, int device, d2_dtype dtype,
+                    void* hip_stream) {
+  if (!out) return D2_EINVAL;
+  *out = nullptr;
+  if (dtype != D2_F32 && dtype != D2_F64) return D2_EINVAL;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 ||
+      device >= ndev) {
+    (void)hipGetLastError();
+    return D2_EDEVICE;
+  }
+  d2_ctx* c = new d2_ctx();
+  c->device = device;
+  c->dt = dtype;
+  if (hipSetDevice(device) != hipSuccess) {
+    delete c;
+    return D2_EDEVICE;
+  }
+  if (hip_stream) {
+    c->stream = (hipStream_t)hip_stream;
+  } else {
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) !=
+        hipSuccess) {
+      delete c;
+      return D2_EDEVICE;
+    }
+    c->own_stream = true;
+  }
+  if (hipEventCreate(&c->ev0) != hipSuccess ||
+      hipEventCreate(&c->ev1) != hipSuccess) {
+    delete c;
+    return D2_EDEVICE;
+  }
+  *out = c;
+  return D2_OK;
+}
+
+void d2_destroy(d2_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  free_instances(c);
+  free_centroids(c);
+  if (c->ev0) (void)hipEventDestroy(c->ev0);
+  if (c->ev1) (void)hipEventDestroy(c->ev1);
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
+const char* d2_last_error(const d2_ctx* c) {
+  return c ? c->err.c_str() : "null context";
+}
+
+d2_status d2_load_instances(d2_ctx* c, int64_t N, int32_t d,
+                            const int64_t* offsets, const double* X,
+                            const double* W) {
+  if (!c) return D2_EINVAL;
+  if (N < 1 || d < 1 || !offsets || !X || !W)
+    return c->fail(D2_EINVAL, "need N >= 1, d >= 1 and non-null arrays");
+  if (offsets[0] != 0) return c->fail(D2_EINVAL, "offsets[0] must be 0");
+  int mkmax = 0;
+  for (int64_t k = 0; k < N; ++k) {
+    int64_t mk = offsets[k + 1] - offsets[k];
+    if (mk < 1 || mk > 64)
+      return c->fail(D2_EINVAL, "instance " + std::to_string(k) +
+                                    ": support size must be in [1, 64]");
+    mkmax = std::max<int>(mkmax, (int)mk);
+  }
+  const int64_t n = offsets[N];
+  if (n > INT32_MAX) return c->fail(D2_EINVAL, "n exceeds 2^31 - 1");
+  std::vector<double> Wn(W, W + n);
+  for (int64_t k = 0; k < N; ++k) {
+    double s = 0.0;
+    for (int64_t j = offsets[k]; j < offsets[k + 1]; ++j) {
+      if (!(W[j] >= 0.0) || !std::isfinite(W[j]))
+        return c->fail(D2_EINVAL, "instance " + std::to_string(k) +
+                                      ": weights must be finite and >= 0");
+      for (int t = 0; t < d; ++t)
+        if (!std::isfinite(X[j * d + t]))
+          return c->fail(D2_EINVAL, "instance " + std::to_string(k) +
+                                        ": non-finite support point");
+      s += W[j];
+    }
+    if (!(std::fabs(s - 1.0) <= 1e-6))
+      return c->fail(D2_EINVAL, "instance " + std::to_string(k) +
+                                    ": weights do not sum to 1");
+    for (int64_t j = offsets[k]; j < offsets[k + 1]; ++j) Wn[j] = W[j] / s;
+  }
+  HIPCHK(c, hipSetDevice(c->device));
+  free_instances(c);
+  free_centroids(c);
+  c->N = N;
+  c->n = n;
+  c->d = d;
+  c->mk_max = mkmax;
+  c->h_off.assign(offsets, offsets + N + 1);
+  d2_status s;
+  if ((s = dalloc(c, (void**)&c->d_off, sizeof(int64_t) * (N + 1)))) return s;
+  if ((s = dalloc(c, &c->d_X, c->esz() * n * d))) return s;
+  if ((s = dalloc(c, &c->d_W, c->esz() * n))) return s;
+  if ((s = dalloc(c, (void**)&c->d_labels, sizeof(int32_t) * N))) return s;
+  if ((s = dalloc(c, (void**)&c->d_best, sizeof(double) * N))) return s;
+  HIPCHK(c, hipMemcpy(c->d_off, offsets, sizeof(int64_t) * (N + 1),
+                      hipMemcpyHostToDevice));
+  if (c->dt == D2_F64) {
+    if ((s = upload_conv<double>(c, c->d_X, X, (size_t)n * d))) return s;
+    if ((s = upload_conv<double>(c, c->d_W, Wn.data(), n))) return s;
+  } else {
+    if ((s = upload_conv<float>(c, c->d_X, X, (size_t)n * d))) return s;
+    if ((s = upload_conv<float>(c, c->d_W, Wn.data(), n))) return s;
+  }
+  c->h_labels.assign(N, 0);
+  return D2_OK;
+}
+
+d2_status d2_centroids_set(d2_ctx* c, int32_t K, int32_t m, const double* Xc,
+                           const double* Wc) {
+  if (!c) return D2_EINVAL;
+  if (!c->N) return c->fail(D2_ESTATE, "load instances first");
+  if (K < 1 || !Xc || !Wc) return c->fail(D2_EINVAL, "bad centroid arguments");
+  d2_status s = check_limits(c, m);
+  if (s) return s;
+  if (!finite_all(Xc, (size_t)K * m * c->d))
+    return c->fail(D2_EINVAL, "non-finite centroid support");
+  for (int q = 0; q < K; ++q) {
+    double sum = 0.0;
+    for (int i = 0; i < m; ++i) {
+      double v = Wc[(size_t)q * m + i];
+      if (!(v >= 0.0) || !std::isfinite(v))
+        return c->fail(D2_EINVAL, "centroid weights must be finite, >= 0");
+      sum += v;
+    }
+    if (!(std::fabs(sum - 1.0) <= 1e-6))
+      return c->fail(D2_EINVAL, "centroid " + std::to_string(q) +
+                                    ": weights do not sum to 1");
+  }
+  HIPCHK(c, hipSetDevice(c->device));
+  bool reshape = (K != c->K || m != c->m);
+  if ((s = set_centroids_host(c, K, m, Xc, Wc))) return s;
+  c->R = slots_for(c);
+  if (reshape) {
+    c->have_labels = false;
+    c->have_cache = false;
+  }
+  return D2_OK;
+}
+
+d2_status d2_centroids_get(d2_ctx* c, double* Xc, double* Wc) {
+  if (!c) return D2_EINVAL;
+  if (!c->d_xc) return c->fail(D2_ESTATE, "no centroids");
+  HIPCHK(c, hipSetDevice(c->device));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  const int K = c->K, m = c->m, MP = c->MP, d = c->d;
+  std::vector<double> hx((size_t)K * MP * d), hw((size_t)K * MP);
+  HIPCHK(c, hipMemcpy(hx.data(), c->d_xc, hx.size() * 8,
+                      hipMemcpyDeviceToHost));
+  HIPCHK(c, hipMemcpy(hw.data(), c->d_wc, hw.size() * 8,
+                      hipMemcpyDeviceToHost));
+  for (int q = 0; q < K; ++q)
+    for (int i = 0; i < m; ++i) {
+      if (Wc) Wc[(size_t)q * m + i] = hw[(size_t)q * MP + i];
+      if (Xc)
+        for (int t = 0; t < d; ++t)
+          Xc[((size_t)q * m + i) * d + t] = hx[((size_t)q * MP + i) * d + t];
+    }
+  return D2_OK;
+}
+
+d2_status d2_centroids_init(d2_ctx* c, int32_t K, int32_t m,
+                            const int64_t* members) {
+  if (!c) return D2_EINVAL;
+  if (!c->N) return c->fail(D2_ESTATE, "load instances first");
+  if (K < 1 || !members) return c->fail(D2_EINVAL, "bad init arguments");
+  d2_status s = check_limits(c, m);
+  if (s) return s;
+  const int d = c->d;
+  // instance data back from the device is not needed: keep a host copy
+  // of the chosen members only
+  std::vector<double> Xc((size_t)K * m * d), Wc((size_t)K * m);
+  for (int q = 0; q < K; ++q) {
+    int64_t k = members[q];
+    if (k < 0 || k >= c->N)
+      return c->fail(D2_EINVAL, "member index out of range");
+    int mk = (int)(c->h_off[k + 1] - c->h_off[k]);
+    if (mk < m)
+      return c->fail(D2_EINVAL, "member " + std::to_string(k) +
+                                    " has fewer than m support points");
+    std::vector<double> y((size_t)mk * d), wy(mk);
+    if (c->dt == D2_F64) {
+      if ((s = download_conv<double>(c, y.data(),
+                                     (const double*)c->d_X + c->h_off[k] * d,
+                                     (size_t)mk * d)))
+        return s;
+      if ((s = download_conv<double>(c, wy.data(),
+                                     (const double*)c->d_W + c->h_off[k], mk)))
+        return s;
+    } else {
+      if ((s = download_conv<float>(c, y.data(),
+                                    (const float*)c->d_X + c->h_off[k] * d,
+                                    (size_t)mk * d)))
+        return s;
+      if ((s = download_conv<float>(c, wy.data(),
+                                    (const float*)c->d_W + c->h_off[k], mk)))
+        return s;
+    }
+    merge_support(mk, d, y.data(), wy.data(), m, &Xc[(size_t)q * m * d],
+                  &Wc[(size_t)q * m]);
+  }
+  return d2_centroids_set(c, K, m, Xc.data(), Wc.data());
+}
+
+d2_status d2_labels_set(d2_ctx* c, const int32_t* labels) {
+  if (!c) return D2_EINVAL;
+  if (!c->N || !c->K) return c->fail(D2_ESTATE, "need instances, centroids");
+  if (!labels) return c->fail(D2_EINVAL, "null labels");
+  for (int64_t k = 0; k < c->N; ++k)
+    if (labels[k] < 0 || labels[k] >= c->K)
+      return c->fail(D2_EINVAL, "label out of range at " + std::to_string(k));
+  HIPCHK(c, hipSetDevice(c->device));
+  c->h_labels.assign(labels, labels + c->N);
+  HIPCHK(c, hipMemcpy(c->d_labels, labels, sizeof(int32_t) * c->N,
+                      hipMemcpyHostToDevice));
+  c->have_labels = true;
+  c->lists_valid = false;
+  return D2_OK;
+}
+
+d2_status d2_labels_get(d2_ctx* c, int32_t* labels) {
+  if (!c) return D2_EINVAL;
+  if (!c->have_labels) return c->fail(D2_ESTATE, "no labels");
+  if (!labels) return c->fail(D2_EINVAL, "null labels");
+  std::copy(c->h_labels.begin(), c->h_labels.end(), labels);
+  return D2_OK;
+}
+
+d2_status d2_assign(d2_ctx* c, const d2_ot_params* p, int32_t* labels_out,
+                    double* dist_out, int64_t* n_changed) {
+  if (!c) return D2_EINVAL;
+  if (!c->N || !c->K) return c->fail(D2_ESTATE, "need instances, centroids");
+  if (!p || p->iters < 1 || !(p->rho0 > 0) || !(p->eps >= 0))
+    return c->fail(D2_EINVAL, "bad transport parameters");
+  HIPCHK(c, hipSetDevice(c->device));
+  d2_status s = c->dt == D2_F64 ? run_assign<double>(c, p, nullptr)
+                                : run_assign<float>(c, p, nullptr);
+  if (s) return s;
+  std::vector<int32_t> lab(c->N);
+  HIPCHK(c, hipMemcpy(lab.data(), c->d_labels, sizeof(int32_t) * c->N,
+                      hipMemcpyDeviceToHost));
+  int64_t changed = 0;
+  for (int64_t k = 0; k < c->N; ++k)
+    changed += (!c->have_labels || lab[k] != c->h_labels[k]);
+  c->h_labels.swap(lab);
+  c->have_labels = true;
+  c->lists_valid = false;
+  if (labels_out) std::copy(c->h_labels.begin(), c->h_labels.end(), labels_out);
+  if (dist_out)
+    HIPCHK(c, hipMemcpy(dist_out, c->d_best, sizeof(double) * c->N,
+                        hipMemcpyDeviceToHost));
+  if (n_changed) *n_changed = changed;
+  return D2_OK;
+}
+
+d2_status d2_barycenter(d2_ctx* c, const d2_badmm_params* p,
+                        d2_badmm_stats* st) {
+  if (!c) return D2_EINVAL;
+  if (!c->N || !c->K) return c->fail(D2_ESTATE, "need instances, centroids");
+  if (!c->have_labels) return c->fail(D2_ESTATE, "need labels");
+  if (!p || p->iters < 1 || p->tau < 1 || !(p->rho0 > 0) || !(p->eps >= 0) ||
+      (p->rule != 1 && p->rule != 2) || p->xplan != 0 ||
+      (p->init != D2_INIT_PRODUCT && p->init != D2_INIT_CACHED))
+    return c->fail(D2_EINVAL, "bad B-ADMM parameters");
+  HIPCHK(c, hipSetDevice(c->device));
+  d2_status s = ensure_plans(c);
+  if (s) return s;
+  if ((s = build_lists(c, p->init == D2_INIT_CACHED))) return s;
+  return c->dt == D2_F64 ? run_barycenter<double>(c, p, st)
+                         : run_barycenter<float>(c, p, st);
+}
+
+d2_status d2_support_update(d2_ctx* c) {
+  if (!c) return D2_EINVAL;
+  if (!c->have_cache || !c->have_labels || c->h_cache_labels != c->h_labels)
+    return c->fail(D2_ESTATE, "need a barycenter on the current labels");
+  HIPCHK(c, hipSetDevice(c->device));
+  d2_status s;
+  if (!c->lists_valid && (s = build_lists(c, false))) return s;
+  int nl = 0;
+  if (c->dt == D2_F64) {
+    auto a = make_args<double>(c, nullptr);
+    s = launch_aux<double>(c, a, d2k::kXO, nl);
+  } else {
+    auto a = make_args<float>(c, nullptr);
+    s = launch_aux<float>(c, a, d2k::kXO, nl);
+  }
+  if (s) return s;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return D2_OK;
+}
+
+d2_status d2_cluster(d2_ctx* c, int32_t rounds, const d2_badmm_params* bp,
+                     const d2_ot_params* op, d2_round_cb cb, void* user) {
+  if (!c) return D2_EINVAL;
+  if (rounds < 0 || !bp || !op) return c->fail(D2_EINVAL, "bad arguments");
+  for (int r = 0; r < rounds; ++r) {
+    d2_round_info info;
+    std::memset(&info, 0, sizeof(info));
+    info.round = r;
+    int64_t changed = 0;
+    float msa = 0.f;
+    if (!c->N || !c->K) return c->fail(D2_ESTATE, "need instances, centroids");
+    HIPCHK(c, hipSetDevice(c->device));
+    std::vector<double> best(c->N);
+    d2_status s = d2_assign(c, op, nullptr, best.data(), &changed);
+    if (s) return s;
+    (void)msa;
+    double sum = 0.0;
+    for (double v : best) sum += v;
+    info.n_changed = changed;
+    info.assign_obj = sum / (double)c->N;
+    d2_badmm_params q = *bp;
+    q.init = (r == 0 && !c->have_cache) ? D2_INIT_PRODUCT : bp->init;
+    d2_badmm_stats st;
+    if ((s = d2_barycenter(c, &q, &st))) return s;
+    info.ms_barycenter = st.ms;
+    if (cb) cb(&info, user);
+  }
+  return D2_OK;
+}
+
+d2_status d2_objective(d2_ctx* c, double* trace, int32_t max_iters,
+                       double* rho) {
+  if (!c) return D2_EINVAL;
+  if (!c->trace_rows) return c->fail(D2_ESTATE, "no barycenter yet");
+  HIPCHK(c, hipSetDevice(c->device));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  int rows = std::min(max_iters, c->trace_rows);
+  if (trace && rows > 0)
+    HIPCHK(c, hipMemcpy(trace, c->d_trace, sizeof(double) * rows * c->K,
+                        hipMemcpyDeviceToHost));
+  if (rho)
+    HIPCHK(c, hipMemcpy(rho, c->d_rho, sizeof(double) * c->K,
+                        hipMemcpyDeviceToHost));
+  return D2_OK;
+}
+
+d2_status d2_plans_get(d2_ctx* c, int64_t k, double* P1, double* P2,
+                       double* L) {
+  if (!c) return D2_EINVAL;
+  if (!c->d_P1 || !c->have_cache) return c->fail(D2_ESTATE, "no plans yet");
+  if (k < 0 || k >= c->N) return c->fail(D2_EINVAL, "instance out of range");
+  HIPCHK(c, hipSetDevice(c->device));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  size_t cnt = (size_t)c->m * (c->h_off[k + 1] - c->h_off[k]);
+  size_t ofs = (size_t)c->m * c->h_off[k];
+  void* src[3] = {c->d_P1, c->d_P2, c->d_L};
+  double* dst[3] = {P1, P2, L};
+  for (int q = 0; q < 3; ++q) {
+    if (!dst[q]) continue;
+    d2_status s =
+        c->dt == D2_F64
+            ? download_conv<double>(c, dst[q], (const double*)src[q] + ofs, cnt)
+            : download_conv<float>(c, dst[q], (const float*)src[q] + ofs, cnt);
+    if (s) return s;
+  }
+  return D2_OK;
+}
+
+d2_status d2_sizes(const d2_ctx* c, int64_t* N, int64_t* n, int32_t* d,
+                   int32_t* K, int32_t* m) {
+  if (!c) return D2_EINVAL;
+  if (N) *N = c->N;
+  if (n) *n = c->n;
+  if (d) *d = c->d;
+  if (K) *K = c->K;
+  if (m) *m = c->m;
+  return D2_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,258 @@
+"""Python binding of libd2.so (include/d2.h): argument marshalling only.
+
+Every step of the B-ADMM barycenter / D2-clustering path runs in the HIP
+library; this module converts numpy arrays to C pointers and C status codes
+to exceptions.  There is no CPU fallback: if the library cannot be loaded or
+no GPU is present the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libd2.so")
+
+D2_OK, D2_EINVAL, D2_ENOMEM, D2_EDEVICE, D2_ENUMERIC, D2_ESTATE = range(6)
+D2_F32, D2_F64 = 0, 1
+D2_INIT_PRODUCT, D2_INIT_CACHED = 0, 1
+STATUS_NAMES = {0: "D2_OK", 1: "D2_EINVAL", 2: "D2_ENOMEM", 3: "D2_EDEVICE",
+                4: "D2_ENUMERIC", 5: "D2_ESTATE"}
+
+# every symbol include/d2.h declares
+EXPORTS = [
+    "d2_create", "d2_destroy", "d2_last_error", "d2_load_instances",
+    "d2_centroids_set", "d2_centroids_get", "d2_centroids_init",
+    "d2_labels_set", "d2_labels_get", "d2_assign", "d2_barycenter",
+    "d2_support_update", "d2_cluster", "d2_objective", "d2_plans_get",
+    "d2_sizes",
+]
+
+
+class D2Error(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class BadmmParams(ctypes.Structure):
+    _fields_ = [("rho0", ctypes.c_double), ("eps", ctypes.c_double),
+                ("tau", ctypes.c_int32), ("iters", ctypes.c_int32),
+                ("rule", ctypes.c_int32), ("xplan", ctypes.c_int32),
+                ("init", ctypes.c_int32), ("fixed_support", ctypes.c_int32)]
+
+
+class OtParams(ctypes.Structure):
+    _fields_ = [("rho0", ctypes.c_double), ("eps", ctypes.c_double),
+                ("iters", ctypes.c_int32)]
+
+
+class BadmmStats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("n_empty", ctypes.c_int32),
+                ("launches", ctypes.c_int32), ("graph", ctypes.c_int32),
+                ("ms", ctypes.c_double)]
+
+
+class RoundInfo(ctypes.Structure):
+    _fields_ = [("round", ctypes.c_int32), ("n_changed", ctypes.c_int64),
+                ("assign_obj", ctypes.c_double), ("ms_assign", ctypes.c_double),
+                ("ms_barycenter", ctypes.c_double)]
+
+
+ROUND_CB = ctypes.CFUNCTYPE(None, ctypes.POINTER(RoundInfo), ctypes.c_void_p)
+
+_lib = None
+_p = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libd2.so and declare the C signatures (raises if absent)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise OSError(f"{path} is missing: build it with "
+                      "`python -m paper_1510_00012_amd.build`")
+    lib = ctypes.CDLL(path)
+    sig = {
+        "d2_create": ([ctypes.POINTER(_p), ctypes.c_int, ctypes.c_int, _p],
+                      ctypes.c_int),
+        "d2_destroy": ([_p], None),
+        "d2_last_error": ([_p], ctypes.c_char_p),
+        "d2_load_instances": ([_p, _i64, _i32, _p, _p, _p], ctypes.c_int),
+        "d2_centroids_set": ([_p, _i32, _i32, _p, _p], ctypes.c_int),
+        "d2_centroids_get": ([_p, _p, _p], ctypes.c_int),
+        "d2_centroids_init": ([_p, _i32, _i32, _p], ctypes.c_int),
+        "d2_labels_set": ([_p, _p], ctypes.c_int),
+        "d2_labels_get": ([_p, _p], ctypes.c_int),
+        "d2_assign": ([_p, ctypes.POINTER(OtParams), _p, _p, _p],
+                      ctypes.c_int),
+        "d2_barycenter": ([_p, ctypes.POINTER(BadmmParams),
+                           ctypes.POINTER(BadmmStats)], ctypes.c_int),
+        "d2_support_update": ([_p], ctypes.c_int),
+        "d2_cluster": ([_p, _i32, ctypes.POINTER(BadmmParams),
+                        ctypes.POINTER(OtParams), ROUND_CB, _p], ctypes.c_int),
+        "d2_objective": ([_p, _p, _i32, _p], ctypes.c_int),
+        "d2_plans_get": ([_p, _i64, _p, _p, _p], ctypes.c_int),
+        "d2_sizes": ([_p, _p, _p, _p, _p, _p], ctypes.c_int),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _c(a, dt):
+    return np.ascontiguousarray(a, dtype=dt)
+
+
+def badmm_params(iters=100, tau=10, rho0=2.0, eps=1e-16, rule=1,
+                 init=D2_INIT_CACHED, fixed_support=False):
+    return BadmmParams(rho0=rho0, eps=eps, tau=tau, iters=iters, rule=rule,
+                       xplan=0, init=init, fixed_support=int(fixed_support))
+
+
+def ot_params(iters=100, rho0=2.0, eps=1e-16):
+    return OtParams(rho0=rho0, eps=eps, iters=iters)
+
+
+class D2Context:
+    """One library context (device buffers, stream, cached plans)."""
+
+    def __init__(self, device=0, dtype="f32", stream=None):
+        self.lib = load_library()
+        self.dtype = dtype
+        h = _p()
+        dt = D2_F64 if dtype in ("f64", "float64", np.float64) else D2_F32
+        st = self.lib.d2_create(ctypes.byref(h), int(device), dt,
+                                None if stream is None else _p(int(stream)))
+        if st != D2_OK:
+            raise D2Error(st, "d2_create failed (no usable HIP device?)")
+        self.h = h
+        self.N = self.n = self.d = self.K = self.m = 0
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.d2_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _chk(self, st):
+        if st != D2_OK:
+            msg = self.lib.d2_last_error(self.h)
+            raise D2Error(st, msg.decode() if msg else "")
+
+    # ------------------------------------------------------------ data
+    def load_instances(self, offsets, X, W):
+        off = _c(offsets, np.int64)
+        X = _c(X, np.float64)
+        W = _c(W, np.float64)
+        N = len(off) - 1
+        d = X.shape[1] if X.ndim == 2 else 1
+        self._chk(self.lib.d2_load_instances(self.h, N, d, _ptr(off), _ptr(X),
+                                             _ptr(W)))
+        self.offsets, self.N, self.n, self.d = off, N, int(off[-1]), d
+
+    def centroids_set(self, Xc, Wc):
+        Xc = _c(Xc, np.float64)
+        Wc = _c(Wc, np.float64)
+        K, m = Wc.shape
+        self._chk(self.lib.d2_centroids_set(self.h, K, m, _ptr(Xc), _ptr(Wc)))
+        self.K, self.m = K, m
+
+    def centroids_init(self, members, m):
+        mem = _c(members, np.int64)
+        self._chk(self.lib.d2_centroids_init(self.h, len(mem), int(m),
+                                             _ptr(mem)))
+        self.K, self.m = len(mem), int(m)
+
+    def centroids_get(self):
+        Xc = np.empty((self.K, self.m, self.d))
+        Wc = np.empty((self.K, self.m))
+        self._chk(self.lib.d2_centroids_get(self.h, _ptr(Xc), _ptr(Wc)))
+        return Xc, Wc
+
+    def labels_set(self, labels):
+        lab = _c(labels, np.int32)
+        self._chk(self.lib.d2_labels_set(self.h, _ptr(lab)))
+
+    def labels_get(self):
+        lab = np.empty(self.N, dtype=np.int32)
+        self._chk(self.lib.d2_labels_get(self.h, _ptr(lab)))
+        return lab
+
+    # ------------------------------------------------------------ steps
+    def assign(self, iters=100, rho0=2.0, eps=1e-16):
+        lab = np.empty(self.N, dtype=np.int32)
+        dist = np.empty(self.N)
+        nch = ctypes.c_int64(0)
+        p = ot_params(iters, rho0, eps)
+        self._chk(self.lib.d2_assign(self.h, ctypes.byref(p), _ptr(lab),
+                                     _ptr(dist), ctypes.byref(nch)))
+        return lab, dist, int(nch.value)
+
+    def barycenter(self, iters=100, tau=10, rho0=2.0, eps=1e-16, rule=1,
+                   init=D2_INIT_CACHED, fixed_support=False):
+        p = badmm_params(iters, tau, rho0, eps, rule, init, fixed_support)
+        s = BadmmStats()
+        self._chk(self.lib.d2_barycenter(self.h, ctypes.byref(p),
+                                         ctypes.byref(s)))
+        return {"iters": s.iters, "n_empty": s.n_empty,
+                "launches": s.launches, "graph": s.graph, "ms": s.ms}
+
+    def support_update(self):
+        self._chk(self.lib.d2_support_update(self.h))
+
+    def cluster(self, rounds, iters=100, tau=10, rho0=2.0, eps=1e-16, rule=1,
+                assign_iters=100, callback=None):
+        bp = badmm_params(iters, tau, rho0, eps, rule, D2_INIT_CACHED)
+        op = ot_params(assign_iters, rho0, eps)
+        recs = []
+
+        def _cb(info, user):
+            r = info.contents
+            rec = {"round": r.round, "n_changed": r.n_changed,
+                   "assign_obj": r.assign_obj,
+                   "ms_barycenter": r.ms_barycenter}
+            recs.append(rec)
+            if callback:
+                callback(rec)
+
+        cb = ROUND_CB(_cb)
+        self._chk(self.lib.d2_cluster(self.h, int(rounds), ctypes.byref(bp),
+                                      ctypes.byref(op), cb, None))
+        return recs
+
+    def objective(self, iters):
+        tr = np.zeros((iters, self.K))
+        rho = np.zeros(self.K)
+        self._chk(self.lib.d2_objective(self.h, _ptr(tr), int(iters),
+                                        _ptr(rho)))
+        return tr, rho
+
+    def plans_get(self, k):
+        mk = int(self.offsets[k + 1] - self.offsets[k])
+        bufs = [np.empty(self.m * mk) for _ in range(3)]
+        self._chk(self.lib.d2_plans_get(self.h, int(k), *[_ptr(b) for b in bufs]))
+        return tuple(b.reshape(mk, self.m).T.copy() for b in bufs)
