@@ -175,6 +175,23 @@ d2_status d2_objective(d2_ctx* ctx, double* trace, int32_t max_iters,
 d2_status d2_plans_get(d2_ctx* ctx, int64_t k, double* P1, double* P2,
                        double* L);
 
+/* Per-kernel timing.  With profiling on, every kernel launch of the
+ * context is bracketed by two HIP events recorded on the context's stream,
+ * and the elapsed times are accumulated per kernel kind when the call that
+ * launched them synchronises.  Kinds: "rho_cost", "init_a", "iter_ba",
+ * "b_xnum", "a_from_p2", "b_final", "xnum_only", "assign". */
+typedef struct {
+  char name[24];
+  int64_t launches;
+  double total_ms;
+} d2_kernel_stat;
+
+d2_status d2_set_profiling(d2_ctx* ctx, int32_t on);
+/* Copy up to `cap` accumulated records (kinds with at least one launch) and
+ * their number; `reset` != 0 clears the accumulators afterwards. */
+d2_status d2_kernel_stats(d2_ctx* ctx, d2_kernel_stat* out, int32_t cap,
+                          int32_t* count, int32_t reset);
+
 /* Sizes: N, n, d, K, m of the context (any pointer may be NULL). */
 d2_status d2_sizes(const d2_ctx* ctx, int64_t* N, int64_t* n, int32_t* d,
                    int32_t* K, int32_t* m);

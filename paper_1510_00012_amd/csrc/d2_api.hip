@@ -21,37 +21,51 @@ int ilog2(int v) {
 }
 int pad_rows(int m) { return 1 << std::max(3, ilog2(m)); }
 
-// ---------------------------------------------------------------------------
-// kernel tables indexed by [log2(MP) - 3][log2(R)]
-// ---------------------------------------------------------------------------
-template <typename T> struct Kern {
-  using BA = void (*)(d2k::Args<T>);
-  using AX = void (*)(d2k::Args<T>, int);
-  using AS = void (*)(d2k::AssignArgs<T>);
-  BA ba[4][6] = {};
-  AX aux[4][6] = {};
-  AS asg[4][6] = {};
-  template <int MP, int R> void add() {
-    ba[ilog2(MP) - 3][ilog2(R)] = &d2k::k_iter_ba<T, MP, R>;
-    aux[ilog2(MP) - 3][ilog2(R)] = &d2k::k_aux<T, MP, R>;
-    asg[ilog2(MP) - 3][ilog2(R)] = &d2k::k_assign<T, MP, R>;
-  }
-  Kern() {
-    add<8, 1>(); add<8, 2>(); add<8, 4>(); add<8, 8>();
-    add<16, 1>(); add<16, 2>(); add<16, 4>(); add<16, 8>(); add<16, 16>();
-    add<32, 1>(); add<32, 2>(); add<32, 4>(); add<32, 8>(); add<32, 16>();
-    add<32, 32>();
-    add<64, 1>(); add<64, 2>(); add<64, 4>(); add<64, 8>(); add<64, 16>();
-    add<64, 32>();
-  }
-};
+}  // namespace
 
-template <typename T> const Kern<T>& kern() {
-  static Kern<T> k;
-  return k;
+// kernel tables, filled by the per-type translation units
+void d2k_fill_f32(d2k::KernTable<float>* t);
+void d2k_fill_f64(d2k::KernTable<double>* t);
+void d2k_fill_fin(d2k::FinFn* f);
+
+namespace {
+
+template <typename T> const d2k::KernTable<T>& kern();
+template <> const d2k::KernTable<float>& kern<float>() {
+  static const d2k::KernTable<float> t = [] {
+    d2k::KernTable<float> x;
+    d2k_fill_f32(&x);
+    return x;
+  }();
+  return t;
+}
+template <> const d2k::KernTable<double>& kern<double>() {
+  static const d2k::KernTable<double> t = [] {
+    d2k::KernTable<double> x;
+    d2k_fill_f64(&x);
+    return x;
+  }();
+  return t;
+}
+const d2k::FinFn* fin_table() {
+  static d2k::FinFn f[4] = {};
+  static bool init = false;
+  if (!init) {
+    d2k_fill_fin(f);
+    init = true;
+  }
+  return f;
 }
 
 }  // namespace
+
+enum KernelKind {
+  kKRho = 0, kKInitA, kKIterBA, kKBX, kKAP, kKBF, kKXO, kKAssign, kKFin,
+  kKinds
+};
+static const char* kKindNames[kKinds] = {"rho_cost", "init_a", "iter_ba",
+                                         "b_xnum", "a_from_p2", "b_final",
+                                         "xnum_only", "assign", "finalize"};
 
 struct d2_ctx {
   int device = 0;
@@ -61,7 +75,7 @@ struct d2_ctx {
   std::string err;
   // instances
   int64_t N = 0, n = 0;
-  int d = 0, mk_max = 0;
+  int d = 0, xs = 0, mk_max = 0;  // xs: device row stride of X (4 if d<=4)
   std::vector<int64_t> h_off;
   int64_t* d_off = nullptr;
   void* d_X = nullptr;
@@ -102,6 +116,16 @@ struct d2_ctx {
   double* d_trace = nullptr;
   int trace_cap = 0, trace_rows = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  // per-kernel profiling
+  bool prof = false;
+  struct Pending {
+    int kind;
+    hipEvent_t a, b;
+  };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> ev_pool;
+  int64_t prof_launches[kKinds] = {};
+  double prof_ms[kKinds] = {};
 
   d2_status fail(d2_status s, const std::string& msg) {
     err = msg;
@@ -388,6 +412,58 @@ d2_status ensure_plans(d2_ctx* c) {
   return D2_OK;
 }
 
+hipEvent_t take_event(d2_ctx* c) {
+  if (!c->ev_pool.empty()) {
+    hipEvent_t e = c->ev_pool.back();
+    c->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Bracket a launch with events when profiling (start before, stop after).
+hipEvent_t prof_begin(d2_ctx* c) {
+  if (!c->prof) return nullptr;
+  hipEvent_t a = take_event(c);
+  if (a) (void)hipEventRecord(a, c->stream);
+  return a;
+}
+
+void prof_end(d2_ctx* c, int kind, hipEvent_t a) {
+  if (!c->prof || !a) return;
+  hipEvent_t b = take_event(c);
+  if (!b) return;
+  (void)hipEventRecord(b, c->stream);
+  c->pending.push_back({kind, a, b});
+}
+
+// Called after the stream has been synchronised.
+void prof_collect(d2_ctx* c) {
+  for (auto& p : c->pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      c->prof_launches[p.kind] += 1;
+      c->prof_ms[p.kind] += ms;
+    }
+    c->ev_pool.push_back(p.a);
+    c->ev_pool.push_back(p.b);
+  }
+  c->pending.clear();
+}
+
+int aux_kind(int mode) {
+  switch (mode) {
+    case d2k::kRho: return kKRho;
+    case d2k::kA0: return kKInitA;
+    case d2k::kAP: return kKAP;
+    case d2k::kBX: return kKBX;
+    case d2k::kBF: return kKBF;
+    default: return kKXO;
+  }
+}
+
 template <typename T>
 d2k::Args<T> make_args(d2_ctx* c, const d2_badmm_params* p) {
   d2k::Args<T> a;
@@ -396,9 +472,6 @@ d2k::Args<T> make_args(d2_ctx* c, const d2_badmm_params* p) {
   a.W = (const T*)c->d_W;
   a.work = c->d_work;
   a.chunks = c->d_chunks;
-  a.ctab = c->d_ctab;
-  a.ninv = c->d_ninv;
-  a.cinv = c->d_cinv;
   a.P1 = (T*)c->d_P1;
   a.P2 = (T*)c->d_P2;
   a.L = (T*)c->d_L;
@@ -406,21 +479,48 @@ d2k::Args<T> make_args(d2_ctx* c, const d2_badmm_params* p) {
   a.warm = c->d_warm;
   a.xc = c->d_xc;
   a.w_in = c->d_wbuf;
-  a.w_out = c->d_wbuf;
   a.rho = c->d_rho;
   a.part = c->d_part;
   a.partx = c->d_partx;
-  a.cnt = c->d_cnt;
-  a.trace = nullptr;
-  a.rho0 = p ? p->rho0 : 2.0;
   a.eps = p ? p->eps : 1e-16;
   a.m = c->m;
   a.d = c->d;
+  a.xs = c->xs;
   a.rule = p ? p->rule : 1;
   a.ps = c->MP + 2;
-  a.onfly = c->onfly ? 1 : 0;
   a.nchunks = c->nchunks;
   return a;
+}
+
+d2k::FinArgs make_fin(d2_ctx* c, const d2_badmm_params* p) {
+  d2k::FinArgs f;
+  f.ctab = c->d_ctab;
+  f.ninv = c->d_ninv;
+  f.cinv = c->d_cinv;
+  f.part = c->d_part;
+  f.partx = c->d_partx;
+  f.w_out = c->d_wbuf;
+  f.rho = c->d_rho;
+  f.xc = c->d_xc;
+  f.trace = nullptr;
+  f.rho0 = p ? p->rho0 : 2.0;
+  f.m = c->m;
+  f.d = c->d;
+  f.rule = p ? p->rule : 1;
+  f.ps = c->MP + 2;
+  return f;
+}
+
+d2_status launch_fin(d2_ctx* c, const d2k::FinArgs& f, int mode, int& nl) {
+  d2k::FinFn fn = fin_table()[ilog2(c->MP) - 3];
+  size_t shm =
+      mode == d2k::kFinX ? sizeof(double) * c->MP * (c->d + 1) : 0;
+  hipEvent_t pe = prof_begin(c);
+  hipLaunchKernelGGL(fn, dim3(c->K), dim3(256), shm, c->stream, f, mode);
+  HIPCHK(c, hipGetLastError());
+  prof_end(c, kKFin, pe);
+  ++nl;
+  return D2_OK;
 }
 
 template <typename T>
@@ -434,9 +534,11 @@ d2_status launch_aux(d2_ctx* c, const d2k::Args<T>& a, int mode, int& nl) {
   if (xnum)
     while (waves > 1 && per_wave * waves > 64 * 1024) --waves;
   size_t shm = xnum ? per_wave * waves : 0;
+  hipEvent_t pe = prof_begin(c);
   hipLaunchKernelGGL(fn, dim3(c->nchunks), dim3(64 * waves), shm, c->stream,
                      a, mode);
   HIPCHK(c, hipGetLastError());
+  prof_end(c, aux_kind(mode), pe);
   ++nl;
   return D2_OK;
 }
@@ -444,11 +546,13 @@ d2_status launch_aux(d2_ctx* c, const d2k::Args<T>& a, int mode, int& nl) {
 template <typename T>
 d2_status launch_ba(d2_ctx* c, const d2k::Args<T>& a, int& nl) {
   const auto& kt = kern<T>();
-  auto fn = kt.ba[ilog2(c->MP) - 3][ilog2(c->R)];
+  auto fn = kt.ba[c->onfly ? 1 : 0][ilog2(c->MP) - 3][ilog2(c->R)];
   if (!fn) return c->fail(D2_EINVAL, "no kernel for this tile shape");
+  hipEvent_t pe = prof_begin(c);
   hipLaunchKernelGGL(fn, dim3(c->nchunks), dim3(64 * c->waves), 0, c->stream,
                      a);
   HIPCHK(c, hipGetLastError());
+  prof_end(c, kKIterBA, pe);
   ++nl;
   return D2_OK;
 }
@@ -475,33 +579,43 @@ d2_status run_barycenter(d2_ctx* c, const d2_badmm_params* p,
   HIPCHK(c, hipEventRecord(c->ev0, c->stream));
   int nl = 0;
   d2k::Args<T> a = make_args<T>(c, p);
+  d2k::FinArgs f = make_fin(c, p);
   double* wb0 = c->d_wbuf;
   double* wb1 = c->d_wbuf + K * MP;
   auto wbuf = [&](int q) { return (q & 1) ? wb1 : wb0; };
   d2_status s;
+  // rho from the cost at the initial support
   if ((s = launch_aux<T>(c, a, d2k::kRho, nl))) return s;
+  if ((s = launch_fin(c, f, d2k::kFinRho, nl))) return s;
+  // A_0 from the initial plans -> w^1
   a.w_in = wbuf(0);
-  a.w_out = wbuf(1);
-  a.trace = c->d_trace;
+  f.w_out = wbuf(1);
+  f.trace = c->d_trace;
   if ((s = launch_aux<T>(c, a, d2k::kA0, nl))) return s;
+  if ((s = launch_fin(c, f, d2k::kFinW, nl))) return s;
   for (int n = 0; n < T_; ++n) {
-    bool xupd = !p->fixed_support && ((n + 1) % tau == 0);
+    const bool xupd = !p->fixed_support && ((n + 1) % tau == 0);
     a.w_in = wbuf(n + 1);
-    a.w_out = wbuf(n + 2);
-    a.trace = c->d_trace + (size_t)(n + 1) * K;
+    f.w_out = wbuf(n + 2);
+    f.trace = c->d_trace + (size_t)(n + 1) * K;
     if (n == T_ - 1) {
       if ((s = launch_aux<T>(c, a, xupd ? d2k::kBX : d2k::kBF, nl))) return s;
+      if (xupd && (s = launch_fin(c, f, d2k::kFinX, nl))) return s;
     } else if (xupd) {
       if ((s = launch_aux<T>(c, a, d2k::kBX, nl))) return s;
+      if ((s = launch_fin(c, f, d2k::kFinX, nl))) return s;
       if ((s = launch_aux<T>(c, a, d2k::kAP, nl))) return s;
+      if ((s = launch_fin(c, f, d2k::kFinW, nl))) return s;
     } else {
       if ((s = launch_ba<T>(c, a, nl))) return s;
+      if ((s = launch_fin(c, f, d2k::kFinW, nl))) return s;
     }
   }
   HIPCHK(c, hipEventRecord(c->ev1, c->stream));
   HIPCHK(c, hipMemcpyAsync(c->d_wc, wbuf(T_), sizeof(double) * K * MP,
                            hipMemcpyDeviceToDevice, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  prof_collect(c);
   float ms = 0.f;
   HIPCHK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
   c->trace_rows = T_;
@@ -555,16 +669,20 @@ d2_status run_assign(d2_ctx* c, const d2_ot_params* p, float* ms_out) {
   a.eps = p->eps;
   a.m = c->m;
   a.d = c->d;
+  a.xs = c->xs;
   a.K = c->K;
   a.iters = p->iters;
   const int wpb = 4;
   int64_t blocks = (c->N + wpb - 1) / wpb;
   HIPCHK(c, hipEventRecord(c->ev0, c->stream));
+  hipEvent_t pe = prof_begin(c);
   hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(64 * wpb), 0, c->stream,
                      a);
   HIPCHK(c, hipGetLastError());
+  prof_end(c, kKAssign, pe);
   HIPCHK(c, hipEventRecord(c->ev1, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  prof_collect(c);
   float ms = 0.f;
   HIPCHK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
   if (ms_out) *ms_out = ms;
@@ -624,6 +742,11 @@ void d2_destroy(d2_ctx* c) {
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   free_instances(c);
   free_centroids(c);
+  for (auto& p : c->pending) {
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  for (auto e : c->ev_pool) (void)hipEventDestroy(e);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -675,21 +798,26 @@ d2_status d2_load_instances(d2_ctx* c, int64_t N, int32_t d,
   c->N = N;
   c->n = n;
   c->d = d;
+  c->xs = d <= 4 ? 4 : d;
   c->mk_max = mkmax;
   c->h_off.assign(offsets, offsets + N + 1);
   d2_status s;
   if ((s = dalloc(c, (void**)&c->d_off, sizeof(int64_t) * (N + 1)))) return s;
-  if ((s = dalloc(c, &c->d_X, c->esz() * n * d))) return s;
+  if ((s = dalloc(c, &c->d_X, c->esz() * n * c->xs))) return s;
   if ((s = dalloc(c, &c->d_W, c->esz() * n))) return s;
   if ((s = dalloc(c, (void**)&c->d_labels, sizeof(int32_t) * N))) return s;
   if ((s = dalloc(c, (void**)&c->d_best, sizeof(double) * N))) return s;
   HIPCHK(c, hipMemcpy(c->d_off, offsets, sizeof(int64_t) * (N + 1),
                       hipMemcpyHostToDevice));
+  // supports with row stride xs (zero padding for d <= 4)
+  std::vector<double> Xp((size_t)n * c->xs, 0.0);
+  for (int64_t j = 0; j < n; ++j)
+    for (int t = 0; t < d; ++t) Xp[(size_t)j * c->xs + t] = X[j * d + t];
   if (c->dt == D2_F64) {
-    if ((s = upload_conv<double>(c, c->d_X, X, (size_t)n * d))) return s;
+    if ((s = upload_conv<double>(c, c->d_X, Xp.data(), Xp.size()))) return s;
     if ((s = upload_conv<double>(c, c->d_W, Wn.data(), n))) return s;
   } else {
-    if ((s = upload_conv<float>(c, c->d_X, X, (size_t)n * d))) return s;
+    if ((s = upload_conv<float>(c, c->d_X, Xp.data(), Xp.size()))) return s;
     if ((s = upload_conv<float>(c, c->d_W, Wn.data(), n))) return s;
   }
   c->h_labels.assign(N, 0);
@@ -768,24 +896,26 @@ d2_status d2_centroids_init(d2_ctx* c, int32_t K, int32_t m,
     if (mk < m)
       return c->fail(D2_EINVAL, "member " + std::to_string(k) +
                                     " has fewer than m support points");
-    std::vector<double> y((size_t)mk * d), wy(mk);
+    std::vector<double> yp((size_t)mk * c->xs), y((size_t)mk * d), wy(mk);
+    const size_t xo = (size_t)c->h_off[k] * c->xs;
     if (c->dt == D2_F64) {
-      if ((s = download_conv<double>(c, y.data(),
-                                     (const double*)c->d_X + c->h_off[k] * d,
-                                     (size_t)mk * d)))
+      if ((s = download_conv<double>(c, yp.data(), (const double*)c->d_X + xo,
+                                     yp.size())))
         return s;
       if ((s = download_conv<double>(c, wy.data(),
                                      (const double*)c->d_W + c->h_off[k], mk)))
         return s;
     } else {
-      if ((s = download_conv<float>(c, y.data(),
-                                    (const float*)c->d_X + c->h_off[k] * d,
-                                    (size_t)mk * d)))
+      if ((s = download_conv<float>(c, yp.data(), (const float*)c->d_X + xo,
+                                    yp.size())))
         return s;
       if ((s = download_conv<float>(c, wy.data(),
                                     (const float*)c->d_W + c->h_off[k], mk)))
         return s;
     }
+    for (int j = 0; j < mk; ++j)
+      for (int t = 0; t < d; ++t)
+        y[(size_t)j * d + t] = yp[(size_t)j * c->xs + t];
     merge_support(mk, d, y.data(), wy.data(), m, &Xc[(size_t)q * m * d],
                   &Wc[(size_t)q * m]);
   }
@@ -876,7 +1006,9 @@ d2_status d2_support_update(d2_ctx* c) {
     s = launch_aux<float>(c, a, d2k::kXO, nl);
   }
   if (s) return s;
+  if ((s = launch_fin(c, make_fin(c, nullptr), d2k::kFinX, nl))) return s;
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  prof_collect(c);
   return D2_OK;
 }
 
@@ -945,6 +1077,35 @@ d2_status d2_plans_get(d2_ctx* c, int64_t k, double* P1, double* P2,
             : download_conv<float>(c, dst[q], (const float*)src[q] + ofs, cnt);
     if (s) return s;
   }
+  return D2_OK;
+}
+
+d2_status d2_set_profiling(d2_ctx* c, int32_t on) {
+  if (!c) return D2_EINVAL;
+  c->prof = on != 0;
+  return D2_OK;
+}
+
+d2_status d2_kernel_stats(d2_ctx* c, d2_kernel_stat* out, int32_t cap,
+                          int32_t* count, int32_t reset) {
+  if (!c) return D2_EINVAL;
+  int n = 0;
+  for (int q = 0; q < kKinds; ++q) {
+    if (!c->prof_launches[q]) continue;
+    if (out && n < cap) {
+      std::memset(out[n].name, 0, sizeof(out[n].name));
+      std::strncpy(out[n].name, kKindNames[q], sizeof(out[n].name) - 1);
+      out[n].launches = c->prof_launches[q];
+      out[n].total_ms = c->prof_ms[q];
+    }
+    ++n;
+  }
+  if (count) *count = n;
+  if (reset)
+    for (int q = 0; q < kKinds; ++q) {
+      c->prof_launches[q] = 0;
+      c->prof_ms[q] = 0.0;
+    }
   return D2_OK;
 }
 

@@ -27,7 +27,7 @@ EXPORTS = [
     "d2_centroids_set", "d2_centroids_get", "d2_centroids_init",
     "d2_labels_set", "d2_labels_get", "d2_assign", "d2_barycenter",
     "d2_support_update", "d2_cluster", "d2_objective", "d2_plans_get",
-    "d2_sizes",
+    "d2_sizes", "d2_set_profiling", "d2_kernel_stats",
 ]
 
 
@@ -59,6 +59,11 @@ class RoundInfo(ctypes.Structure):
     _fields_ = [("round", ctypes.c_int32), ("n_changed", ctypes.c_int64),
                 ("assign_obj", ctypes.c_double), ("ms_assign", ctypes.c_double),
                 ("ms_barycenter", ctypes.c_double)]
+
+
+class KernelStat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 24), ("launches", ctypes.c_int64),
+                ("total_ms", ctypes.c_double)]
 
 
 ROUND_CB = ctypes.CFUNCTYPE(None, ctypes.POINTER(RoundInfo), ctypes.c_void_p)
@@ -99,6 +104,9 @@ def load_library(path: str = LIB_PATH):
         "d2_objective": ([_p, _p, _i32, _p], ctypes.c_int),
         "d2_plans_get": ([_p, _i64, _p, _p, _p], ctypes.c_int),
         "d2_sizes": ([_p, _p, _p, _p, _p, _p], ctypes.c_int),
+        "d2_set_profiling": ([_p, _i32], ctypes.c_int),
+        "d2_kernel_stats": ([_p, ctypes.POINTER(KernelStat), _i32, _p, _i32],
+                            ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -250,6 +258,19 @@ class D2Context:
         self._chk(self.lib.d2_objective(self.h, _ptr(tr), int(iters),
                                         _ptr(rho)))
         return tr, rho
+
+    def set_profiling(self, on=True):
+        self._chk(self.lib.d2_set_profiling(self.h, int(bool(on))))
+
+    def kernel_stats(self, reset=False):
+        """{kind: (launches, total_ms)} accumulated while profiling."""
+        arr = (KernelStat * 16)()
+        cnt = ctypes.c_int32(0)
+        self._chk(self.lib.d2_kernel_stats(self.h, arr, 16, ctypes.byref(cnt),
+                                           int(bool(reset))))
+        return {arr[q].name.decode(): (int(arr[q].launches),
+                                       float(arr[q].total_ms))
+                for q in range(min(cnt.value, 16))}
 
     def plans_get(self, k):
         mk = int(self.offsets[k + 1] - self.offsets[k])
