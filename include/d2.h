@@ -76,6 +76,11 @@ typedef struct {
   double rho0;
   double eps;
   int32_t iters;
+  /* 1: skip a centroid whose lower bound sum_j w^(k)_j min_i C_ij (valid for
+   * any plan with the instance's column sums, hence for Pi1) exceeds the
+   * best distance found by more than 1e-4 relative; the labels and minimal
+   * distances are those of the exhaustive search.  0: evaluate every pair. */
+  int32_t prune;
 } d2_ot_params;
 
 typedef struct {
@@ -131,6 +136,11 @@ d2_status d2_labels_get(d2_ctx* ctx, int32_t* labels);
  * n_changed may be NULL. */
 d2_status d2_assign(d2_ctx* ctx, const d2_ot_params* p, int32_t* labels_out,
                     double* dist_out, int64_t* n_changed);
+
+/* Pairs run through the transport iterations by the last d2_assign and the
+ * total number of (instance, centroid) pairs. */
+d2_status d2_assign_pairs(const d2_ctx* ctx, int64_t* evaluated,
+                          int64_t* total);
 
 /* Centroid update (Sec. 3.2, Algorithm "Centroid Update with B-ADMM") for
  * all K clusters of the current labels in one batched pass: Lambda = 0,
@@ -191,6 +201,13 @@ d2_status d2_set_profiling(d2_ctx* ctx, int32_t on);
  * their number; `reset` != 0 clears the accumulators afterwards. */
 d2_status d2_kernel_stats(d2_ctx* ctx, d2_kernel_stat* out, int32_t cap,
                           int32_t* count, int32_t reset);
+
+/* Launch schedule of the barycenter kernels: instances per workgroup chunk
+ * (1 .. 4096) and wavefronts per workgroup (1, 2 or 4).  Results do not
+ * depend on the schedule beyond floating-point summation order.  The
+ * autotuner (paper_1510_00012_amd.autotune) picks these per workload. */
+d2_status d2_set_schedule(d2_ctx* ctx, int32_t chunk_instances,
+                          int32_t waves_per_group);
 
 /* Sizes: N, n, d, K, m of the context (any pointer may be NULL). */
 d2_status d2_sizes(const d2_ctx* ctx, int64_t* N, int64_t* n, int32_t* d,

@@ -13,7 +13,7 @@ SOURCES = ["d2_api.hip", "d2_k_f32.hip", "d2_k_f64.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
-    "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",
+    "-O3", "-std=c++20", "-fPIC", "-shared", "--offload-arch=gfx950",
     # keep packed-FP32 instructions out of generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"),

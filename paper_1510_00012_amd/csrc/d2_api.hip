@@ -92,6 +92,8 @@ struct d2_ctx {
   bool have_labels = false, have_cache = false;
   int32_t* d_labels = nullptr;
   double* d_best = nullptr;
+  unsigned long long* d_evals = nullptr;
+  int64_t last_evals = 0, last_pairs = 0;
   // plans
   void* d_P1 = nullptr;
   void* d_P2 = nullptr;
@@ -198,6 +200,7 @@ void free_instances(d2_ctx* c) {
   dfree(c->d_W);
   dfree(c->d_labels);
   dfree(c->d_best);
+  dfree(c->d_evals);
   dfree(c->d_trace);
   c->trace_cap = 0;
   c->N = c->n = 0;
@@ -664,6 +667,8 @@ d2_status run_assign(d2_ctx* c, const d2_ot_params* p, float* ms_out) {
   a.wc = c->d_wc;
   a.labels = c->d_labels;
   a.best = c->d_best;
+  a.evaluated = c->d_evals;
+  a.prune = p->prune ? 1 : 0;
   a.N = c->N;
   a.rho0 = p->rho0;
   a.eps = p->eps;
@@ -674,6 +679,8 @@ d2_status run_assign(d2_ctx* c, const d2_ot_params* p, float* ms_out) {
   a.iters = p->iters;
   const int wpb = 4;
   int64_t blocks = (c->N + wpb - 1) / wpb;
+  HIPCHK(c, hipMemsetAsync(c->d_evals, 0, sizeof(unsigned long long),
+                           c->stream));
   HIPCHK(c, hipEventRecord(c->ev0, c->stream));
   hipEvent_t pe = prof_begin(c);
   hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(64 * wpb), 0, c->stream,
@@ -686,6 +693,10 @@ d2_status run_assign(d2_ctx* c, const d2_ot_params* p, float* ms_out) {
   float ms = 0.f;
   HIPCHK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
   if (ms_out) *ms_out = ms;
+  unsigned long long ev = 0;
+  HIPCHK(c, hipMemcpy(&ev, c->d_evals, sizeof(ev), hipMemcpyDeviceToHost));
+  c->last_evals = (int64_t)ev;
+  c->last_pairs = c->N * (int64_t)c->K;
   return D2_OK;
 }
 
@@ -807,6 +818,8 @@ d2_status d2_load_instances(d2_ctx* c, int64_t N, int32_t d,
   if ((s = dalloc(c, &c->d_W, c->esz() * n))) return s;
   if ((s = dalloc(c, (void**)&c->d_labels, sizeof(int32_t) * N))) return s;
   if ((s = dalloc(c, (void**)&c->d_best, sizeof(double) * N))) return s;
+  if ((s = dalloc(c, (void**)&c->d_evals, sizeof(unsigned long long))))
+    return s;
   HIPCHK(c, hipMemcpy(c->d_off, offsets, sizeof(int64_t) * (N + 1),
                       hipMemcpyHostToDevice));
   // supports with row stride xs (zero padding for d <= 4)
@@ -973,6 +986,14 @@ d2_status d2_assign(d2_ctx* c, const d2_ot_params* p, int32_t* labels_out,
   return D2_OK;
 }
 
+d2_status d2_assign_pairs(const d2_ctx* c, int64_t* evaluated,
+                          int64_t* total) {
+  if (!c) return D2_EINVAL;
+  if (evaluated) *evaluated = c->last_evals;
+  if (total) *total = c->last_pairs;
+  return D2_OK;
+}
+
 d2_status d2_barycenter(d2_ctx* c, const d2_badmm_params* p,
                         d2_badmm_stats* st) {
   if (!c) return D2_EINVAL;
@@ -1106,6 +1127,20 @@ d2_status d2_kernel_stats(d2_ctx* c, d2_kernel_stat* out, int32_t cap,
       c->prof_launches[q] = 0;
       c->prof_ms[q] = 0.0;
     }
+  return D2_OK;
+}
+
+d2_status d2_set_schedule(d2_ctx* c, int32_t chunk_instances,
+                          int32_t waves_per_group) {
+  if (!c) return D2_EINVAL;
+  if (chunk_instances < 1 || chunk_instances > 4096 ||
+      (waves_per_group != 1 && waves_per_group != 2 && waves_per_group != 4))
+    return c->fail(D2_EINVAL, "bad schedule");
+  if (chunk_instances != c->chunk_inst) {
+    c->chunk_inst = chunk_instances;
+    free_lists(c);
+  }
+  c->waves = waves_per_group;
   return D2_OK;
 }
 

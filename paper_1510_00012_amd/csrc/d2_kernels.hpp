@@ -46,32 +46,34 @@ constexpr int kWave = 64;
 // ---------------------------------------------------------------------------
 // arithmetic helpers
 // ---------------------------------------------------------------------------
-// exp(x) for FP32: 2^(x log2 e) by the hardware base-2 exponential, with a
-// first-order correction for the rounding error of the product x*log2(e)
-// (its exact residual r gives exp(x) = 2^t * 2^r ~ 2^t (1 + r ln 2)).
-__device__ __forceinline__ float dexp(float x) {
-  const float kL2E = 1.44269502162933349609375f;       // log2(e) rounded
-  const float kL2ELo = 1.925963033500011079e-08f;     // log2(e) - kL2E
-  const float kLn2 = 0.693147180559945309f;
-  float t = x * kL2E;
-  float r = fmaf(x, kL2E, -t) + x * kL2ELo;
-  float e = __builtin_amdgcn_exp2f(t);
-  return fmaf(e, r * kLn2, e);
+// Exponentials are evaluated as 2^t with t = x * log2(e): the caller folds
+// log2(e) into its 1/rho scale, so exp costs one multiply-add plus the
+// hardware base-2 exponential (FP32) or exp2 (FP64).
+constexpr double kLog2e = 1.4426950408889634074;
+__device__ __forceinline__ float dexp2(float t) {
+  return __builtin_amdgcn_exp2f(t);
 }
-__device__ __forceinline__ double dexp(double x) { return exp(x); }
+__device__ __forceinline__ double dexp2(double t) { return exp2(t); }
 __device__ __forceinline__ float drcp(float x) {
   return __builtin_amdgcn_rcpf(x);
 }
 __device__ __forceinline__ double drcp(double x) { return 1.0 / x; }
+// reciprocal of a column / row sum; an all-inactive column has sum 0 and
+// only zero numerators, so clamping keeps 0 * (1/sum) finite
+template <typename T> __device__ __forceinline__ T rcp_sum(T s) {
+  return drcp(s > T(1e-30) ? s : T(1e-30));
+}
 __device__ __forceinline__ float dsqrt(float v) { return sqrtf(v); }
 __device__ __forceinline__ double dsqrt(double v) { return sqrt(v); }
 
 // ---------------------------------------------------------------------------
 // lane exchange: DPP within 16-lane rows, ds_swizzle across 16, bpermute 32
 // ---------------------------------------------------------------------------
+// (bound_ctrl set: every exchange below reads an in-row lane of a fully
+// active wavefront, and it lets the compiler fold the move into the add)
 template <int CTRL> __device__ __forceinline__ float xdpp(float v) {
-  return __int_as_float(
-      __builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL,
+                                                    0xF, 0xF, true));
 }
 template <int CTRL> __device__ __forceinline__ double xdpp(double v) {
   long long b = __double_as_longlong(v);
@@ -79,6 +81,13 @@ template <int CTRL> __device__ __forceinline__ double xdpp(double v) {
                                     false);
   int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, false);
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <int CTRL> __device__ __forceinline__ float xdpp_raw(float v) {
+  return __int_as_float(
+      __builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL> __device__ __forceinline__ double xdpp_raw(double v) {
+  return xdpp<CTRL>(v);
 }
 __device__ __forceinline__ float xswz16(float v) {
   return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x401F));
@@ -113,6 +122,35 @@ template <int MP, typename T> __device__ __forceinline__ T sum_row(T v) {
 }
 template <typename T> __device__ __forceinline__ T sum_wave(T v) {
   return sum_col<64>(v);
+}
+// sum_col of NS independent values, stage by stage so that the exchanges of
+// different slots interleave (no idle cycles between dependent DPP adds)
+template <int MP, int NS, typename T>
+__device__ __forceinline__ void sum_col_n(T (&v)[NS]) {
+  if constexpr (MP >= 2) {
+#pragma unroll
+    for (int r = 0; r < NS; ++r) v[r] += xdpp<0xB1>(v[r]);
+  }
+  if constexpr (MP >= 4) {
+#pragma unroll
+    for (int r = 0; r < NS; ++r) v[r] += xdpp<0x4E>(v[r]);
+  }
+  if constexpr (MP >= 8) {
+#pragma unroll
+    for (int r = 0; r < NS; ++r) v[r] += xdpp<0x141>(v[r]);
+  }
+  if constexpr (MP >= 16) {
+#pragma unroll
+    for (int r = 0; r < NS; ++r) v[r] += xdpp<0x140>(v[r]);
+  }
+  if constexpr (MP >= 32) {
+#pragma unroll
+    for (int r = 0; r < NS; ++r) v[r] += xswz16(v[r]);
+  }
+  if constexpr (MP >= 64) {
+#pragma unroll
+    for (int r = 0; r < NS; ++r) v[r] += x32(v[r]);
+  }
 }
 
 // support point of a column for the on-the-fly cost (d <= 4, stride 4)
@@ -171,28 +209,36 @@ struct FinArgs {
 };
 
 // ---------------------------------------------------------------------------
-// tile loads / phases
+// tiles
 // ---------------------------------------------------------------------------
-template <typename T, int MP, int R> struct Tile {
+// Per-wavefront scalars are made explicitly uniform (readfirstlane) so that
+// per-instance control flow is scalar and the instance's offsets come from
+// scalar loads.
+__device__ __forceinline__ int uni(int v) {
+  return __builtin_amdgcn_readfirstlane(v);
+}
+
+template <typename T, int MP> struct Tile {
   static constexpr int CPS = kWave / MP;
   int64_t o, base;
-  int mk, i, g, ic;
+  int mk, nsl, i, g, ic;
   bool rowok;
-  __device__ __forceinline__ void setup(const Args<T>& a, int k) {
+  __device__ __forceinline__ void setup(const int64_t* off, int m, int k) {
     const int lane = threadIdx.x & (kWave - 1);
     i = lane % MP;
     g = lane / MP;
-    rowok = i < a.m;
+    rowok = i < m;
     ic = rowok ? i : 0;
-    o = a.off[k];
-    mk = (int)(a.off[k + 1] - o);
-    base = (int64_t)a.m * o;
+    o = off[k];
+    mk = (int)(off[k + 1] - o);
+    nsl = (mk + CPS - 1) / CPS;
+    base = (int64_t)m * o;
   }
   __device__ __forceinline__ int col(int r) const { return g + CPS * r; }
   __device__ __forceinline__ bool valid(int r) const {
     return rowok && col(r) < mk;
   }
-  // in-bounds element index for every lane (inactive lanes clamp)
+  // in-bounds column for every lane (inactive lanes clamp to the last)
   __device__ __forceinline__ int colc(int r) const {
     int j = col(r);
     return j < mk ? j : mk - 1;
@@ -201,6 +247,23 @@ template <typename T, int MP, int R> struct Tile {
     return base + (int64_t)colc(r) * m + ic;
   }
 };
+
+// Calls f.template operator()<NS>() with the smallest specialised slot
+// count NS >= nsl (exact up to 8, then 12, 16, 24, 32; NS <= R).  Each
+// specialisation is straight-line code over exactly NS register slots.
+template <int R, typename F>
+__device__ __forceinline__ void with_slots(int nsl, F&& f) {
+#define D2_NS(NSV)                           \
+  if constexpr (NSV <= R) {                  \
+    if (nsl <= NSV) {                        \
+      f.template operator()<NSV>();          \
+      return;                                \
+    }                                        \
+  }
+  D2_NS(1) D2_NS(2) D2_NS(3) D2_NS(4) D2_NS(5) D2_NS(6) D2_NS(7) D2_NS(8)
+  D2_NS(12) D2_NS(16) D2_NS(24) D2_NS(32)
+#undef D2_NS
+}
 
 template <typename T>
 __device__ __forceinline__ T cost_generic(const double* xrow, const T* yrow,
@@ -228,25 +291,28 @@ __device__ __forceinline__ T cost4(const T (&xr)[4],
   return s;
 }
 
+// Scales of one cluster: rho, a2 = log2(e)/rho.  Inactive lanes carry
+// zero plan, zero weight and a zero eps (el), so every product, column and
+// row sum below is exact without per-lane selects.
+
 // Phase B: Pi1~ = Pi1 exp(Lambda/rho) + eps, row sums r_i,
 // Pi2 = Pi1~ w_i / r_i, Lambda += rho (Pi1 - Pi2).  In: p = Pi1; out: p = Pi2.
-template <typename T, int MP, int R>
-__device__ __forceinline__ void phase_b(const bool (&v)[R], T (&p)[R],
-                                        T (&l)[R], T wi, T rho, T irho,
-                                        T eps) {
-  T bv[R];
+template <typename T, int MP, int NS>
+__device__ __forceinline__ void phase_b(const T (&el)[NS], T (&p)[NS],
+                                        T (&l)[NS], T wi, T rho, T a2) {
+  T bv[NS];
   T rs = T(0);
 #pragma unroll
-  for (int r = 0; r < R; ++r) {
-    bv[r] = v[r] ? p[r] * dexp(l[r] * irho) + eps : T(0);
+  for (int r = 0; r < NS; ++r) {
+    bv[r] = fma(p[r], dexp2(l[r] * a2), el[r]);
     rs += bv[r];
   }
   rs = sum_row<MP>(rs);
-  const T coef = rs > T(0) ? wi * drcp(rs) : T(0);
+  const T coef = wi * rcp_sum(rs);
 #pragma unroll
-  for (int r = 0; r < R; ++r) {
+  for (int r = 0; r < NS; ++r) {
     T p2 = bv[r] * coef;
-    l[r] = l[r] + rho * (p[r] - p2);
+    l[r] = fma(rho, p[r] - p2, l[r]);
     p[r] = p2;
   }
 }
@@ -254,20 +320,23 @@ __device__ __forceinline__ void phase_b(const bool (&v)[R], T (&p)[R],
 // Phase A: in p = Pi2, l = Lambda, cost cs, instance weights wk; out
 // p = Pi1 (column KL projection).  Returns the row sum r_i of Pi1~ in rr and
 // adds <C, Pi1> to f.
-template <typename T, int MP, int R>
-__device__ __forceinline__ void phase_a(const bool (&v)[R], T (&p)[R],
-                                        const T (&l)[R], const T (&cs)[R],
-                                        const T (&wk)[R], T irho, T eps, T& rr,
-                                        T& f) {
+template <typename T, int MP, int NS>
+__device__ __forceinline__ void phase_a(const T (&el)[NS], T (&p)[NS],
+                                        const T (&l)[NS], const T (&cs)[NS],
+                                        const T (&wk)[NS], T a2, T& rr, T& f) {
+  T av[NS], s[NS];
+#pragma unroll
+  for (int r = 0; r < NS; ++r) {
+    av[r] = fma(p[r], dexp2(-(cs[r] + l[r]) * a2), el[r]);
+    s[r] = av[r];
+  }
+  sum_col_n<MP, NS>(s);
   rr = T(0);
 #pragma unroll
-  for (int r = 0; r < R; ++r) {
-    T av = v[r] ? p[r] * dexp(-(cs[r] + l[r]) * irho) + eps : T(0);
-    T s = sum_col<MP>(av);
-    T p1 = (v[r] && s > T(0)) ? av * (wk[r] * drcp(s)) : T(0);
+  for (int r = 0; r < NS; ++r) {
+    T p1 = av[r] * (wk[r] * rcp_sum(s[r]));
     f = fma(cs[r], p1, f);
-    T b = v[r] ? p1 * dexp(l[r] * irho) + eps : T(0);
-    rr += b;
+    rr += fma(p1, dexp2(l[r] * a2), el[r]);
     p[r] = p1;
   }
   rr = sum_row<MP>(rr);
@@ -277,7 +346,7 @@ __device__ __forceinline__ void phase_a(const bool (&v)[R], T (&p)[R],
 template <typename T, int MP>
 __device__ __forceinline__ double consensus_term(T rr, bool rowok, int rule) {
   T tot = sum_col<MP>(rowok ? rr : T(0));
-  T wt = tot > T(0) ? rr / tot : T(0);
+  T wt = rowok ? rr * rcp_sum(tot) : T(0);
   return (double)(rule == 2 ? dsqrt(wt) : wt);
 }
 
@@ -302,19 +371,62 @@ __device__ __forceinline__ void write_w_record(double accw, double accf,
 // ---------------------------------------------------------------------------
 // Hot kernel: one launch per B-ADMM iteration (phase B of n, phase A of n+1)
 // ---------------------------------------------------------------------------
+template <typename T, int MP, int NS, bool ONFLY>
+__device__ __forceinline__ void ba_tile(const Args<T>& a, const Tile<T, MP>& tl,
+                                        const T (&xr)[4], T wi, T rho, T a2,
+                                        T eps, double& accw, double& accf) {
+  using V4 = typename Vec4<T>::type;
+  T p[NS], l[NS], cs[NS], wk[NS];
+  bool v[NS];
+#pragma unroll
+  for (int r = 0; r < NS; ++r) {
+    const int64_t e = tl.eidx(r, a.m);
+    const int jc = tl.colc(r);
+    v[r] = tl.valid(r);
+    p[r] = a.P1[e];
+    l[r] = a.L[e];
+    wk[r] = a.W[tl.o + jc];
+    if constexpr (ONFLY) {
+      const V4 y = reinterpret_cast<const V4*>(a.X)[tl.o + jc];
+      cs[r] = cost4<T>(xr, y);
+    } else {
+      cs[r] = a.Cc[e];
+    }
+  }
+  T el[NS];
+#pragma unroll
+  for (int r = 0; r < NS; ++r) {
+    p[r] = v[r] ? p[r] : T(0);
+    l[r] = v[r] ? l[r] : T(0);
+    wk[r] = v[r] ? wk[r] : T(0);
+    el[r] = v[r] ? eps : T(0);
+  }
+  phase_b<T, MP, NS>(el, p, l, wi, rho, a2);
+  T rr, f = T(0);
+  phase_a<T, MP, NS>(el, p, l, cs, wk, a2, rr, f);
+  accw += consensus_term<T, MP>(rr, tl.rowok, a.rule);
+  accf += (double)f;
+#pragma unroll
+  for (int r = 0; r < NS; ++r)
+    if (v[r]) {
+      const int64_t e = tl.eidx(r, a.m);
+      a.P1[e] = p[r];
+      a.L[e] = l[r];
+    }
+}
+
 template <typename T, int MP, int R, bool ONFLY>
 __global__ void __launch_bounds__(256) k_iter_ba(Args<T> a) {
-  using V4 = typename Vec4<T>::type;
   const int ch = blockIdx.x;
   if (ch >= a.nchunks) return;
   const Chunk cj = a.chunks[ch];
   const int c = cj.cluster;
-  const int wave = threadIdx.x / kWave, nwaves = blockDim.x / kWave;
+  const int wave = uni(threadIdx.x / kWave), nwaves = blockDim.x / kWave;
   const int lane = threadIdx.x & (kWave - 1);
   const int i = lane % MP;
   const bool rowok = i < a.m;
   const T rho = (T)a.rho[c];
-  const T irho = T(1) / rho;
+  const T a2 = (T)(kLog2e / a.rho[c]);
   const T eps = (T)a.eps;
   const T wi = rowok ? (T)a.w_in[c * MP + i] : T(0);
   T xr[4] = {T(0), T(0), T(0), T(0)};
@@ -325,42 +437,11 @@ __global__ void __launch_bounds__(256) k_iter_ba(Args<T> a) {
   }
   double accw = 0.0, accf = 0.0;
   for (int pos = cj.begin + wave; pos < cj.end; pos += nwaves) {
-    Tile<T, MP, R> tl;
-    tl.setup(a, a.work[pos]);
-    T p[R], l[R], cs[R], wk[R];
-    bool v[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int64_t e = tl.eidx(r, a.m);
-      const int jc = tl.colc(r);
-      v[r] = tl.valid(r);
-      p[r] = a.P1[e];
-      l[r] = a.L[e];
-      wk[r] = a.W[tl.o + jc];
-      if constexpr (ONFLY) {
-        const V4 y = reinterpret_cast<const V4*>(a.X)[tl.o + jc];
-        cs[r] = cost4<T>(xr, y);
-      } else {
-        cs[r] = a.Cc[e];
-      }
-    }
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      p[r] = v[r] ? p[r] : T(0);
-      l[r] = v[r] ? l[r] : T(0);
-    }
-    phase_b<T, MP, R>(v, p, l, wi, rho, irho, eps);
-    T rr, f = T(0);
-    phase_a<T, MP, R>(v, p, l, cs, wk, irho, eps, rr, f);
-    accw += consensus_term<T, MP>(rr, rowok, a.rule);
-    accf += (double)f;
-#pragma unroll
-    for (int r = 0; r < R; ++r)
-      if (v[r]) {
-        const int64_t e = tl.eidx(r, a.m);
-        a.P1[e] = p[r];
-        a.L[e] = l[r];
-      }
+    Tile<T, MP> tl;
+    tl.setup(a.off, a.m, uni(a.work[pos]));
+    with_slots<R>(tl.nsl, [&]<int NS>() {
+      ba_tile<T, MP, NS, ONFLY>(a, tl, xr, wi, rho, a2, eps, accw, accf);
+    });
   }
   write_w_record<MP>(accw, accf, a.part, a.ps, ch);
 }
@@ -368,6 +449,106 @@ __global__ void __launch_bounds__(256) k_iter_ba(Args<T> a) {
 // ---------------------------------------------------------------------------
 // Auxiliary kernel: cost sums / init phase A / phase-B variants / numerators
 // ---------------------------------------------------------------------------
+template <typename T, int MP, int NS>
+__device__ __forceinline__ void aux_tile(const Args<T>& a, const Tile<T, MP>& tl,
+                                         int k, int mode, const double* xrow,
+                                         T wi, T rho, T a2, T eps,
+                                         double& accw, double& accf,
+                                         double* accx) {
+  const int d = a.d;
+  const int lane = threadIdx.x & (kWave - 1);
+  T p[NS], l[NS], cs[NS], wk[NS], el[NS];
+  bool v[NS];
+#pragma unroll
+  for (int r = 0; r < NS; ++r) {
+    v[r] = tl.valid(r);
+    p[r] = l[r] = cs[r] = wk[r] = T(0);
+    el[r] = v[r] ? eps : T(0);
+  }
+  if (mode == kRho) {
+    T s = T(0);
+#pragma unroll
+    for (int r = 0; r < NS; ++r) {
+      T cv = cost_generic<T>(xrow, a.X + (tl.o + tl.colc(r)) * a.xs, d);
+      if (v[r]) {
+        if (a.Cc) a.Cc[tl.eidx(r, a.m)] = cv;
+        s += cv;
+      }
+    }
+    accf += (double)s;  // lane partial, reduced over the wave at the end
+    return;
+  }
+  if (mode == kA0 || mode == kAP) {
+    const bool cached = (mode == kAP) || (a.warm && a.warm[k]);
+#pragma unroll
+    for (int r = 0; r < NS; ++r) {
+      const int64_t e = tl.eidx(r, a.m);
+      const int jc = tl.colc(r);
+      wk[r] = a.W[tl.o + jc];
+      T cv = cost_generic<T>(xrow, a.X + (tl.o + jc) * a.xs, d);
+      if (mode == kAP && a.Cc && v[r]) a.Cc[e] = cv;
+      cs[r] = (mode == kA0 && a.Cc) ? a.Cc[e] : cv;
+      if (mode == kAP) {
+        p[r] = a.P2[e];
+        l[r] = a.L[e];
+      } else {
+        p[r] = cached ? a.P2[e] : wi * wk[r];
+      }
+      p[r] = v[r] ? p[r] : T(0);
+      l[r] = v[r] ? l[r] : T(0);
+      wk[r] = v[r] ? wk[r] : T(0);
+    }
+    T rr, f = T(0);
+    phase_a<T, MP, NS>(el, p, l, cs, wk, a2, rr, f);
+    accw += consensus_term<T, MP>(rr, tl.rowok, a.rule);
+    accf += (double)f;
+#pragma unroll
+    for (int r = 0; r < NS; ++r)
+      if (v[r]) {
+        const int64_t e = tl.eidx(r, a.m);
+        a.P1[e] = p[r];
+        a.L[e] = l[r];
+      }
+    return;
+  }
+  // phase-B modes and the support-only mode
+#pragma unroll
+  for (int r = 0; r < NS; ++r) {
+    const int64_t e = tl.eidx(r, a.m);
+    if (mode == kXO) {
+      p[r] = a.P2[e];
+    } else {
+      p[r] = a.P1[e];
+      l[r] = a.L[e];
+    }
+    p[r] = v[r] ? p[r] : T(0);
+    l[r] = v[r] ? l[r] : T(0);
+  }
+  if (mode != kXO) {
+    phase_b<T, MP, NS>(el, p, l, wi, rho, a2);
+#pragma unroll
+    for (int r = 0; r < NS; ++r)
+      if (v[r]) {
+        const int64_t e = tl.eidx(r, a.m);
+        a.P2[e] = p[r];
+        a.L[e] = l[r];
+      }
+  }
+  if (mode == kBX || mode == kXO) {
+    // numerators sum_j Pi2_ij y_j,t (t < d) and denominators sum_j Pi2_ij
+    for (int t = 0; t <= d; ++t) {
+      T s = T(0);
+#pragma unroll
+      for (int r = 0; r < NS; ++r) {
+        T yv = t < d ? a.X[(tl.o + tl.colc(r)) * a.xs + t] : T(1);
+        s = fma(p[r], yv, s);
+      }
+      s = sum_row<MP>(s);
+      if (lane < MP) accx[lane * (d + 1) + t] += (double)s;
+    }
+  }
+}
+
 template <typename T, int MP, int R>
 __global__ void __launch_bounds__(256) k_aux(Args<T> a, int mode) {
   extern __shared__ double s_dyn[];  // [nwaves][MP][d+1] support numerators
@@ -375,15 +556,16 @@ __global__ void __launch_bounds__(256) k_aux(Args<T> a, int mode) {
   if (ch >= a.nchunks) return;
   const Chunk cj = a.chunks[ch];
   const int c = cj.cluster;
-  const int wave = threadIdx.x / kWave, nwaves = blockDim.x / kWave;
+  const int wave = uni(threadIdx.x / kWave), nwaves = blockDim.x / kWave;
   const int lane = threadIdx.x & (kWave - 1);
   const int i = lane % MP;
   const int d = a.d;
   const bool rowok = i < a.m;
   const bool xnum = (mode == kBX || mode == kXO);
   const T eps = (T)a.eps;
-  const T rho = mode == kRho ? T(1) : (T)a.rho[c];
-  const T irho = T(1) / rho;
+  const double rhod = mode == kRho ? 1.0 : a.rho[c];
+  const T rho = (T)rhod;
+  const T a2 = (T)(kLog2e / rhod);
   const T wi = rowok ? (T)a.w_in[c * MP + i] : T(0);
   const double* xrow = a.xc + ((int64_t)c * MP + (rowok ? i : 0)) * d;
   double* accx = s_dyn + (int64_t)wave * MP * (d + 1);
@@ -391,97 +573,13 @@ __global__ void __launch_bounds__(256) k_aux(Args<T> a, int mode) {
     for (int q = lane; q < MP * (d + 1); q += kWave) accx[q] = 0.0;
   double accw = 0.0, accf = 0.0;
   for (int pos = cj.begin + wave; pos < cj.end; pos += nwaves) {
-    Tile<T, MP, R> tl;
-    const int k = a.work[pos];
-    tl.setup(a, k);
-    T p[R], l[R], cs[R], wk[R];
-    bool v[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      v[r] = tl.valid(r);
-      p[r] = l[r] = cs[r] = wk[r] = T(0);
-    }
-    if (mode == kRho) {
-      T s = T(0);
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        T cv = cost_generic<T>(xrow, a.X + (tl.o + tl.colc(r)) * a.xs, d);
-        if (v[r]) {
-          if (a.Cc) a.Cc[tl.eidx(r, a.m)] = cv;
-          s += cv;
-        }
-      }
-      accf += (double)s;  // lane partial, reduced over the wave at the end
-      continue;
-    }
-    if (mode == kA0 || mode == kAP) {
-      const bool cached = (mode == kAP) || (a.warm && a.warm[k]);
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const int64_t e = tl.eidx(r, a.m);
-        const int jc = tl.colc(r);
-        wk[r] = a.W[tl.o + jc];
-        T cv = cost_generic<T>(xrow, a.X + (tl.o + jc) * a.xs, d);
-        if (mode == kAP && a.Cc && v[r]) a.Cc[e] = cv;
-        cs[r] = (mode == kA0 && a.Cc) ? a.Cc[e] : cv;
-        if (mode == kAP) {
-          p[r] = a.P2[e];
-          l[r] = a.L[e];
-        } else {
-          p[r] = cached ? a.P2[e] : wi * wk[r];
-        }
-        p[r] = v[r] ? p[r] : T(0);
-        l[r] = v[r] ? l[r] : T(0);
-      }
-      T rr, f = T(0);
-      phase_a<T, MP, R>(v, p, l, cs, wk, irho, eps, rr, f);
-      accw += consensus_term<T, MP>(rr, rowok, a.rule);
-      accf += (double)f;
-#pragma unroll
-      for (int r = 0; r < R; ++r)
-        if (v[r]) {
-          const int64_t e = tl.eidx(r, a.m);
-          a.P1[e] = p[r];
-          a.L[e] = l[r];
-        }
-      continue;
-    }
-    // phase-B modes and the support-only mode
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int64_t e = tl.eidx(r, a.m);
-      if (mode == kXO) {
-        p[r] = a.P2[e];
-      } else {
-        p[r] = a.P1[e];
-        l[r] = a.L[e];
-      }
-      p[r] = v[r] ? p[r] : T(0);
-      l[r] = v[r] ? l[r] : T(0);
-    }
-    if (mode != kXO) {
-      phase_b<T, MP, R>(v, p, l, wi, rho, irho, eps);
-#pragma unroll
-      for (int r = 0; r < R; ++r)
-        if (v[r]) {
-          const int64_t e = tl.eidx(r, a.m);
-          a.P2[e] = p[r];
-          a.L[e] = l[r];
-        }
-    }
-    if (xnum) {
-      // numerators sum_j Pi2_ij y_j,t (t < d) and denominators sum_j Pi2_ij
-      for (int t = 0; t <= d; ++t) {
-        T s = T(0);
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-          T yv = t < d ? a.X[(tl.o + tl.colc(r)) * a.xs + t] : T(1);
-          s = fma(p[r], yv, s);
-        }
-        s = sum_row<MP>(s);
-        if (lane < MP) accx[lane * (d + 1) + t] += (double)s;
-      }
-    }
+    Tile<T, MP> tl;
+    const int k = uni(a.work[pos]);
+    tl.setup(a.off, a.m, k);
+    with_slots<R>(tl.nsl, [&]<int NS>() {
+      aux_tile<T, MP, NS>(a, tl, k, mode, xrow, wi, rho, a2, eps, accw, accf,
+                          accx);
+    });
   }
   const int nrec = MP * (d + 1);
   if (mode == kRho) {
@@ -507,33 +605,39 @@ __global__ void __launch_bounds__(256) k_aux(Args<T> a, int mode) {
 }
 
 // ---------------------------------------------------------------------------
-// Per-cluster finalisation: sums the chunk records of a cluster in chunk
-// order.  One workgroup per cluster.
+// Per-cluster finalisation: sums the chunk records of a cluster in a fixed
+// order.  One workgroup per cluster; each thread owns one column and one
+// residue class of chunks, and issues its loads 8 at a time.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ double sum_strided(const double* base, int64_t st,
+                                              int q0, int qn, int step) {
+  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int q = q0;
+  for (; q + 7 * step < qn; q += 8 * step) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc[u] += base[(int64_t)(q + u * step) * st];
+  }
+  for (int u = 0; q < qn; q += step, ++u) acc[u] += base[(int64_t)q * st];
+  return ((acc[0] + acc[1]) + (acc[2] + acc[3])) +
+         ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+}
+
 template <int MP>
 __global__ void __launch_bounds__(256) k_fin(FinArgs f, int mode) {
   extern __shared__ double s_x[];  // kFinX: MP*(d+1) sums
   __shared__ double s_red[256];
   __shared__ double s_out[MP + 1];
   __shared__ double s_v[MP];
+  __shared__ double s_vs;
   const int c = blockIdx.x;
   const int2 ct = f.ctab[c];
   if (ct.y == 0) return;  // empty cluster: keep everything
   const int tid = threadIdx.x, nt = blockDim.x;
   if (mode == kFinX) {
     const int nrec = MP * (f.d + 1);
-    for (int q = tid; q < nrec; q += nt) {
-      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-      int u = 0;
-      for (; u + 3 < ct.y; u += 4) {
-        s0 += f.partx[(int64_t)(ct.x + u) * nrec + q];
-        s1 += f.partx[(int64_t)(ct.x + u + 1) * nrec + q];
-        s2 += f.partx[(int64_t)(ct.x + u + 2) * nrec + q];
-        s3 += f.partx[(int64_t)(ct.x + u + 3) * nrec + q];
-      }
-      for (; u < ct.y; ++u) s0 += f.partx[(int64_t)(ct.x + u) * nrec + q];
-      s_x[q] = (s0 + s1) + (s2 + s3);
-    }
+    for (int q = tid; q < nrec; q += nt)
+      s_x[q] = sum_strided(f.partx + (int64_t)ct.x * nrec + q, nrec, 0, ct.y,
+                           1);
     __syncthreads();
     for (int q = tid; q < MP * f.d; q += nt) {
       const int ii = q / f.d, t = q % f.d;
@@ -546,12 +650,10 @@ __global__ void __launch_bounds__(256) k_fin(FinArgs f, int mode) {
   const int ncol = mode == kFinRho ? 1 : MP + 1;
   const int groups = nt / ncol;
   const int col = tid % ncol, grp = tid / ncol;
-  if (grp < groups) {
-    double s = 0.0;
-    for (int q = grp; q < ct.y; q += groups)
-      s += f.part[(int64_t)(ct.x + q) * f.ps + col];
-    s_red[grp * ncol + col] = s;
-  }
+  if (grp < groups)
+    s_red[grp * ncol + col] =
+        sum_strided(f.part + (int64_t)ct.x * f.ps + col, f.ps, grp, ct.y,
+                    groups);
   __syncthreads();
   if (tid < ncol) {
     double t = 0.0;
@@ -564,7 +666,6 @@ __global__ void __launch_bounds__(256) k_fin(FinArgs f, int mode) {
     return;
   }
   const double ni = f.ninv[c];
-  __shared__ double s_vs;
   if (tid < MP) {
     double t = tid < f.m ? s_out[tid] * ni : 0.0;
     s_v[tid] = f.rule == 2 ? t * t : t;
@@ -592,89 +693,190 @@ template <typename T> struct AssignArgs {
   const double* wc;  // K x MP
   int32_t* labels;
   double* best;
+  unsigned long long* evaluated;  // pairs run through the iterations
   int64_t N;
   double rho0, eps;
-  int m, d, xs, K, iters;
+  int m, d, xs, K, iters, prune;
 };
 
-template <typename T, int MP, int R>
-__global__ void __launch_bounds__(256) k_assign(AssignArgs<T> a) {
-  constexpr int CPS = kWave / MP;
-  const int lane = threadIdx.x & (kWave - 1);
-  const int64_t k = (int64_t)blockIdx.x * (blockDim.x / kWave) +
-                    threadIdx.x / kWave;
-  if (k >= a.N) return;  // whole wavefront exits together
-  const int i = lane % MP, g = lane / MP;
-  const int64_t o = a.off[k];
-  const int mk = (int)(a.off[k + 1] - o);
-  const bool rowok = i < a.m;
-  const T eps = (T)a.eps;
-  T wk[R];
-  bool v[R];
-  int jc[R];
+// Any coupling whose column sums are the instance weights w_j (as Pi1's are,
+// Eq. (badmmc0)) has cost sum_j w_j sum_i (Pi1_ij / w_j) C_ij >=
+// sum_j w_j min_i C_ij.  This lower bound of the assignment distance lets a
+// centroid be skipped when it exceeds the best distance found so far.
+template <typename T, int MP, int NS>
+__device__ __forceinline__ double cost_lower_bound(const T (&cs)[NS],
+                                                   const bool (&v)[NS],
+                                                   const T (&wk)[NS], int i) {
+  const T big = T(3.0e38);
+  T mn[NS];
 #pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const int j = g + CPS * r;
-    v[r] = rowok && j < mk;
-    jc[r] = j < mk ? j : mk - 1;
-    wk[r] = a.W[o + jc[r]];
-    wk[r] = v[r] ? wk[r] : T(0);
+  for (int r = 0; r < NS; ++r) mn[r] = v[r] ? cs[r] : big;
+  // column minimum over the MP lanes of each column group
+#pragma unroll
+  for (int r = 0; r < NS; ++r) {
+    if constexpr (MP >= 2) mn[r] = fmin(mn[r], xdpp_raw<0xB1>(mn[r]));
+    if constexpr (MP >= 4) mn[r] = fmin(mn[r], xdpp_raw<0x4E>(mn[r]));
+    if constexpr (MP >= 8) mn[r] = fmin(mn[r], xdpp_raw<0x141>(mn[r]));
+    if constexpr (MP >= 16) mn[r] = fmin(mn[r], xdpp_raw<0x140>(mn[r]));
+    if constexpr (MP >= 32) mn[r] = fmin(mn[r], xswz16(mn[r]));
+    if constexpr (MP >= 64) mn[r] = fmin(mn[r], x32(mn[r]));
   }
-  double bestv = 0.0;
-  int bestc = -1;
+  double lb = 0.0;
+#pragma unroll
+  for (int r = 0; r < NS; ++r)
+    if (i == 0 && wk[r] > T(0)) lb += (double)wk[r] * (double)mn[r];
+  return sum_wave(lb);
+}
+
+template <typename T, int MP, int NS>
+__device__ __forceinline__ void pair_costs(const AssignArgs<T>& a,
+                                           const Tile<T, MP>& tl, int c,
+                                           const bool (&v)[NS],
+                                           const int (&jc)[NS], T (&cs)[NS]) {
+  const double* xrow = a.xc + ((int64_t)c * MP + tl.ic) * a.d;
+#pragma unroll
+  for (int r = 0; r < NS; ++r) {
+    T cv = cost_generic<T>(xrow, a.X + (tl.o + jc[r]) * a.xs, a.d);
+    cs[r] = v[r] ? cv : T(0);
+  }
+}
+
+// B-ADMM transport value <C, Pi1> of one (instance, centroid) pair after
+// `iters` iterations with both marginals fixed.
+template <typename T, int MP, int NS>
+__device__ __forceinline__ double pair_value(const AssignArgs<T>& a,
+                                             const Tile<T, MP>& tl, int c,
+                                             const T (&cs)[NS],
+                                             const T (&wk)[NS],
+                                             const T (&el)[NS],
+                                             const bool (&v)[NS]) {
+  T p1[NS], p2[NS], l[NS], kc[NS], av[NS], s[NS], E[NS];
+  T csum = T(0);
+#pragma unroll
+  for (int r = 0; r < NS; ++r) csum += cs[r];
+  const double tot = sum_wave((double)csum);
+  const double rhod = a.rho0 * tot / ((double)a.m * tl.mk);
+  const T rho = (T)rhod;
+  const T a2 = (T)(kLog2e / rhod);
+  const T wi = tl.rowok ? (T)a.wc[c * MP + tl.i] : T(0);
+  // exp(-(C + Lambda)/rho) = K / E with K = exp(-C/rho) fixed for the
+  // pair and E = exp(Lambda/rho), which the Pi1~ step needs anyway
+#pragma unroll
+  for (int r = 0; r < NS; ++r) {
+    p2[r] = wi * wk[r];
+    l[r] = T(0);
+    p1[r] = T(0);
+    kc[r] = v[r] ? dexp2(-cs[r] * a2) : T(0);
+  }
+  for (int it = 0; it < a.iters; ++it) {
+#pragma unroll
+    for (int r = 0; r < NS; ++r) {
+      E[r] = dexp2(l[r] * a2);
+      av[r] = fma(p2[r] * kc[r], drcp(E[r]), el[r]);
+      s[r] = av[r];
+    }
+    sum_col_n<MP, NS>(s);
+    T rr = T(0);
+#pragma unroll
+    for (int r = 0; r < NS; ++r) {
+      const T q = av[r] * (wk[r] * rcp_sum(s[r]));
+      p1[r] = q;
+      p2[r] = fma(q, E[r], el[r]);
+      rr += p2[r];
+    }
+    rr = sum_row<MP>(rr);
+    const T coef = wi * rcp_sum(rr);
+#pragma unroll
+    for (int r = 0; r < NS; ++r) {
+      const T q = p2[r] * coef;
+      l[r] = fma(rho, p1[r] - q, l[r]);
+      p2[r] = q;
+    }
+  }
+  T fv = T(0);
+#pragma unroll
+  for (int r = 0; r < NS; ++r) fv = fma(cs[r], p1[r], fv);
+  return sum_wave((double)fv);
+}
+
+template <typename T, int MP, int NS>
+__device__ __forceinline__ void assign_tile(const AssignArgs<T>& a,
+                                            const Tile<T, MP>& tl,
+                                            double& bestv, int& bestc,
+                                            int& nevals) {
+  const T eps = (T)a.eps;
+  T wk[NS], el[NS], cs[NS];
+  bool v[NS];
+  int jc[NS];
+#pragma unroll
+  for (int r = 0; r < NS; ++r) {
+    v[r] = tl.valid(r);
+    jc[r] = tl.colc(r);
+    wk[r] = a.W[tl.o + jc[r]];
+    wk[r] = v[r] ? wk[r] : T(0);
+    el[r] = v[r] ? eps : T(0);
+  }
+  if (!a.prune) {
+    for (int c = 0; c < a.K; ++c) {
+      pair_costs<T, MP, NS>(a, tl, c, v, jc, cs);
+      const double val = pair_value<T, MP, NS>(a, tl, c, cs, wk, el, v);
+      ++nevals;
+      if (bestc < 0 || val < bestv) {
+        bestv = val;
+        bestc = c;
+      }
+    }
+    return;
+  }
+  // 1) the centroid with the smallest lower bound is evaluated first
+  int c0 = 0;
+  double lb0 = 0.0;
   for (int c = 0; c < a.K; ++c) {
-    const double* xrow = a.xc + ((int64_t)c * MP + (rowok ? i : 0)) * a.d;
-    T cs[R], p1[R], p2[R], l[R];
-    T csum = T(0);
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      T cv = cost_generic<T>(xrow, a.X + (o + jc[r]) * a.xs, a.d);
-      cs[r] = v[r] ? cv : T(0);
-      csum += cs[r];
+    pair_costs<T, MP, NS>(a, tl, c, v, jc, cs);
+    const double lb = cost_lower_bound<T, MP, NS>(cs, v, wk, tl.i);
+    if (c == 0 || lb < lb0) {
+      lb0 = lb;
+      c0 = c;
     }
-    const double tot = sum_wave((double)csum);
-    const T rho = (T)(a.rho0 * tot / ((double)a.m * mk));
-    const T irho = T(1) / rho;
-    const T wi = rowok ? (T)a.wc[c * MP + i] : T(0);
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      p2[r] = wi * wk[r];
-      l[r] = T(0);
-      p1[r] = T(0);
-    }
-    for (int it = 0; it < a.iters; ++it) {
-      T rr = T(0);
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        T av = v[r] ? p2[r] * dexp(-(cs[r] + l[r]) * irho) + eps : T(0);
-        T s = sum_col<MP>(av);
-        T q = (v[r] && s > T(0)) ? av * (wk[r] * drcp(s)) : T(0);
-        p1[r] = q;
-        T b = v[r] ? q * dexp(l[r] * irho) + eps : T(0);
-        p2[r] = b;
-        rr += b;
-      }
-      rr = sum_row<MP>(rr);
-      const T coef = rr > T(0) ? wi * drcp(rr) : T(0);
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        T q = p2[r] * coef;
-        l[r] = l[r] + rho * (p1[r] - q);
-        p2[r] = q;
-      }
-    }
-    T fv = T(0);
-#pragma unroll
-    for (int r = 0; r < R; ++r) fv = fma(cs[r], p1[r], fv);
-    const double val = sum_wave((double)fv);
-    if (bestc < 0 || val < bestv) {
+  }
+  pair_costs<T, MP, NS>(a, tl, c0, v, jc, cs);
+  bestv = pair_value<T, MP, NS>(a, tl, c0, cs, wk, el, v);
+  bestc = c0;
+  ++nevals;
+  // 2) every other centroid unless its bound clears the best value by a
+  // margin far above FP32 rounding of the column sums (so a skipped
+  // centroid can never be the argmin; ties go to the lowest index)
+  for (int c = 0; c < a.K; ++c) {
+    if (c == c0) continue;
+    pair_costs<T, MP, NS>(a, tl, c, v, jc, cs);
+    const double lb = cost_lower_bound<T, MP, NS>(cs, v, wk, tl.i);
+    if (lb > bestv * (1.0 + 1e-4)) continue;
+    const double val = pair_value<T, MP, NS>(a, tl, c, cs, wk, el, v);
+    ++nevals;
+    if (val < bestv || (val == bestv && c < bestc)) {
       bestv = val;
       bestc = c;
     }
   }
+}
+
+template <typename T, int MP, int R>
+__global__ void __launch_bounds__(256) k_assign(AssignArgs<T> a) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t k = (int64_t)blockIdx.x * (blockDim.x / kWave) +
+                    uni(threadIdx.x / kWave);
+  if (k >= a.N) return;  // whole wavefront exits together
+  Tile<T, MP> tl;
+  tl.setup(a.off, a.m, (int)k);
+  double bestv = 0.0;
+  int bestc = -1, nevals = 0;
+  with_slots<R>(tl.nsl, [&]<int NS>() {
+    assign_tile<T, MP, NS>(a, tl, bestv, bestc, nevals);
+  });
   if (lane == 0) {
     a.labels[k] = bestc;
     a.best[k] = bestv;
+    if (a.evaluated) atomicAdd(a.evaluated, (unsigned long long)nevals);
   }
 }
 

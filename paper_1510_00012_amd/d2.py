@@ -27,7 +27,8 @@ EXPORTS = [
     "d2_centroids_set", "d2_centroids_get", "d2_centroids_init",
     "d2_labels_set", "d2_labels_get", "d2_assign", "d2_barycenter",
     "d2_support_update", "d2_cluster", "d2_objective", "d2_plans_get",
-    "d2_sizes", "d2_set_profiling", "d2_kernel_stats",
+    "d2_sizes", "d2_set_profiling", "d2_kernel_stats", "d2_set_schedule",
+    "d2_assign_pairs",
 ]
 
 
@@ -46,7 +47,7 @@ class BadmmParams(ctypes.Structure):
 
 class OtParams(ctypes.Structure):
     _fields_ = [("rho0", ctypes.c_double), ("eps", ctypes.c_double),
-                ("iters", ctypes.c_int32)]
+                ("iters", ctypes.c_int32), ("prune", ctypes.c_int32)]
 
 
 class BadmmStats(ctypes.Structure):
@@ -105,6 +106,8 @@ def load_library(path: str = LIB_PATH):
         "d2_plans_get": ([_p, _i64, _p, _p, _p], ctypes.c_int),
         "d2_sizes": ([_p, _p, _p, _p, _p, _p], ctypes.c_int),
         "d2_set_profiling": ([_p, _i32], ctypes.c_int),
+        "d2_set_schedule": ([_p, _i32, _i32], ctypes.c_int),
+        "d2_assign_pairs": ([_p, _p, _p], ctypes.c_int),
         "d2_kernel_stats": ([_p, ctypes.POINTER(KernelStat), _i32, _p, _i32],
                             ctypes.c_int),
     }
@@ -130,8 +133,8 @@ def badmm_params(iters=100, tau=10, rho0=2.0, eps=1e-16, rule=1,
                        xplan=0, init=init, fixed_support=int(fixed_support))
 
 
-def ot_params(iters=100, rho0=2.0, eps=1e-16):
-    return OtParams(rho0=rho0, eps=eps, iters=iters)
+def ot_params(iters=100, rho0=2.0, eps=1e-16, prune=True):
+    return OtParams(rho0=rho0, eps=eps, iters=iters, prune=int(bool(prune)))
 
 
 class D2Context:
@@ -211,11 +214,11 @@ class D2Context:
         return lab
 
     # ------------------------------------------------------------ steps
-    def assign(self, iters=100, rho0=2.0, eps=1e-16):
+    def assign(self, iters=100, rho0=2.0, eps=1e-16, prune=True):
         lab = np.empty(self.N, dtype=np.int32)
         dist = np.empty(self.N)
         nch = ctypes.c_int64(0)
-        p = ot_params(iters, rho0, eps)
+        p = ot_params(iters, rho0, eps, prune)
         self._chk(self.lib.d2_assign(self.h, ctypes.byref(p), _ptr(lab),
                                      _ptr(dist), ctypes.byref(nch)))
         return lab, dist, int(nch.value)
@@ -229,13 +232,20 @@ class D2Context:
         return {"iters": s.iters, "n_empty": s.n_empty,
                 "launches": s.launches, "graph": s.graph, "ms": s.ms}
 
+    def assign_pairs(self):
+        """(pairs iterated, total pairs) of the last assignment."""
+        e, t = ctypes.c_int64(0), ctypes.c_int64(0)
+        self._chk(self.lib.d2_assign_pairs(self.h, ctypes.byref(e),
+                                           ctypes.byref(t)))
+        return int(e.value), int(t.value)
+
     def support_update(self):
         self._chk(self.lib.d2_support_update(self.h))
 
     def cluster(self, rounds, iters=100, tau=10, rho0=2.0, eps=1e-16, rule=1,
-                assign_iters=100, callback=None):
+                assign_iters=100, prune=True, callback=None):
         bp = badmm_params(iters, tau, rho0, eps, rule, D2_INIT_CACHED)
-        op = ot_params(assign_iters, rho0, eps)
+        op = ot_params(assign_iters, rho0, eps, prune)
         recs = []
 
         def _cb(info, user):
@@ -258,6 +268,10 @@ class D2Context:
         self._chk(self.lib.d2_objective(self.h, _ptr(tr), int(iters),
                                         _ptr(rho)))
         return tr, rho
+
+    def set_schedule(self, chunk_instances, waves_per_group):
+        self._chk(self.lib.d2_set_schedule(self.h, int(chunk_instances),
+                                           int(waves_per_group)))
 
     def set_profiling(self, on=True):
         self._chk(self.lib.d2_set_profiling(self.h, int(bool(on))))

@@ -270,3 +270,24 @@ def test_cluster_call_runs_and_is_deterministic(d2):
     assert outs[0][3][0]["n_changed"] == 5000
     assert [r["n_changed"] for r in outs[0][3]] == \
         [r["n_changed"] for r in outs[1][3]]
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_assignment_pruning_is_exact(d2, dtype):
+    """The lower-bound pruning of the assignment returns exactly the labels
+    and minimal distances of the exhaustive search, while iterating fewer
+    (instance, centroid) pairs."""
+    print(f"[assign_prune {dtype}]", flush=True)
+    wl = make_workload("cfg2", N=4000)
+    mem = pick_init_members(wl["offsets"], 16, 16, 23)
+    Xc, Wc = oracle.init_centroids(wl, mem, 16)
+    with _ctx(d2, wl, dtype) as ctx:
+        ctx.centroids_set(Xc, Wc)
+        lab_a, best_a, _ = ctx.assign(iters=100, prune=False)
+        ev_a, tot = ctx.assign_pairs()
+        lab_b, best_b, _ = ctx.assign(iters=100, prune=True)
+        ev_b, _ = ctx.assign_pairs()
+    assert ev_a == tot == 4000 * 16
+    assert ev_b < tot
+    assert np.array_equal(lab_a, lab_b)
+    assert np.array_equal(best_a, best_b)

@@ -467,3 +467,19 @@ def test_cluster_loop_with_one_point_is_lloyd_on_means(oracle_mod):
                 cen[c] = means[lab == c].mean(0)
     assert np.array_equal(out["labels"], lab)
     np.testing.assert_allclose(out["Xc"][:, 0], cen, atol=1e-12)
+
+
+def test_assignment_lower_bound_holds(oracle_mod):
+    """The pruning bound used by the assignment: any plan with the instance's
+    column sums (Pi1 after any number of iterations) costs at least
+    sum_j w_j min_i C_ij; checked on the oracle's transport values and on
+    the exact W^2 (LP)."""
+    rng = np.random.default_rng(31)
+    for _ in range(30):
+        m, mk = rng.integers(1, 9), rng.integers(1, 9)
+        x, w = _rand_dist(rng, m, 3)
+        y, wy = _rand_dist(rng, mk, 3)
+        lb = float(wy @ cdist(x, y, "sqeuclidean").min(axis=0))
+        for T in (1, 5, 100):
+            assert oracle_mod.badmm_ot(x, w, y, wy, T=T) >= lb * (1 - 1e-12)
+        assert oracle_mod.exact_w2(x, w, y, wy)[0] >= lb * (1 - 1e-9)
