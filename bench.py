@@ -115,9 +115,9 @@ def cpu_baseline(wl, Xc, Wc, T, tau, T_assign, target_s=15.0):
         t2 = time.perf_counter()
         return t1 - t0, t2 - t1
 
-    pa, pb = run(64)
-    per = (pa + pb) / 64
-    S = int(min(N, max(64, target_s / max(per, 1e-9))))
+    pa, pb = run(512)
+    per = (pa + pb) / 512
+    S = int(min(N, max(512, target_s / max(per, 1e-9))))
     ta, tb = run(S)
     return {"value": S * T / (ta + tb), "unit": "instance-iterations/s",
             "cores": oracle.num_threads(), "kind": "oracle",
@@ -133,6 +133,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cfg2")
     ap.add_argument("--iters", type=int, default=None)
+    ap.add_argument("--profile-rounds", type=int, default=3,
+                    help="host-issued rounds timed per kernel with HIP events")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="run a plain device copy of this size first (counter "
+                         "calibration for rocprofv3 --pmc runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     args = ap.parse_args()
@@ -159,6 +164,14 @@ def main():
         f"K={K} m={m} d={wl['X'].shape[1]} T={T} "
         f"(generated in {time.perf_counter() - t0:.1f}s)")
     members = pick_init_members(wl["offsets"], K, m, wl["seed"])
+    if args.copy_mib:
+        src = torch.ones(args.copy_mib * 262144, dtype=torch.float32,
+                         device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log(f"[bench] calibration copy of {args.copy_mib} MiB done")
     stream = torch.cuda.Stream()
     ctx = d2.D2Context(0, "f32", stream=stream.cuda_stream)
     ctx.load_instances(wl["offsets"], wl["X"], wl["W"])
@@ -173,9 +186,7 @@ def main():
     for w in range(args.warmup):
         step(w == 0)
         log(f"[bench] warmup round {w} done")
-    torch.cuda.synchronize()
-    ctx.set_profiling(True)
-    ctx.kernel_stats(reset=True)
+    # timed rounds: the barycenter call replays its captured HIP graph
     bary_ms = []
     torch.cuda.synchronize()
     ts = time.perf_counter()
@@ -184,10 +195,20 @@ def main():
         bary_ms.append(st["ms"])
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - ts
+    graphed = bool(st["graph"])
+    # per-kernel durations: further rounds with every launch bracketed by
+    # HIP events on the context's stream (kernels inside a replayed graph
+    # cannot be bracketed individually)
+    ctx.set_profiling(True)
+    ctx.kernel_stats(reset=True)
+    for _ in range(args.profile_rounds):
+        step(False)
+    torch.cuda.synchronize()
     ctx.set_profiling(False)
     ks = ctx.kernel_stats(reset=True)
-    log(f"[bench] timed {args.steps} rounds in {elapsed:.3f}s; kernels: "
-        + ", ".join(f"{k}={v[1]:.1f}ms/{v[0]}" for k, v in ks.items()))
+    log(f"[bench] timed {args.steps} rounds in {elapsed:.3f}s (graph="
+        f"{graphed}); per-kernel ({args.profile_rounds} profiled rounds): "
+        + ", ".join(f"{k}={v[1]:.2f}ms/{v[0]}" for k, v in ks.items()))
 
     ms_step = 1000.0 * elapsed / args.steps
     value = N * T * args.steps / elapsed
@@ -211,7 +232,7 @@ def main():
                 "kernel": "k_iter_ba", "avg_launch_ms": 1000 * avg_s,
                 "bytes_per_launch": b}
 
-    dominant = max(ks.items(), key=lambda kv: kv[1][1])[0]
+    dominant = max(ks.items(), key=lambda kv: kv[1][1])[0] if ks else None
     rec = {
         "metric": "B-ADMM instance-iterations/s",
         "value": value,
@@ -236,9 +257,13 @@ def main():
         },
         "barycenter_inst_iter_per_s": N * T / (np.mean(bary_ms) / 1000.0),
         "barycenter_ms_mean": float(np.mean(bary_ms)),
+        "barycenter_graph": graphed,
+        "kernel_timing": "HIP events around each launch on the context "
+                         f"stream, {args.profile_rounds} host-issued rounds "
+                         "after the timed rounds",
         "kernel_ms": {k: {"launches": v[0], "total_ms": v[1]}
                       for k, v in ks.items()},
-        "roofline": roof(dominant),
+        "roofline": roof(dominant) if dominant else None,
         "roofline_plan_update": roof("iter_ba") if "iter_ba" in ks else None,
         "kernel_source_hash": src_hash,
     }

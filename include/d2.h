@@ -189,7 +189,7 @@ d2_status d2_plans_get(d2_ctx* ctx, int64_t k, double* P1, double* P2,
  * context is bracketed by two HIP events recorded on the context's stream,
  * and the elapsed times are accumulated per kernel kind when the call that
  * launched them synchronises.  Kinds: "rho_cost", "init_a", "iter_ba",
- * "b_xnum", "a_from_p2", "b_final", "xnum_only", "assign". */
+ * "b_final", "xnum_only", "assign", "finalize". */
 typedef struct {
   char name[24];
   int64_t launches;
@@ -201,6 +201,13 @@ d2_status d2_set_profiling(d2_ctx* ctx, int32_t on);
  * their number; `reset` != 0 clears the accumulators afterwards. */
 d2_status d2_kernel_stats(d2_ctx* ctx, d2_kernel_stat* out, int32_t cap,
                           int32_t* count, int32_t reset);
+
+/* Capture the launch sequence of d2_barycenter in a HIP graph on first use
+ * (per iterations / tau / rule / schedule / sizes) and replay it (on = 1,
+ * the default), or issue every launch from the host (on = 0).  With
+ * profiling on, launches are issued from the host so that each can be
+ * bracketed by events. */
+d2_status d2_set_graph(d2_ctx* ctx, int32_t on);
 
 /* Launch schedule of the barycenter kernels: instances per workgroup chunk
  * (1 .. 4096) and wavefronts per workgroup (1, 2 or 4).  Results do not

@@ -60,12 +60,11 @@ const d2k::FinFn* fin_table() {
 }  // namespace
 
 enum KernelKind {
-  kKRho = 0, kKInitA, kKIterBA, kKBX, kKAP, kKBF, kKXO, kKAssign, kKFin,
-  kKinds
+  kKRho = 0, kKInitA, kKIterBA, kKBF, kKXO, kKAssign, kKFin, kKinds
 };
 static const char* kKindNames[kKinds] = {"rho_cost", "init_a", "iter_ba",
-                                         "b_xnum", "a_from_p2", "b_final",
-                                         "xnum_only", "assign", "finalize"};
+                                         "b_final", "xnum_only", "assign",
+                                         "finalize"};
 
 struct d2_ctx {
   int device = 0;
@@ -77,14 +76,15 @@ struct d2_ctx {
   int64_t N = 0, n = 0;
   int d = 0, xs = 0, mk_max = 0;  // xs: device row stride of X (4 if d<=4)
   std::vector<int64_t> h_off;
+  std::vector<int64_t> h_pofs;  // plan tile offsets (128-byte aligned), N+1
   int64_t* d_off = nullptr;
+  int64_t* d_pofs = nullptr;
   void* d_X = nullptr;
   void* d_W = nullptr;
   // centroids (double on device, rows padded to MP)
   int K = 0, m = 0, MP = 0, R = 0;
   double* d_xc = nullptr;
   double* d_wc = nullptr;
-  double* d_wbuf = nullptr;  // 2 x K x MP
   double* d_rho = nullptr;
   int* d_cnt = nullptr;
   // labels
@@ -110,14 +110,21 @@ struct d2_ctx {
   double* d_ninv = nullptr;
   double* d_cinv = nullptr;
   uint8_t* d_warm = nullptr;
-  double* d_part = nullptr;
-  double* d_partx = nullptr;
+  double* d_part = nullptr;   // 2 x cap x ps (double-buffered records)
+  double* d_partx = nullptr;  // 2 x cap x MP x (d+1) support records
+  int* d_nch = nullptr;       // device copy of nchunks
   std::vector<int2> h_ctab;
   bool lists_valid = false;
   // objective trace of the last barycenter
   double* d_trace = nullptr;
   int trace_cap = 0, trace_rows = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  // captured launch sequence of d2_barycenter
+  bool use_graph = true;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  std::vector<double> graph_key;
+  int graph_launches = 0;
   // per-kernel profiling
   bool prof = false;
   struct Pending {
@@ -164,7 +171,16 @@ d2_status dalloc(d2_ctx* c, void** p, size_t bytes) {
   return D2_OK;
 }
 
+void drop_graph(d2_ctx* c) {
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  c->gexec = nullptr;
+  c->graph = nullptr;
+  c->graph_key.clear();
+}
+
 void free_plans(d2_ctx* c) {
+  drop_graph(c);
   dfree(c->d_P1);
   dfree(c->d_P2);
   dfree(c->d_L);
@@ -181,14 +197,16 @@ void free_lists(d2_ctx* c) {
   dfree(c->d_warm);
   dfree(c->d_part);
   dfree(c->d_partx);
+  dfree(c->d_nch);
   c->nch_cap = 0;
   c->lists_valid = false;
+  drop_graph(c);
 }
 
 void free_centroids(d2_ctx* c) {
+  drop_graph(c);
   dfree(c->d_xc);
   dfree(c->d_wc);
-  dfree(c->d_wbuf);
   dfree(c->d_rho);
   dfree(c->d_cnt);
   c->K = c->m = c->MP = 0;
@@ -196,6 +214,7 @@ void free_centroids(d2_ctx* c) {
 
 void free_instances(d2_ctx* c) {
   dfree(c->d_off);
+  dfree(c->d_pofs);
   dfree(c->d_X);
   dfree(c->d_W);
   dfree(c->d_labels);
@@ -281,8 +300,6 @@ d2_status ensure_centroid_bufs(d2_ctx* c, int K, int m) {
   if ((s = dalloc(c, (void**)&c->d_xc, sizeof(double) * K * c->MP * c->d)))
     return s;
   if ((s = dalloc(c, (void**)&c->d_wc, sizeof(double) * K * c->MP))) return s;
-  if ((s = dalloc(c, (void**)&c->d_wbuf, sizeof(double) * 2 * K * c->MP)))
-    return s;
   if ((s = dalloc(c, (void**)&c->d_rho, sizeof(double) * K))) return s;
   if ((s = dalloc(c, (void**)&c->d_cnt, sizeof(int) * K))) return s;
   HIPCHK(c, hipMemset(c->d_cnt, 0, sizeof(int) * K));
@@ -377,10 +394,11 @@ d2_status build_lists(d2_ctx* c, bool warm_start) {
     if ((s = dalloc(c, (void**)&c->d_cinv, sizeof(double) * K))) return s;
     if ((s = dalloc(c, (void**)&c->d_warm, N))) return s;
     if ((s = dalloc(c, (void**)&c->d_part,
-                    sizeof(double) * cap * (c->MP + 2))))
+                    sizeof(double) * 2 * cap * (c->MP + 2))))
       return s;
+    if ((s = dalloc(c, (void**)&c->d_nch, sizeof(int)))) return s;
     if ((s = dalloc(c, (void**)&c->d_partx,
-                    sizeof(double) * cap * c->MP * (c->d + 1))))
+                    sizeof(double) * 2 * cap * c->MP * (c->d + 1))))
       return s;
   }
   std::vector<uint8_t> warm(N, 0);
@@ -399,13 +417,26 @@ d2_status build_lists(d2_ctx* c, bool warm_start) {
   HIPCHK(c, hipMemcpy(c->d_cinv, cinv.data(), sizeof(double) * K,
                       hipMemcpyHostToDevice));
   HIPCHK(c, hipMemcpy(c->d_warm, warm.data(), N, hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->d_nch, &c->nchunks, sizeof(int),
+                      hipMemcpyHostToDevice));
   c->lists_valid = true;
   return D2_OK;
 }
 
 d2_status ensure_plans(d2_ctx* c) {
   if (c->d_P1) return D2_OK;
-  size_t bytes = (size_t)c->m * c->n * c->esz();
+  // plan tile of instance k starts at pofs[k], a multiple of 32 elements
+  c->h_pofs.assign(c->N + 1, 0);
+  for (int64_t k = 0; k < c->N; ++k) {
+    int64_t sz = (int64_t)c->m * (c->h_off[k + 1] - c->h_off[k]);
+    c->h_pofs[k + 1] = c->h_pofs[k] + (sz + 31) / 32 * 32;
+  }
+  dfree(c->d_pofs);
+  d2_status s0 = dalloc(c, (void**)&c->d_pofs, sizeof(int64_t) * (c->N + 1));
+  if (s0) return s0;
+  HIPCHK(c, hipMemcpy(c->d_pofs, c->h_pofs.data(),
+                      sizeof(int64_t) * (c->N + 1), hipMemcpyHostToDevice));
+  size_t bytes = (size_t)c->h_pofs[c->N] * c->esz();
   d2_status s;
   if ((s = dalloc(c, &c->d_P1, bytes))) return s;
   if ((s = dalloc(c, &c->d_P2, bytes))) return s;
@@ -460,8 +491,6 @@ int aux_kind(int mode) {
   switch (mode) {
     case d2k::kRho: return kKRho;
     case d2k::kA0: return kKInitA;
-    case d2k::kAP: return kKAP;
-    case d2k::kBX: return kKBX;
     case d2k::kBF: return kKBF;
     default: return kKXO;
   }
@@ -471,45 +500,48 @@ template <typename T>
 d2k::Args<T> make_args(d2_ctx* c, const d2_badmm_params* p) {
   d2k::Args<T> a;
   a.off = c->d_off;
+  a.pofs = c->d_pofs;
   a.X = (const T*)c->d_X;
   a.W = (const T*)c->d_W;
   a.work = c->d_work;
   a.chunks = c->d_chunks;
+  a.nch = c->d_nch;
+  a.ctab = c->d_ctab;
+  a.ninv = c->d_ninv;
   a.P1 = (T*)c->d_P1;
   a.P2 = (T*)c->d_P2;
   a.L = (T*)c->d_L;
   a.Cc = (T*)c->d_C;
   a.warm = c->d_warm;
   a.xc = c->d_xc;
-  a.w_in = c->d_wbuf;
+  a.wc = c->d_wc;
   a.rho = c->d_rho;
+  a.part_in = c->d_part;
   a.part = c->d_part;
-  a.partx = c->d_partx;
+  a.xin = nullptr;
+  a.xout = nullptr;
+  a.trace = nullptr;
+  a.recost = 0;
   a.eps = p ? p->eps : 1e-16;
   a.m = c->m;
   a.d = c->d;
   a.xs = c->xs;
   a.rule = p ? p->rule : 1;
   a.ps = c->MP + 2;
-  a.nchunks = c->nchunks;
   return a;
 }
 
 d2k::FinArgs make_fin(d2_ctx* c, const d2_badmm_params* p) {
   d2k::FinArgs f;
   f.ctab = c->d_ctab;
-  f.ninv = c->d_ninv;
   f.cinv = c->d_cinv;
   f.part = c->d_part;
-  f.partx = c->d_partx;
-  f.w_out = c->d_wbuf;
+  f.xrec = c->d_partx;
   f.rho = c->d_rho;
   f.xc = c->d_xc;
-  f.trace = nullptr;
   f.rho0 = p ? p->rho0 : 2.0;
   f.m = c->m;
   f.d = c->d;
-  f.rule = p ? p->rule : 1;
   f.ps = c->MP + 2;
   return f;
 }
@@ -533,12 +565,12 @@ d2_status launch_aux(d2_ctx* c, const d2k::Args<T>& a, int mode, int& nl) {
   if (!fn) return c->fail(D2_EINVAL, "no kernel for this tile shape");
   int waves = c->waves;
   size_t per_wave = sizeof(double) * c->MP * (c->d + 1);
-  bool xnum = (mode == d2k::kBX || mode == d2k::kXO);
+  bool xnum = (mode == d2k::kXO) || (mode == d2k::kA0 && a.xout);
   if (xnum)
     while (waves > 1 && per_wave * waves > 64 * 1024) --waves;
   size_t shm = xnum ? per_wave * waves : 0;
   hipEvent_t pe = prof_begin(c);
-  hipLaunchKernelGGL(fn, dim3(c->nchunks), dim3(64 * waves), shm, c->stream,
+  hipLaunchKernelGGL(fn, dim3(c->nch_cap), dim3(64 * waves), shm, c->stream,
                      a, mode);
   HIPCHK(c, hipGetLastError());
   prof_end(c, aux_kind(mode), pe);
@@ -551,8 +583,13 @@ d2_status launch_ba(d2_ctx* c, const d2k::Args<T>& a, int& nl) {
   const auto& kt = kern<T>();
   auto fn = kt.ba[c->onfly ? 1 : 0][ilog2(c->MP) - 3][ilog2(c->R)];
   if (!fn) return c->fail(D2_EINVAL, "no kernel for this tile shape");
+  int waves = c->waves;
+  size_t per_wave = sizeof(double) * c->MP * (c->d + 1);
+  if (a.xout)
+    while (waves > 1 && per_wave * waves > 64 * 1024) --waves;
+  size_t shm = a.xout ? per_wave * waves : 0;
   hipEvent_t pe = prof_begin(c);
-  hipLaunchKernelGGL(fn, dim3(c->nchunks), dim3(64 * c->waves), 0, c->stream,
+  hipLaunchKernelGGL(fn, dim3(c->nch_cap), dim3(64 * waves), shm, c->stream,
                      a);
   HIPCHK(c, hipGetLastError());
   prof_end(c, kKIterBA, pe);
@@ -560,11 +597,70 @@ d2_status launch_ba(d2_ctx* c, const d2k::Args<T>& a, int& nl) {
   return D2_OK;
 }
 
+// The launch sequence of one B-ADMM call (all clusters): issued eagerly or
+// captured once into a HIP graph and replayed.  It contains kernel launches
+// only.
+template <typename T>
+d2_status issue_barycenter(d2_ctx* c, const d2_badmm_params* p, int& nl) {
+  const int K = c->K, T_ = p->iters, tau = p->tau;
+  const int64_t ps = c->MP + 2;
+  const int64_t xs = (int64_t)c->MP * (c->d + 1);
+  d2k::Args<T> a = make_args<T>(c, p);
+  d2k::FinArgs f = make_fin(c, p);
+  double* rec[2] = {c->d_part, c->d_part + (int64_t)c->nch_cap * ps};
+  double* xrec[2] = {c->d_partx, c->d_partx + (int64_t)c->nch_cap * xs};
+  // support update after iteration n (0-based): (n + 1) % tau == 0
+  auto xupd = [&](int n) {
+    return !p->fixed_support && n < T_ && ((n + 1) % tau == 0);
+  };
+  d2_status s;
+  // rho from the cost at the initial support
+  a.part = rec[1];
+  f.part = rec[1];
+  if ((s = launch_aux<T>(c, a, d2k::kRho, nl))) return s;
+  if ((s = launch_fin(c, f, d2k::kFinRho, nl))) return s;
+  // A_0 from the initial plans and weights
+  a.part = rec[0];
+  a.xout = xupd(0) ? xrec[0] : nullptr;
+  if ((s = launch_aux<T>(c, a, d2k::kA0, nl))) return s;
+  for (int n = 0; n < T_; ++n) {
+    a.part_in = rec[n & 1];      // records of A_n -> w^{n+1}, F(n)
+    a.part = rec[(n + 1) & 1];   // records of A_{n+1}
+    a.trace = c->d_trace + (size_t)n * K;
+    // support records of A_n (support update after iteration n)
+    const bool xin = xupd(n);
+    a.xin = (xin && c->onfly) ? xrec[n & 1] : nullptr;
+    a.xout = xupd(n + 1) ? xrec[(n + 1) & 1] : nullptr;
+    a.recost = 0;
+    if (xin && !c->onfly) {
+      // large d: a per-cluster launch updates x, then the next phase A
+      // recomputes (and re-caches) the cost
+      f.xrec = xrec[n & 1];
+      if ((s = launch_fin(c, f, d2k::kFinX, nl))) return s;
+      a.recost = 1;
+    }
+    if (n == T_ - 1) {
+      if ((s = launch_aux<T>(c, a, d2k::kBF, nl))) return s;
+    } else {
+      if ((s = launch_ba<T>(c, a, nl))) return s;
+    }
+  }
+  return D2_OK;
+}
+
+std::vector<double> graph_key(const d2_ctx* c, const d2_badmm_params* p) {
+  return {(double)p->iters, (double)p->tau, (double)p->fixed_support,
+          (double)p->rule, p->eps, p->rho0, (double)c->waves,
+          (double)c->nch_cap, (double)c->MP, (double)c->R, (double)c->onfly,
+          (double)c->dt, (double)c->K};
+}
+
 template <typename T>
 d2_status run_barycenter(d2_ctx* c, const d2_badmm_params* p,
                          d2_badmm_stats* st) {
-  const int K = c->K, MP = c->MP, T_ = p->iters, tau = p->tau;
+  const int K = c->K, MP = c->MP, T_ = p->iters;
   if (T_ > c->trace_cap) {
+    drop_graph(c);
     dfree(c->d_trace);
     d2_status s = dalloc(c, (void**)&c->d_trace, sizeof(double) * T_ * K);
     if (s) return s;
@@ -572,51 +668,43 @@ d2_status run_barycenter(d2_ctx* c, const d2_badmm_params* p,
   }
   HIPCHK(c, hipMemsetAsync(c->d_trace, 0, sizeof(double) * T_ * K,
                            c->stream));
-  // both weight buffers start at the current weights (empty clusters keep
-  // them through the call)
-  HIPCHK(c, hipMemcpyAsync(c->d_wbuf, c->d_wc, sizeof(double) * K * MP,
-                           hipMemcpyDeviceToDevice, c->stream));
-  HIPCHK(c, hipMemcpyAsync(c->d_wbuf + K * MP, c->d_wc,
-                           sizeof(double) * K * MP, hipMemcpyDeviceToDevice,
-                           c->stream));
-  HIPCHK(c, hipEventRecord(c->ev0, c->stream));
   int nl = 0;
-  d2k::Args<T> a = make_args<T>(c, p);
-  d2k::FinArgs f = make_fin(c, p);
-  double* wb0 = c->d_wbuf;
-  double* wb1 = c->d_wbuf + K * MP;
-  auto wbuf = [&](int q) { return (q & 1) ? wb1 : wb0; };
+  bool graphed = false;
   d2_status s;
-  // rho from the cost at the initial support
-  if ((s = launch_aux<T>(c, a, d2k::kRho, nl))) return s;
-  if ((s = launch_fin(c, f, d2k::kFinRho, nl))) return s;
-  // A_0 from the initial plans -> w^1
-  a.w_in = wbuf(0);
-  f.w_out = wbuf(1);
-  f.trace = c->d_trace;
-  if ((s = launch_aux<T>(c, a, d2k::kA0, nl))) return s;
-  if ((s = launch_fin(c, f, d2k::kFinW, nl))) return s;
-  for (int n = 0; n < T_; ++n) {
-    const bool xupd = !p->fixed_support && ((n + 1) % tau == 0);
-    a.w_in = wbuf(n + 1);
-    f.w_out = wbuf(n + 2);
-    f.trace = c->d_trace + (size_t)(n + 1) * K;
-    if (n == T_ - 1) {
-      if ((s = launch_aux<T>(c, a, xupd ? d2k::kBX : d2k::kBF, nl))) return s;
-      if (xupd && (s = launch_fin(c, f, d2k::kFinX, nl))) return s;
-    } else if (xupd) {
-      if ((s = launch_aux<T>(c, a, d2k::kBX, nl))) return s;
-      if ((s = launch_fin(c, f, d2k::kFinX, nl))) return s;
-      if ((s = launch_aux<T>(c, a, d2k::kAP, nl))) return s;
-      if ((s = launch_fin(c, f, d2k::kFinW, nl))) return s;
-    } else {
-      if ((s = launch_ba<T>(c, a, nl))) return s;
-      if ((s = launch_fin(c, f, d2k::kFinW, nl))) return s;
+  // per-kernel event timing needs eager launches
+  const bool want_graph = c->use_graph && !c->prof;
+  if (want_graph) {
+    std::vector<double> key = graph_key(c, p);
+    if (!c->gexec || key != c->graph_key) {
+      drop_graph(c);
+      HIPCHK(c, hipStreamBeginCapture(c->stream,
+                                      hipStreamCaptureModeThreadLocal));
+      int cnt = 0;
+      s = issue_barycenter<T>(c, p, cnt);
+      hipGraph_t g = nullptr;
+      hipError_t e = hipStreamEndCapture(c->stream, &g);
+      if (s) {
+        if (g) (void)hipGraphDestroy(g);
+        return s;
+      }
+      if (e != hipSuccess)
+        return c->fail(D2_EDEVICE, std::string("hipStreamEndCapture: ") +
+                                       hipGetErrorString(e));
+      c->graph = g;
+      HIPCHK(c, hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0));
+      c->graph_key = key;
+      c->graph_launches = cnt;
     }
+    HIPCHK(c, hipEventRecord(c->ev0, c->stream));
+    HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
+    HIPCHK(c, hipEventRecord(c->ev1, c->stream));
+    nl = c->graph_launches;
+    graphed = true;
+  } else {
+    HIPCHK(c, hipEventRecord(c->ev0, c->stream));
+    if ((s = issue_barycenter<T>(c, p, nl))) return s;
+    HIPCHK(c, hipEventRecord(c->ev1, c->stream));
   }
-  HIPCHK(c, hipEventRecord(c->ev1, c->stream));
-  HIPCHK(c, hipMemcpyAsync(c->d_wc, wbuf(T_), sizeof(double) * K * MP,
-                           hipMemcpyDeviceToDevice, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   prof_collect(c);
   float ms = 0.f;
@@ -642,7 +730,7 @@ d2_status run_barycenter(d2_ctx* c, const d2_badmm_params* p,
     for (int q = 0; q < K; ++q) ne += c->h_ctab[q].y == 0;
     st->n_empty = ne;
     st->launches = nl;
-    st->graph = 0;
+    st->graph = graphed ? 1 : 0;
     st->ms = ms;
   }
   return D2_OK;
@@ -1021,9 +1109,11 @@ d2_status d2_support_update(d2_ctx* c) {
   int nl = 0;
   if (c->dt == D2_F64) {
     auto a = make_args<double>(c, nullptr);
+    a.xout = c->d_partx;
     s = launch_aux<double>(c, a, d2k::kXO, nl);
   } else {
     auto a = make_args<float>(c, nullptr);
+    a.xout = c->d_partx;
     s = launch_aux<float>(c, a, d2k::kXO, nl);
   }
   if (s) return s;
@@ -1087,7 +1177,7 @@ d2_status d2_plans_get(d2_ctx* c, int64_t k, double* P1, double* P2,
   HIPCHK(c, hipSetDevice(c->device));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   size_t cnt = (size_t)c->m * (c->h_off[k + 1] - c->h_off[k]);
-  size_t ofs = (size_t)c->m * c->h_off[k];
+  size_t ofs = (size_t)c->h_pofs[k];
   void* src[3] = {c->d_P1, c->d_P2, c->d_L};
   double* dst[3] = {P1, P2, L};
   for (int q = 0; q < 3; ++q) {
@@ -1130,6 +1220,13 @@ d2_status d2_kernel_stats(d2_ctx* c, d2_kernel_stat* out, int32_t cap,
   return D2_OK;
 }
 
+d2_status d2_set_graph(d2_ctx* c, int32_t on) {
+  if (!c) return D2_EINVAL;
+  c->use_graph = on != 0;
+  if (!c->use_graph) drop_graph(c);
+  return D2_OK;
+}
+
 d2_status d2_set_schedule(d2_ctx* c, int32_t chunk_instances,
                           int32_t waves_per_group) {
   if (!c) return D2_EINVAL;
@@ -1140,6 +1237,7 @@ d2_status d2_set_schedule(d2_ctx* c, int32_t chunk_instances,
     c->chunk_inst = chunk_instances;
     free_lists(c);
   }
+  if (c->waves != waves_per_group) drop_graph(c);
   c->waves = waves_per_group;
   return D2_OK;
 }

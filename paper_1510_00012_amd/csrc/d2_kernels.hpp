@@ -22,19 +22,23 @@
 // tile's loads are in flight together.
 //
 // A workgroup processes one "chunk": a run of instances of one cluster from
-// the cluster-sorted work list, and writes one double record per chunk
-// (weight-consensus sums, objective, support numerators, cost sums).  A
-// second small launch (k_fin, one workgroup per cluster) sums the records of
-// each cluster in chunk order and writes the cluster result.  Every
-// reduction has a fixed order, so runs are bitwise reproducible, and no
-// cross-workgroup synchronisation happens inside a kernel.
+// the cluster-sorted work list, and writes double records per chunk
+// (weight-consensus sums and objective; support-update numerators).  The
+// next launch's workgroups sum their cluster's records in a fixed chunk
+// order in a short prologue, so every workgroup of a cluster obtains the
+// same bits; no cross-workgroup synchronisation happens inside a kernel and
+// runs are bitwise reproducible.  Plan tiles start on 128-byte boundaries.
+//
+// Support update without an extra pass over the plans: Pi2 = Pi1~ w_i/r_i,
+// so x_i = sum_k sum_j Pi2_ij y_j / sum_k sum_j Pi2_ij
+//        = (sum_k u_i^(k)) / #{k : r_i^(k) > 0},  u_i^(k) = sum_j Pi1~_ij y_j / r_i
+// which phase A has in registers when it builds Pi1~ and r.
 //
 // Iteration schedule (carried state = Pi1 and Lambda between launches):
-//   A0       Pi2^0 (product or cached), Lambda = 0 -> Pi1^1, records for w^1
-//   BA (hot) [Pi2^{n+1}, Lambda^{n+1} from Pi1^{n+1}, Lambda^n, w^{n+1};
-//             then Pi1^{n+2}, records for w^{n+2}]   (one launch/iteration)
-//   BX / BF  phase B only: store Pi2, Lambda; support numerators (BX)
-//   AP       phase A from stored Pi2, Lambda (after a support update)
+//   A0       Pi2^0 (product or cached), Lambda = 0 -> Pi1^1, records of A_0
+//   BA (hot) prologue: w^{n+1} (and x after iteration n) from the records of
+//            A_n; B_n: Pi2^{n+1}, Lambda^{n+1}; A_{n+1}: Pi1^{n+2}, records
+//   BF       last launch: prologue, B_{T-1}, store Pi2 (the warm-start cache)
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -162,13 +166,11 @@ template <> struct Vec4<double> { using type = double4; };
 enum Mode : int {
   kRho = 0,  // cost at the initial support (stored if cached): cost sums
   kA0 = 1,   // phase A from Pi2^0 (product / cached), Lambda := 0
-  kAP = 2,   // phase A from stored Pi2 and Lambda; recompute (+store) cost
-  kBX = 3,   // phase B, store Pi2 and Lambda, support numerators
-  kBF = 4,   // phase B, store Pi2 and Lambda (last iteration, no x update)
-  kXO = 5,   // support numerators from stored Pi2 only
+  kBF = 4,   // phase B of the last iteration: store Pi2 and Lambda
+  kXO = 5,   // support records from the stored Pi2 only
 };
-// Finalisation modes.
-enum FinMode : int { kFinW = 0, kFinRho = 1, kFinX = 2 };
+// Finalisation modes (per-cluster launches).
+enum FinMode : int { kFinRho = 1, kFinX = 2 };
 
 struct Chunk {
   int32_t cluster, begin, end, pad;
@@ -176,37 +178,82 @@ struct Chunk {
 
 template <typename T> struct Args {
   const int64_t* off;   // N+1 instance offsets
+  const int64_t* pofs;  // N plan tile offsets (elements, 128-byte aligned)
   const T* X;           // n x xs supports (xs = 4 when d <= 4, zero padded)
   const T* W;           // n weights
   const int32_t* work;  // instance ids sorted by cluster
   const Chunk* chunks;  // per workgroup
+  const int* nch;       // number of chunks (the grid may be larger)
+  const int2* ctab;     // per cluster {first chunk, number of chunks}
+  const double* ninv;   // per cluster 1 / N_c
   T* P1;
   T* P2;
   T* L;
-  T* Cc;                // cost cache (m x n) or nullptr when computed on the fly
+  T* Cc;                // cost cache (plan layout) or nullptr (on the fly)
   const uint8_t* warm;  // per instance: start from cached Pi2
-  const double* xc;     // K x MP x d centroid support
-  const double* w_in;   // K x MP weights used by phase B / the product init
+  double* xc;           // K x MP x d centroid support
+  double* wc;           // K x MP centroid weights (initial / published)
   const double* rho;    // K
-  double* part;         // chunk records, stride ps
-  double* partx;        // chunk support numerators, stride MP*(d+1)
+  const double* part_in;  // weight records of the previous phase A
+  double* part;           // weight records written by this launch, stride ps
+  const double* xin;      // support records of the previous phase A or null
+  double* xout;           // support records of this launch's phase A or null
+  double* trace;          // K objective values of the previous phase A
   double eps;
-  int m, d, xs, rule, ps, nchunks;
+  int m, d, xs, rule, ps;
+  int recost;             // cached cost: recompute from xc and store
 };
 
 struct FinArgs {
   const int2* ctab;     // per cluster {first chunk, number of chunks}
-  const double* ninv;   // per cluster 1 / N_c
   const double* cinv;   // per cluster 1 / (m * sum_k m_k)
   const double* part;
-  const double* partx;
-  double* w_out;        // K x MP
+  const double* xrec;
   double* rho;          // K
   double* xc;           // K x MP x d
-  double* trace;        // K or nullptr
   double rho0;
-  int m, d, rule, ps;
+  int m, d, ps;
 };
+
+// fixed-order strided sum of double records, loads issued 8 at a time
+__device__ __forceinline__ double sum_strided(const double* base, int64_t st,
+                                              int q0, int qn, int step) {
+  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int q = q0;
+  for (; q + 7 * step < qn; q += 8 * step) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc[u] += base[(int64_t)(q + u * step) * st];
+  }
+  for (int u = 0; q < qn; q += step, ++u) acc[u] += base[(int64_t)q * st];
+  return ((acc[0] + acc[1]) + (acc[2] + acc[3])) +
+         ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+}
+
+// Sums columns [0, ncol) of a cluster's chunk records (stride `st`) into
+// out[] (LDS) in a fixed order; every workgroup that calls it with the same
+// arguments obtains the same bits.
+__device__ __forceinline__ void sum_cluster_records(const double* base,
+                                                    int64_t st, int nch,
+                                                    int ncol, double* red,
+                                                    double* out) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int groups = nt / ncol;
+  if (groups >= 2) {
+    const int col = tid % ncol, grp = tid / ncol;
+    if (grp < groups)
+      red[grp * ncol + col] = sum_strided(base + col, st, grp, nch, groups);
+    __syncthreads();
+    for (int q = tid; q < ncol; q += nt) {
+      double t = 0.0;
+      for (int gI = 0; gI < groups; ++gI) t += red[gI * ncol + q];
+      out[q] = t;
+    }
+  } else {
+    for (int q = tid; q < ncol; q += nt)
+      out[q] = sum_strided(base + q, st, 0, nch, 1);
+  }
+  __syncthreads();
+}
 
 // ---------------------------------------------------------------------------
 // tiles
@@ -223,7 +270,8 @@ template <typename T, int MP> struct Tile {
   int64_t o, base;
   int mk, nsl, i, g, ic;
   bool rowok;
-  __device__ __forceinline__ void setup(const int64_t* off, int m, int k) {
+  __device__ __forceinline__ void setup(const int64_t* off,
+                                        const int64_t* pofs, int m, int k) {
     const int lane = threadIdx.x & (kWave - 1);
     i = lane % MP;
     g = lane / MP;
@@ -232,7 +280,7 @@ template <typename T, int MP> struct Tile {
     o = off[k];
     mk = (int)(off[k + 1] - o);
     nsl = (mk + CPS - 1) / CPS;
-    base = (int64_t)m * o;
+    base = pofs ? pofs[k] : 0;
   }
   __device__ __forceinline__ int col(int r) const { return g + CPS * r; }
   __device__ __forceinline__ bool valid(int r) const {
@@ -291,6 +339,75 @@ __device__ __forceinline__ T cost4(const T (&xr)[4],
   return s;
 }
 
+// ---------------------------------------------------------------------------
+// prologue: cluster quantities from the previous launch's records
+// ---------------------------------------------------------------------------
+// Weights w^{n+1} (R1: normalised mean of w~^(k); R2: normalised square of
+// the mean of sqrt(w~^(k))).  The cluster's first chunk also publishes w and
+// the objective of the phase A that wrote the records.
+template <typename T, int MP>
+__device__ __forceinline__ void cluster_weights(const Args<T>& a, int c,
+                                                int2 ct, bool publish,
+                                                double* s_w) {
+  __shared__ double s_red[256];
+  __shared__ double s_out[MP + 1];
+  __shared__ double s_vs;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  sum_cluster_records(a.part_in + (int64_t)ct.x * a.ps, a.ps, ct.y, MP + 1,
+                      s_red, s_out);
+  const double ni = a.ninv[c];
+  for (int q = tid; q < MP; q += nt) {
+    double t = q < a.m ? s_out[q] * ni : 0.0;
+    s_w[q] = a.rule == 2 ? t * t : t;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double vs = 0.0;
+    for (int q = 0; q < MP; ++q) vs += s_w[q];
+    s_vs = vs;
+    if (publish && a.trace) a.trace[c] = s_out[MP] * ni;
+  }
+  __syncthreads();
+  for (int q = tid; q < MP; q += nt) {
+    s_w[q] = s_w[q] / s_vs;
+    if (publish) a.wc[c * MP + q] = s_w[q];
+  }
+  __syncthreads();
+}
+
+// Updated support (d <= 4) from support records: x_i = sum u / sum den;
+// a row no member carries mass on keeps its point.  Result in s_x[MP][4].
+template <typename T, int MP>
+__device__ __forceinline__ void cluster_support(const Args<T>& a, int c,
+                                                int2 ct, bool publish,
+                                                double* s_x) {
+  __shared__ double s_red[256];
+  __shared__ double s_out[MP * 5];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int d = a.d, ncol = MP * (d + 1);
+  sum_cluster_records(a.xin + (int64_t)ct.x * ncol, ncol, ct.y, ncol, s_red,
+                      s_out);
+  for (int q = tid; q < MP * 4; q += nt) {
+    const int ii = q / 4, t = q % 4;
+    double v = 0.0;
+    if (ii < a.m && t < d) {
+      const double den = s_out[ii * (d + 1) + d];
+      const int64_t xi = ((int64_t)c * MP + ii) * d + t;
+      v = den > 0.0 ? s_out[ii * (d + 1) + t] / den : a.xc[xi];
+    }
+    s_x[q] = v;
+  }
+  __syncthreads();
+  if (publish)
+    for (int q = tid; q < MP * d; q += nt) {
+      const int ii = q / d, t = q % d;
+      if (ii < a.m) a.xc[((int64_t)c * MP + ii) * d + t] = s_x[ii * 4 + t];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// phases of one tile
+// ---------------------------------------------------------------------------
 // Scales of one cluster: rho, a2 = log2(e)/rho.  Inactive lanes carry
 // zero plan, zero weight and a zero eps (el), so every product, column and
 // row sum below is exact without per-lane selects.
@@ -318,12 +435,13 @@ __device__ __forceinline__ void phase_b(const T (&el)[NS], T (&p)[NS],
 }
 
 // Phase A: in p = Pi2, l = Lambda, cost cs, instance weights wk; out
-// p = Pi1 (column KL projection).  Returns the row sum r_i of Pi1~ in rr and
-// adds <C, Pi1> to f.
+// p = Pi1 (column KL projection) and b = Pi1~.  Returns the row sum r_i of
+// Pi1~ in rr and adds <C, Pi1> to f.
 template <typename T, int MP, int NS>
 __device__ __forceinline__ void phase_a(const T (&el)[NS], T (&p)[NS],
                                         const T (&l)[NS], const T (&cs)[NS],
-                                        const T (&wk)[NS], T a2, T& rr, T& f) {
+                                        const T (&wk)[NS], T a2, T (&b)[NS],
+                                        T& rr, T& f) {
   T av[NS], s[NS];
 #pragma unroll
   for (int r = 0; r < NS; ++r) {
@@ -336,7 +454,8 @@ __device__ __forceinline__ void phase_a(const T (&el)[NS], T (&p)[NS],
   for (int r = 0; r < NS; ++r) {
     T p1 = av[r] * (wk[r] * rcp_sum(s[r]));
     f = fma(cs[r], p1, f);
-    rr += fma(p1, dexp2(l[r] * a2), el[r]);
+    b[r] = fma(p1, dexp2(l[r] * a2), el[r]);
+    rr += b[r];
     p[r] = p1;
   }
   rr = sum_row<MP>(rr);
@@ -368,15 +487,50 @@ __device__ __forceinline__ void write_w_record(double accw, double accf,
   }
 }
 
+// Support record of one tile: u_i,t = sum_j b_ij y_j,t / r_i for t < d and
+// the indicator r_i > 0, added (lanes < MP) to acc[MP][d+1] in LDS.
+template <typename T, int MP, int NS>
+__device__ __forceinline__ void add_support_terms(const Args<T>& a,
+                                                  const Tile<T, MP>& tl,
+                                                  const T (&b)[NS], T rr,
+                                                  double* acc) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int d = a.d;
+  const T ir = rcp_sum(rr);
+  for (int t = 0; t < d; ++t) {
+    T s = T(0);
+#pragma unroll
+    for (int r = 0; r < NS; ++r)
+      s = fma(b[r], a.X[(tl.o + tl.colc(r)) * a.xs + t], s);
+    s = sum_row<MP>(s);
+    if (lane < MP) acc[lane * (d + 1) + t] += (double)(s * ir);
+  }
+  if (lane < MP && rr > T(0)) acc[lane * (d + 1) + d] += 1.0;
+}
+
+// Sum the per-wave support accumulators into this chunk's record.
+__device__ __forceinline__ void write_x_record(const double* acc, int nrec,
+                                               double* xout, int ch) {
+  const int nwaves = blockDim.x / kWave;
+  __syncthreads();
+  for (int q = threadIdx.x; q < nrec; q += blockDim.x) {
+    double s = 0.0;
+    for (int wv = 0; wv < nwaves; ++wv) s += acc[(int64_t)wv * nrec + q];
+    xout[(int64_t)ch * nrec + q] = s;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Hot kernel: one launch per B-ADMM iteration (phase B of n, phase A of n+1)
 // ---------------------------------------------------------------------------
 template <typename T, int MP, int NS, bool ONFLY>
 __device__ __forceinline__ void ba_tile(const Args<T>& a, const Tile<T, MP>& tl,
-                                        const T (&xr)[4], T wi, T rho, T a2,
-                                        T eps, double& accw, double& accf) {
+                                        const T (&xr)[4], const double* xrow,
+                                        T wi, T rho, T a2, T eps,
+                                        double& accw, double& accf,
+                                        double* accx) {
   using V4 = typename Vec4<T>::type;
-  T p[NS], l[NS], cs[NS], wk[NS];
+  T p[NS], l[NS], cs[NS], wk[NS], el[NS], b[NS];
   bool v[NS];
 #pragma unroll
   for (int r = 0; r < NS; ++r) {
@@ -390,10 +544,10 @@ __device__ __forceinline__ void ba_tile(const Args<T>& a, const Tile<T, MP>& tl,
       const V4 y = reinterpret_cast<const V4*>(a.X)[tl.o + jc];
       cs[r] = cost4<T>(xr, y);
     } else {
-      cs[r] = a.Cc[e];
+      cs[r] = a.recost ? cost_generic<T>(xrow, a.X + (tl.o + jc) * a.xs, a.d)
+                       : a.Cc[e];
     }
   }
-  T el[NS];
 #pragma unroll
   for (int r = 0; r < NS; ++r) {
     p[r] = v[r] ? p[r] : T(0);
@@ -403,24 +557,33 @@ __device__ __forceinline__ void ba_tile(const Args<T>& a, const Tile<T, MP>& tl,
   }
   phase_b<T, MP, NS>(el, p, l, wi, rho, a2);
   T rr, f = T(0);
-  phase_a<T, MP, NS>(el, p, l, cs, wk, a2, rr, f);
+  phase_a<T, MP, NS>(el, p, l, cs, wk, a2, b, rr, f);
   accw += consensus_term<T, MP>(rr, tl.rowok, a.rule);
   accf += (double)f;
+  if (a.xout) add_support_terms<T, MP, NS>(a, tl, b, rr, accx);
 #pragma unroll
   for (int r = 0; r < NS; ++r)
     if (v[r]) {
       const int64_t e = tl.eidx(r, a.m);
       a.P1[e] = p[r];
       a.L[e] = l[r];
+      if constexpr (!ONFLY) {
+        if (a.recost) a.Cc[e] = cs[r];
+      }
     }
 }
 
 template <typename T, int MP, int R, bool ONFLY>
 __global__ void __launch_bounds__(256) k_iter_ba(Args<T> a) {
+  extern __shared__ double s_dyn[];  // [nwaves][MP][d+1] support terms
+  __shared__ double s_w[MP];
+  __shared__ double s_x[MP * 4];
   const int ch = blockIdx.x;
-  if (ch >= a.nchunks) return;
+  if (ch >= *a.nch) return;
   const Chunk cj = a.chunks[ch];
   const int c = cj.cluster;
+  const int2 ct = a.ctab[c];
+  cluster_weights<T, MP>(a, c, ct, ch == ct.x, s_w);
   const int wave = uni(threadIdx.x / kWave), nwaves = blockDim.x / kWave;
   const int lane = threadIdx.x & (kWave - 1);
   const int i = lane % MP;
@@ -428,26 +591,40 @@ __global__ void __launch_bounds__(256) k_iter_ba(Args<T> a) {
   const T rho = (T)a.rho[c];
   const T a2 = (T)(kLog2e / a.rho[c]);
   const T eps = (T)a.eps;
-  const T wi = rowok ? (T)a.w_in[c * MP + i] : T(0);
+  const T wi = rowok ? (T)s_w[i] : T(0);
+  const int nrec = MP * (a.d + 1);
+  double* accx = s_dyn + (int64_t)wave * nrec;
+  if (a.xout)
+    for (int q = lane; q < nrec; q += kWave) accx[q] = 0.0;
   T xr[4] = {T(0), T(0), T(0), T(0)};
   if constexpr (ONFLY) {
+    if (a.xin) {
+      cluster_support<T, MP>(a, c, ct, ch == ct.x, s_x);
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
-      if (t < a.d && rowok) xr[t] = (T)a.xc[((int64_t)c * MP + i) * a.d + t];
+      for (int t = 0; t < 4; ++t) xr[t] = (T)s_x[i * 4 + t];
+    } else {
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        if (t < a.d && rowok)
+          xr[t] = (T)a.xc[((int64_t)c * MP + i) * a.d + t];
+    }
   }
+  const double* xrow = a.xc + ((int64_t)c * MP + (rowok ? i : 0)) * a.d;
   double accw = 0.0, accf = 0.0;
   for (int pos = cj.begin + wave; pos < cj.end; pos += nwaves) {
     Tile<T, MP> tl;
-    tl.setup(a.off, a.m, uni(a.work[pos]));
+    tl.setup(a.off, a.pofs, a.m, uni(a.work[pos]));
     with_slots<R>(tl.nsl, [&]<int NS>() {
-      ba_tile<T, MP, NS, ONFLY>(a, tl, xr, wi, rho, a2, eps, accw, accf);
+      ba_tile<T, MP, NS, ONFLY>(a, tl, xr, xrow, wi, rho, a2, eps, accw,
+                                accf, accx);
     });
   }
   write_w_record<MP>(accw, accf, a.part, a.ps, ch);
+  if (a.xout) write_x_record(s_dyn, nrec, a.xout, ch);
 }
 
 // ---------------------------------------------------------------------------
-// Auxiliary kernel: cost sums / init phase A / phase-B variants / numerators
+// Auxiliary kernel: cost sums / first phase A / last phase B / support only
 // ---------------------------------------------------------------------------
 template <typename T, int MP, int NS>
 __device__ __forceinline__ void aux_tile(const Args<T>& a, const Tile<T, MP>& tl,
@@ -457,7 +634,7 @@ __device__ __forceinline__ void aux_tile(const Args<T>& a, const Tile<T, MP>& tl
                                          double* accx) {
   const int d = a.d;
   const int lane = threadIdx.x & (kWave - 1);
-  T p[NS], l[NS], cs[NS], wk[NS], el[NS];
+  T p[NS], l[NS], cs[NS], wk[NS], el[NS], b[NS];
   bool v[NS];
 #pragma unroll
   for (int r = 0; r < NS; ++r) {
@@ -478,30 +655,24 @@ __device__ __forceinline__ void aux_tile(const Args<T>& a, const Tile<T, MP>& tl
     accf += (double)s;  // lane partial, reduced over the wave at the end
     return;
   }
-  if (mode == kA0 || mode == kAP) {
-    const bool cached = (mode == kAP) || (a.warm && a.warm[k]);
+  if (mode == kA0) {
+    const bool cached = a.warm && a.warm[k];
 #pragma unroll
     for (int r = 0; r < NS; ++r) {
       const int64_t e = tl.eidx(r, a.m);
       const int jc = tl.colc(r);
       wk[r] = a.W[tl.o + jc];
-      T cv = cost_generic<T>(xrow, a.X + (tl.o + jc) * a.xs, d);
-      if (mode == kAP && a.Cc && v[r]) a.Cc[e] = cv;
-      cs[r] = (mode == kA0 && a.Cc) ? a.Cc[e] : cv;
-      if (mode == kAP) {
-        p[r] = a.P2[e];
-        l[r] = a.L[e];
-      } else {
-        p[r] = cached ? a.P2[e] : wi * wk[r];
-      }
+      cs[r] = a.Cc ? a.Cc[e]
+                   : cost_generic<T>(xrow, a.X + (tl.o + jc) * a.xs, d);
+      p[r] = cached ? a.P2[e] : wi * wk[r];
       p[r] = v[r] ? p[r] : T(0);
-      l[r] = v[r] ? l[r] : T(0);
       wk[r] = v[r] ? wk[r] : T(0);
     }
     T rr, f = T(0);
-    phase_a<T, MP, NS>(el, p, l, cs, wk, a2, rr, f);
+    phase_a<T, MP, NS>(el, p, l, cs, wk, a2, b, rr, f);
     accw += consensus_term<T, MP>(rr, tl.rowok, a.rule);
     accf += (double)f;
+    if (a.xout) add_support_terms<T, MP, NS>(a, tl, b, rr, accx);
 #pragma unroll
     for (int r = 0; r < NS; ++r)
       if (v[r]) {
@@ -511,20 +682,15 @@ __device__ __forceinline__ void aux_tile(const Args<T>& a, const Tile<T, MP>& tl
       }
     return;
   }
-  // phase-B modes and the support-only mode
+  if (mode == kBF) {
 #pragma unroll
-  for (int r = 0; r < NS; ++r) {
-    const int64_t e = tl.eidx(r, a.m);
-    if (mode == kXO) {
-      p[r] = a.P2[e];
-    } else {
+    for (int r = 0; r < NS; ++r) {
+      const int64_t e = tl.eidx(r, a.m);
       p[r] = a.P1[e];
       l[r] = a.L[e];
+      p[r] = v[r] ? p[r] : T(0);
+      l[r] = v[r] ? l[r] : T(0);
     }
-    p[r] = v[r] ? p[r] : T(0);
-    l[r] = v[r] ? l[r] : T(0);
-  }
-  if (mode != kXO) {
     phase_b<T, MP, NS>(el, p, l, wi, rho, a2);
 #pragma unroll
     for (int r = 0; r < NS; ++r)
@@ -533,55 +699,66 @@ __device__ __forceinline__ void aux_tile(const Args<T>& a, const Tile<T, MP>& tl
         a.P2[e] = p[r];
         a.L[e] = l[r];
       }
+    return;
   }
-  if (mode == kBX || mode == kXO) {
-    // numerators sum_j Pi2_ij y_j,t (t < d) and denominators sum_j Pi2_ij
-    for (int t = 0; t <= d; ++t) {
-      T s = T(0);
+  // kXO: support terms from the stored Pi2 (u = sum_j Pi2 y / sum_j Pi2)
 #pragma unroll
-      for (int r = 0; r < NS; ++r) {
-        T yv = t < d ? a.X[(tl.o + tl.colc(r)) * a.xs + t] : T(1);
-        s = fma(p[r], yv, s);
-      }
-      s = sum_row<MP>(s);
-      if (lane < MP) accx[lane * (d + 1) + t] += (double)s;
-    }
+  for (int r = 0; r < NS; ++r) {
+    const T pv = a.P2[tl.eidx(r, a.m)];
+    p[r] = v[r] ? pv : T(0);
   }
+  T rr = T(0);
+#pragma unroll
+  for (int r = 0; r < NS; ++r) rr += p[r];
+  rr = sum_row<MP>(rr);
+  add_support_terms<T, MP, NS>(a, tl, p, rr, accx);
+  (void)lane;
 }
 
 template <typename T, int MP, int R>
 __global__ void __launch_bounds__(256) k_aux(Args<T> a, int mode) {
-  extern __shared__ double s_dyn[];  // [nwaves][MP][d+1] support numerators
+  extern __shared__ double s_dyn[];  // [nwaves][MP][d+1] support terms
+  __shared__ double s_w[MP];
+  __shared__ double s_x[MP * 4];
   const int ch = blockIdx.x;
-  if (ch >= a.nchunks) return;
+  if (ch >= *a.nch) return;
   const Chunk cj = a.chunks[ch];
   const int c = cj.cluster;
+  const int2 ct = a.ctab[c];
+  if (mode == kBF) {
+    cluster_weights<T, MP>(a, c, ct, ch == ct.x, s_w);
+    // the support update after the last iteration (small d)
+    if (a.xin && a.d <= 4) cluster_support<T, MP>(a, c, ct, ch == ct.x, s_x);
+  } else if (mode == kA0) {
+    for (int q = threadIdx.x; q < MP; q += blockDim.x) s_w[q] = a.wc[c * MP + q];
+    __syncthreads();
+  }
   const int wave = uni(threadIdx.x / kWave), nwaves = blockDim.x / kWave;
   const int lane = threadIdx.x & (kWave - 1);
   const int i = lane % MP;
   const int d = a.d;
   const bool rowok = i < a.m;
-  const bool xnum = (mode == kBX || mode == kXO);
+  const bool xrecs = (mode == kXO) || (mode == kA0 && a.xout);
   const T eps = (T)a.eps;
   const double rhod = mode == kRho ? 1.0 : a.rho[c];
   const T rho = (T)rhod;
   const T a2 = (T)(kLog2e / rhod);
-  const T wi = rowok ? (T)a.w_in[c * MP + i] : T(0);
+  const T wi = (rowok && (mode == kBF || mode == kA0)) ? (T)s_w[i] : T(0);
   const double* xrow = a.xc + ((int64_t)c * MP + (rowok ? i : 0)) * d;
-  double* accx = s_dyn + (int64_t)wave * MP * (d + 1);
-  if (xnum)
-    for (int q = lane; q < MP * (d + 1); q += kWave) accx[q] = 0.0;
+  const int nrec = MP * (d + 1);
+  double* accx = s_dyn + (int64_t)wave * nrec;
+  if (xrecs)
+    for (int q = lane; q < nrec; q += kWave) accx[q] = 0.0;
   double accw = 0.0, accf = 0.0;
   for (int pos = cj.begin + wave; pos < cj.end; pos += nwaves) {
     Tile<T, MP> tl;
     const int k = uni(a.work[pos]);
-    tl.setup(a.off, a.m, k);
+    tl.setup(a.off, a.pofs, a.m, k);
     with_slots<R>(tl.nsl, [&]<int NS>() {
       aux_tile<T, MP, NS>(a, tl, k, mode, xrow, wi, rho, a2, eps, accw, accf,
                           accx);
     });
   }
-  const int nrec = MP * (d + 1);
   if (mode == kRho) {
     accf = sum_wave(accf);
     __shared__ double s_r[4];
@@ -592,93 +769,45 @@ __global__ void __launch_bounds__(256) k_aux(Args<T> a, int mode) {
       for (int q = 0; q < nwaves; ++q) s += s_r[q];
       a.part[(int64_t)ch * a.ps] = s;
     }
-  } else if (mode == kA0 || mode == kAP) {
+  } else if (mode == kA0) {
     write_w_record<MP>(accw, accf, a.part, a.ps, ch);
-  } else if (xnum) {
-    __syncthreads();
-    for (int q = threadIdx.x; q < nrec; q += blockDim.x) {
-      double s = 0.0;
-      for (int wv = 0; wv < nwaves; ++wv) s += s_dyn[(int64_t)wv * nrec + q];
-      a.partx[(int64_t)ch * nrec + q] = s;
-    }
   }
+  if (xrecs) write_x_record(s_dyn, nrec, a.xout, ch);
 }
 
 // ---------------------------------------------------------------------------
-// Per-cluster finalisation: sums the chunk records of a cluster in a fixed
-// order.  One workgroup per cluster; each thread owns one column and one
-// residue class of chunks, and issues its loads 8 at a time.
+// Per-cluster finalisation launches (one workgroup per cluster): rho from
+// the cost records; the support update from support records (used when the
+// support dimension is too large for the prologue).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double sum_strided(const double* base, int64_t st,
-                                              int q0, int qn, int step) {
-  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  int q = q0;
-  for (; q + 7 * step < qn; q += 8 * step) {
-#pragma unroll
-    for (int u = 0; u < 8; ++u) acc[u] += base[(int64_t)(q + u * step) * st];
-  }
-  for (int u = 0; q < qn; q += step, ++u) acc[u] += base[(int64_t)q * st];
-  return ((acc[0] + acc[1]) + (acc[2] + acc[3])) +
-         ((acc[4] + acc[5]) + (acc[6] + acc[7]));
-}
-
 template <int MP>
 __global__ void __launch_bounds__(256) k_fin(FinArgs f, int mode) {
   extern __shared__ double s_x[];  // kFinX: MP*(d+1) sums
   __shared__ double s_red[256];
-  __shared__ double s_out[MP + 1];
-  __shared__ double s_v[MP];
-  __shared__ double s_vs;
   const int c = blockIdx.x;
   const int2 ct = f.ctab[c];
   if (ct.y == 0) return;  // empty cluster: keep everything
   const int tid = threadIdx.x, nt = blockDim.x;
   if (mode == kFinX) {
     const int nrec = MP * (f.d + 1);
-    for (int q = tid; q < nrec; q += nt)
-      s_x[q] = sum_strided(f.partx + (int64_t)ct.x * nrec + q, nrec, 0, ct.y,
-                           1);
-    __syncthreads();
+    sum_cluster_records(f.xrec + (int64_t)ct.x * nrec, nrec, ct.y, nrec, s_red,
+                        s_x);
     for (int q = tid; q < MP * f.d; q += nt) {
       const int ii = q / f.d, t = q % f.d;
       const double den = s_x[ii * (f.d + 1) + f.d];
-      if (ii < f.m && den > 1e-300)
+      if (ii < f.m && den > 0.0)
         f.xc[((int64_t)c * MP + ii) * f.d + t] = s_x[ii * (f.d + 1) + t] / den;
     }
     return;
   }
-  const int ncol = mode == kFinRho ? 1 : MP + 1;
-  const int groups = nt / ncol;
-  const int col = tid % ncol, grp = tid / ncol;
-  if (grp < groups)
-    s_red[grp * ncol + col] =
-        sum_strided(f.part + (int64_t)ct.x * f.ps + col, f.ps, grp, ct.y,
-                    groups);
-  __syncthreads();
-  if (tid < ncol) {
-    double t = 0.0;
-    for (int gI = 0; gI < groups; ++gI) t += s_red[gI * ncol + tid];
-    s_out[tid] = t;
-  }
-  __syncthreads();
-  if (mode == kFinRho) {
-    if (tid == 0) f.rho[c] = f.rho0 * s_out[0] * f.cinv[c];
-    return;
-  }
-  const double ni = f.ninv[c];
-  if (tid < MP) {
-    double t = tid < f.m ? s_out[tid] * ni : 0.0;
-    s_v[tid] = f.rule == 2 ? t * t : t;
-  }
+  // kFinRho: sum of the cost records
+  s_red[tid] = sum_strided(f.part + (int64_t)ct.x * f.ps, f.ps, tid, ct.y, nt);
   __syncthreads();
   if (tid == 0) {
-    double vs = 0.0;
-    for (int q = 0; q < MP; ++q) vs += s_v[q];
-    s_vs = vs;
-    if (f.trace) f.trace[c] = s_out[MP] * ni;
+    double t = 0.0;
+    for (int gI = 0; gI < nt; ++gI) t += s_red[gI];
+    f.rho[c] = f.rho0 * t * f.cinv[c];
   }
-  __syncthreads();
-  if (tid < MP) f.w_out[c * MP + tid] = s_v[tid] / s_vs;
 }
 
 // ---------------------------------------------------------------------------
@@ -867,7 +996,7 @@ __global__ void __launch_bounds__(256) k_assign(AssignArgs<T> a) {
                     uni(threadIdx.x / kWave);
   if (k >= a.N) return;  // whole wavefront exits together
   Tile<T, MP> tl;
-  tl.setup(a.off, a.m, (int)k);
+  tl.setup(a.off, nullptr, a.m, (int)k);
   double bestv = 0.0;
   int bestc = -1, nevals = 0;
   with_slots<R>(tl.nsl, [&]<int NS>() {

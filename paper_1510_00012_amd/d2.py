@@ -28,7 +28,7 @@ EXPORTS = [
     "d2_labels_set", "d2_labels_get", "d2_assign", "d2_barycenter",
     "d2_support_update", "d2_cluster", "d2_objective", "d2_plans_get",
     "d2_sizes", "d2_set_profiling", "d2_kernel_stats", "d2_set_schedule",
-    "d2_assign_pairs",
+    "d2_assign_pairs", "d2_set_graph",
 ]
 
 
@@ -108,6 +108,7 @@ def load_library(path: str = LIB_PATH):
         "d2_set_profiling": ([_p, _i32], ctypes.c_int),
         "d2_set_schedule": ([_p, _i32, _i32], ctypes.c_int),
         "d2_assign_pairs": ([_p, _p, _p], ctypes.c_int),
+        "d2_set_graph": ([_p, _i32], ctypes.c_int),
         "d2_kernel_stats": ([_p, ctypes.POINTER(KernelStat), _i32, _p, _i32],
                             ctypes.c_int),
     }
@@ -268,6 +269,9 @@ class D2Context:
         self._chk(self.lib.d2_objective(self.h, _ptr(tr), int(iters),
                                         _ptr(rho)))
         return tr, rho
+
+    def set_graph(self, on=True):
+        self._chk(self.lib.d2_set_graph(self.h, int(bool(on))))
 
     def set_schedule(self, chunk_instances, waves_per_group):
         self._chk(self.lib.d2_set_schedule(self.h, int(chunk_instances),

@@ -291,3 +291,31 @@ def test_assignment_pruning_is_exact(d2, dtype):
     assert ev_b < tot
     assert np.array_equal(lab_a, lab_b)
     assert np.array_equal(best_a, best_b)
+
+
+def test_graph_replay_matches_eager(d2):
+    """The captured launch sequence replayed several times (labels, warm
+    start and centroids changing in between, eager assignment work between
+    replays) gives bitwise the results of host-issued launches."""
+    print("[graph_replay]", flush=True)
+    wl = make_workload("cfg2", N=5000)
+    mem = pick_init_members(wl["offsets"], 6, 16, 8)
+    with _ctx(d2, wl, "f32") as g, _ctx(d2, wl, "f32") as e:
+        e.set_graph(False)
+        g.centroids_init(mem, 16)
+        e.centroids_init(mem, 16)
+        for r in range(4):
+            lab_g, _, _ = g.assign(iters=60)
+            lab_e, _, _ = e.assign(iters=60)
+            assert np.array_equal(lab_g, lab_e)
+            init = d2.D2_INIT_PRODUCT if r == 0 else d2.D2_INIT_CACHED
+            sg = g.barycenter(iters=30, init=init)
+            se = e.barycenter(iters=30, init=init)
+            assert sg["graph"] == 1 and se["graph"] == 0
+            assert sg["launches"] == se["launches"]
+            Xg, Wg = g.centroids_get()
+            Xe, We = e.centroids_get()
+            assert np.array_equal(Xg, Xe) and np.array_equal(Wg, We), r
+            tg, _ = g.objective(30)
+            te, _ = e.objective(30)
+            assert np.array_equal(tg, te)
