@@ -138,6 +138,9 @@ def main():
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="run a plain device copy of this size first (counter "
                          "calibration for rocprofv3 --pmc runs)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="tune the launch schedule now instead of using the "
+                         "recorded one")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     args = ap.parse_args()
@@ -177,8 +180,21 @@ def main():
     ctx.load_instances(wl["offsets"], wl["X"], wl["W"])
     ctx.centroids_init(members, m)
 
+    sched = {}
+    key = d2.schedule_key(wl["offsets"], K, m, wl["X"].shape[1])
+    rec_sched = None if args.autotune else d2.tuned_schedule(key)
+    if rec_sched:
+        ctx.set_schedule(*rec_sched)
+        sched.update(chunk=rec_sched[0], waves=rec_sched[1], source="recorded")
+        log(f"[bench] recorded schedule {sched} for {key}")
+
     def step(first):
         ctx.assign(iters=T_assign)
+        if first and not sched:
+            # schedule autotuned on the first labels (no plan cache yet)
+            sched.update(ctx.autotune(iters=min(T, 20), tau=tau))
+            sched["source"] = "autotuned"
+            log(f"[bench] autotuned schedule {sched} for {key}")
         return ctx.barycenter(iters=T, tau=tau,
                               init=d2.D2_INIT_PRODUCT if first
                               else d2.D2_INIT_CACHED)
@@ -199,6 +215,7 @@ def main():
     # per-kernel durations: further rounds with every launch bracketed by
     # HIP events on the context's stream (kernels inside a replayed graph
     # cannot be bracketed individually)
+    ev, tot = ctx.assign_pairs()
     ctx.set_profiling(True)
     ctx.kernel_stats(reset=True)
     for _ in range(args.profile_rounds):
@@ -258,6 +275,10 @@ def main():
         "barycenter_inst_iter_per_s": N * T / (np.mean(bary_ms) / 1000.0),
         "barycenter_ms_mean": float(np.mean(bary_ms)),
         "barycenter_graph": graphed,
+        "schedule": {"chunk_instances": sched.get("chunk"),
+                     "waves_per_group": sched.get("waves"),
+                     "source": sched.get("source")},
+        "assign_pairs_evaluated_frac": ev / tot if tot else None,
         "kernel_timing": "HIP events around each launch on the context "
                          f"stream, {args.profile_rounds} host-issued rounds "
                          "after the timed rounds",

@@ -216,6 +216,17 @@ d2_status d2_set_graph(d2_ctx* ctx, int32_t on);
 d2_status d2_set_schedule(d2_ctx* ctx, int32_t chunk_instances,
                           int32_t waves_per_group);
 
+/* Autotuner: times d2_barycenter (`iters` iterations, product start) on the
+ * current labels for each candidate schedule -- instances per chunk in
+ * {16, 32, 64, 128, 256} x wavefronts per workgroup in {2, 4} -- keeps the
+ * fastest (set as the context's schedule) and reports it.  Centroids are
+ * restored afterwards; any warm-start plan cache is dropped, so call it
+ * before the first centroid update.  ms_best (may be NULL) gets the best
+ * device time. */
+d2_status d2_autotune(d2_ctx* ctx, const d2_badmm_params* p,
+                      int32_t* chunk_instances, int32_t* waves_per_group,
+                      double* ms_best);
+
 /* Sizes: N, n, d, K, m of the context (any pointer may be NULL). */
 d2_status d2_sizes(const d2_ctx* ctx, int64_t* N, int64_t* n, int32_t* d,
                    int32_t* K, int32_t* m);

@@ -101,7 +101,7 @@ struct d2_ctx {
   void* d_C = nullptr;
   bool onfly = true;
   // work lists
-  int chunk_inst = 32;  // instances per chunk
+  int chunk_inst = 64;  // instances per chunk
   int waves = 4;        // wavefronts per workgroup
   int nchunks = 0, nch_cap = 0;
   int32_t* d_work = nullptr;
@@ -1239,6 +1239,58 @@ d2_status d2_set_schedule(d2_ctx* c, int32_t chunk_instances,
   }
   if (c->waves != waves_per_group) drop_graph(c);
   c->waves = waves_per_group;
+  return D2_OK;
+}
+
+d2_status d2_autotune(d2_ctx* c, const d2_badmm_params* p,
+                      int32_t* chunk_out, int32_t* waves_out, double* ms_out) {
+  if (!c) return D2_EINVAL;
+  if (!c->N || !c->K || !c->have_labels)
+    return c->fail(D2_ESTATE, "need instances, centroids and labels");
+  if (!p) return c->fail(D2_EINVAL, "null parameters");
+  HIPCHK(c, hipSetDevice(c->device));
+  const size_t nx = (size_t)c->K * c->MP * c->d, nw = (size_t)c->K * c->MP;
+  std::vector<double> hx(nx), hw(nw);
+  HIPCHK(c, hipMemcpy(hx.data(), c->d_xc, nx * 8, hipMemcpyDeviceToHost));
+  HIPCHK(c, hipMemcpy(hw.data(), c->d_wc, nw * 8, hipMemcpyDeviceToHost));
+  d2_badmm_params q = *p;
+  q.init = D2_INIT_PRODUCT;
+  const bool prof = c->prof;
+  c->prof = false;
+  static const int kChunks[] = {16, 32, 64, 128, 256};
+  static const int kWaves[] = {2, 4};
+  double best = INFINITY;
+  int bc = c->chunk_inst, bw = c->waves;
+  d2_status s = D2_OK;
+  for (int ch : kChunks)
+    for (int wv : kWaves) {
+      if ((s = d2_set_schedule(c, ch, wv))) break;
+      double tmin = INFINITY;
+      for (int rep = 0; rep < 2 && !s; ++rep) {  // first call captures
+        d2_badmm_stats st;
+        HIPCHK(c, hipMemcpy(c->d_xc, hx.data(), nx * 8,
+                            hipMemcpyHostToDevice));
+        HIPCHK(c, hipMemcpy(c->d_wc, hw.data(), nw * 8,
+                            hipMemcpyHostToDevice));
+        if ((s = d2_barycenter(c, &q, &st))) break;
+        if (rep > 0) tmin = std::min(tmin, st.ms);
+      }
+      if (s) break;
+      if (tmin < best) {
+        best = tmin;
+        bc = ch;
+        bw = wv;
+      }
+    }
+  c->prof = prof;
+  HIPCHK(c, hipMemcpy(c->d_xc, hx.data(), nx * 8, hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->d_wc, hw.data(), nw * 8, hipMemcpyHostToDevice));
+  c->have_cache = false;
+  if (s) return s;
+  if ((s = d2_set_schedule(c, bc, bw))) return s;
+  if (chunk_out) *chunk_out = bc;
+  if (waves_out) *waves_out = bw;
+  if (ms_out) *ms_out = best;
   return D2_OK;
 }
 

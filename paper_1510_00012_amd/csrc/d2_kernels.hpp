@@ -272,15 +272,20 @@ template <typename T, int MP> struct Tile {
   bool rowok;
   __device__ __forceinline__ void setup(const int64_t* off,
                                         const int64_t* pofs, int m, int k) {
+    set(m, off[k], off[k + 1], pofs ? pofs[k] : 0);
+  }
+  // from instance offsets o0 .. o1 and plan offset pb (all uniform)
+  __device__ __forceinline__ void set(int m, int64_t o0, int64_t o1,
+                                      int64_t pb) {
     const int lane = threadIdx.x & (kWave - 1);
     i = lane % MP;
     g = lane / MP;
     rowok = i < m;
     ic = rowok ? i : 0;
-    o = off[k];
-    mk = (int)(off[k + 1] - o);
+    o = o0;
+    mk = (int)(o1 - o0);
     nsl = (mk + CPS - 1) / CPS;
-    base = pofs ? pofs[k] : 0;
+    base = pb;
   }
   __device__ __forceinline__ int col(int r) const { return g + CPS * r; }
   __device__ __forceinline__ bool valid(int r) const {
@@ -611,9 +616,26 @@ __global__ void __launch_bounds__(256) k_iter_ba(Args<T> a) {
   }
   const double* xrow = a.xc + ((int64_t)c * MP + (rowok ? i : 0)) * a.d;
   double accw = 0.0, accf = 0.0;
-  for (int pos = cj.begin + wave; pos < cj.end; pos += nwaves) {
+  // the next tile's offsets (a chain of dependent scalar loads) are fetched
+  // while the current tile is loaded and computed
+  int pos = cj.begin + wave;
+  int64_t o0 = 0, o1 = 0, pb = 0;
+  if (pos < cj.end) {
+    const int k = uni(a.work[pos]);
+    o0 = a.off[k];
+    o1 = a.off[k + 1];
+    pb = a.pofs[k];
+  }
+  for (; pos < cj.end; pos += nwaves) {
     Tile<T, MP> tl;
-    tl.setup(a.off, a.pofs, a.m, uni(a.work[pos]));
+    tl.set(a.m, o0, o1, pb);
+    const int nxt = pos + nwaves;
+    if (nxt < cj.end) {
+      const int k = uni(a.work[nxt]);
+      o0 = a.off[k];
+      o1 = a.off[k + 1];
+      pb = a.pofs[k];
+    }
     with_slots<R>(tl.nsl, [&]<int NS>() {
       ba_tile<T, MP, NS, ONFLY>(a, tl, xr, xrow, wi, rho, a2, eps, accw,
                                 accf, accx);

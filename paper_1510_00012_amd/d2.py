@@ -28,7 +28,7 @@ EXPORTS = [
     "d2_labels_set", "d2_labels_get", "d2_assign", "d2_barycenter",
     "d2_support_update", "d2_cluster", "d2_objective", "d2_plans_get",
     "d2_sizes", "d2_set_profiling", "d2_kernel_stats", "d2_set_schedule",
-    "d2_assign_pairs", "d2_set_graph",
+    "d2_assign_pairs", "d2_set_graph", "d2_autotune",
 ]
 
 
@@ -109,6 +109,8 @@ def load_library(path: str = LIB_PATH):
         "d2_set_schedule": ([_p, _i32, _i32], ctypes.c_int),
         "d2_assign_pairs": ([_p, _p, _p], ctypes.c_int),
         "d2_set_graph": ([_p, _i32], ctypes.c_int),
+        "d2_autotune": ([_p, ctypes.POINTER(BadmmParams), _p, _p, _p],
+                        ctypes.c_int),
         "d2_kernel_stats": ([_p, ctypes.POINTER(KernelStat), _i32, _p, _i32],
                             ctypes.c_int),
     }
@@ -136,6 +138,25 @@ def badmm_params(iters=100, tau=10, rho0=2.0, eps=1e-16, rule=1,
 
 def ot_params(iters=100, rho0=2.0, eps=1e-16, prune=True):
     return OtParams(rho0=rho0, eps=eps, iters=iters, prune=int(bool(prune)))
+
+
+SCHEDULES = os.path.join(_HERE, "schedules.json")
+
+
+def schedule_key(offsets, K, m, d, dtype="f32", arch="gfx950"):
+    mk = np.diff(np.asarray(offsets))
+    return f"{arch}|{dtype}|{len(mk)}|{K}|{m}|{d}|{int(mk.max())}"
+
+
+def tuned_schedule(key):
+    """(chunk, waves) recorded for a workload signature, or None."""
+    import json
+    try:
+        tab = json.load(open(SCHEDULES))
+    except OSError:
+        return None
+    ent = tab.get(key)
+    return None if ent is None else (int(ent["chunk"]), int(ent["waves"]))
 
 
 class D2Context:
@@ -269,6 +290,15 @@ class D2Context:
         self._chk(self.lib.d2_objective(self.h, _ptr(tr), int(iters),
                                         _ptr(rho)))
         return tr, rho
+
+    def autotune(self, iters=20, tau=10, rho0=2.0, eps=1e-16, rule=1):
+        """Pick the fastest (chunk, waves) schedule on the current labels."""
+        p = badmm_params(iters, tau, rho0, eps, rule, D2_INIT_PRODUCT)
+        ch, wv, ms = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_double(0)
+        self._chk(self.lib.d2_autotune(self.h, ctypes.byref(p),
+                                       ctypes.byref(ch), ctypes.byref(wv),
+                                       ctypes.byref(ms)))
+        return {"chunk": ch.value, "waves": wv.value, "ms": ms.value}
 
     def set_graph(self, on=True):
         self._chk(self.lib.d2_set_graph(self.h, int(bool(on))))

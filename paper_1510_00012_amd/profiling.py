@@ -1,0 +1,110 @@
+"""Summarise rocprofv3 output into the short text records kept in profiles/.
+
+Usage (after the rocprofv3 runs, on any machine):
+  python -m paper_1510_00012_amd.profiling trace  <kernel_stats.csv> <out.md> <cmd>
+  python -m paper_1510_00012_amd.profiling traffic <fetch_counter.csv> \
+      <write_counter.csv> <kernel-substring> <workload> <copy_mib> <out.json> <cmd>
+
+`traffic` scales the per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of the
+kernel by the factor that makes the same counters match a plain device copy
+of known size recorded in the same run (the bench's --copy-mib leg), and
+records the hash of the kernel sources so that a stale record is ignored.
+"""
+from __future__ import annotations
+
+import csv
+import hashlib
+import json
+import os
+import sys
+from collections import defaultdict
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("d2_kernels.hpp", "d2_api.hip"):
+        with open(os.path.join(HERE, "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def trace_summary(stats_csv, out_md, cmd):
+    rows = list(csv.DictReader(open(stats_csv)))
+    lines = [
+        "# rocprofv3 kernel-trace summary",
+        "",
+        f"Command: `{cmd}`",
+        "",
+        f"Kernel source hash: `{kernel_source_hash()}`",
+        "",
+        "| kernel | calls | avg us | min us | max us | total ms | % |",
+        "|---|---|---|---|---|---|---|",
+    ]
+    for r in rows:
+        lines.append(
+            f"| `{r['Name'][:90]}` | {r['Calls']} | "
+            f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['MinNs']) / 1e3:.2f} | "
+            f"{float(r['MaxNs']) / 1e3:.2f} | "
+            f"{float(r['TotalDurationNs']) / 1e6:.3f} | {r['Percentage']} |")
+    open(out_md, "w").write("\n".join(lines) + "\n")
+
+
+def _per_kernel(counter_csv, counter):
+    agg = defaultdict(list)
+    for r in csv.DictReader(open(counter_csv)):
+        if r["Counter_Name"] == counter:
+            agg[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+    return agg
+
+
+def traffic(fetch_csv, write_csv, kernel_sub, workload, copy_mib, out_json,
+            cmd):
+    copy_kib = float(copy_mib) * 1024.0
+    fetch = _per_kernel(fetch_csv, "FETCH_SIZE")
+    write = _per_kernel(write_csv, "WRITE_SIZE")
+
+    def copy_value(agg):
+        # the largest dispatch of the runtime copy is the calibration copy
+        vals = [v for k, vs in agg.items() if "copyBuffer" in k or "copy" in k
+                for v in vs]
+        return max(vals) if vals else None
+
+    cf, cw = copy_value(fetch), copy_value(write)
+    sf = copy_kib / cf if cf else None
+    sw = copy_kib / cw if cw else None
+
+    def kern(agg):
+        vals = [v for k, vs in agg.items() if kernel_sub in k for v in vs]
+        return sum(vals) / len(vals) if vals else None
+
+    kf, kw = kern(fetch), kern(write)
+    rec = {
+        "kernel": kernel_sub,
+        "workload": workload,
+        "command": cmd,
+        "kernel_source_hash": kernel_source_hash(),
+        "fetch_kib_per_dispatch_raw": kf,
+        "write_kib_per_dispatch_raw": kw,
+        "copy_probe_mib": float(copy_mib),
+        "copy_fetch_kib_raw": cf,
+        "copy_write_kib_raw": cw,
+        "fetch_scale": sf,
+        "write_scale": sw,
+        "hbm_bytes_per_launch": (kf * sf + kw * sw) * 1024.0
+        if None not in (kf, kw, sf, sw) else None,
+        "read_bytes_per_launch": kf * sf * 1024.0 if kf and sf else None,
+        "write_bytes_per_launch": kw * sw * 1024.0 if kw and sw else None,
+    }
+    json.dump(rec, open(out_json, "w"), indent=1)
+    return rec
+
+
+if __name__ == "__main__":
+    if sys.argv[1] == "trace":
+        trace_summary(sys.argv[2], sys.argv[3], sys.argv[4])
+    elif sys.argv[1] == "traffic":
+        print(json.dumps(traffic(*sys.argv[2:9]), indent=1))
+    else:
+        raise SystemExit(__doc__)

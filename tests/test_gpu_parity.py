@@ -319,3 +319,29 @@ def test_graph_replay_matches_eager(d2):
             tg, _ = g.objective(30)
             te, _ = e.objective(30)
             assert np.array_equal(tg, te)
+
+
+def test_autotune_then_parity(d2):
+    """The autotuner restores the centroids, picks a valid schedule, and the
+    tuned barycenter still matches the oracle."""
+    print("[autotune]", flush=True)
+    wl = make_workload("cfg2", N=6000)
+    mem = pick_init_members(wl["offsets"], 4, 16, 12)
+    Xc, Wc = oracle.init_centroids(wl, mem, 16)
+    lab, _, _ = oracle.assign(wl, Xc, Wc, T=40)
+    _, _, tr, _, _ = oracle_barycenters(wl, lab, Xc, Wc, T=40)
+    with _ctx(d2, wl, "f32") as ctx:
+        ctx.centroids_set(Xc, Wc)
+        ctx.labels_set(lab)
+        sch = ctx.autotune(iters=10)
+        assert sch["chunk"] in (16, 32, 64, 128, 256)
+        assert sch["waves"] in (2, 4) and sch["ms"] > 0
+        X0, W0 = ctx.centroids_get()
+        assert np.array_equal(X0, Xc)
+        np.testing.assert_allclose(W0, Wc / Wc.sum(1, keepdims=True),
+                                   atol=1e-16)
+        ctx.barycenter(iters=40, init=d2.D2_INIT_CACHED)
+        g_tr, _ = ctx.objective(40)
+        for c in range(4):
+            if tr[c] is not None:
+                assert _rel(g_tr[:, c], tr[c]) < 1e-5
