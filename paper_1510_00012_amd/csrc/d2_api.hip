@@ -74,7 +74,7 @@ struct d2_ctx {
   std::string err;
   // instances
   int64_t N = 0, n = 0;
-  int d = 0, xs = 0, mk_max = 0;  // xs: device row stride of X (4 if d<=4)
+  int d = 0, xs = 0, mk_max = 0;  // xs: row stride of X, d rounded up to 4
   std::vector<int64_t> h_off;
   std::vector<int64_t> h_pofs;  // plan tile offsets (128-byte aligned), N+1
   int64_t* d_off = nullptr;
@@ -93,6 +93,9 @@ struct d2_ctx {
   int32_t* d_labels = nullptr;
   double* d_best = nullptr;
   unsigned long long* d_evals = nullptr;
+  void* d_cmu = nullptr;   // K x d centroid means (device dtype)
+  void* d_crad = nullptr;  // K centroid support radii
+  void* d_xct = nullptr;   // K x MP x xs centroid supports (device dtype)
   int64_t last_evals = 0, last_pairs = 0;
   // plans
   void* d_P1 = nullptr;
@@ -205,6 +208,9 @@ void free_lists(d2_ctx* c) {
 
 void free_centroids(d2_ctx* c) {
   drop_graph(c);
+  dfree(c->d_cmu);
+  dfree(c->d_crad);
+  dfree(c->d_xct);
   dfree(c->d_xc);
   dfree(c->d_wc);
   dfree(c->d_rho);
@@ -742,6 +748,55 @@ int slots_for(const d2_ctx* c) {
   return 1 << ilog2(std::max(1, need));
 }
 
+// Per-centroid mean (weights of the centroid) and support radius around it,
+// for the cheap assignment lower bound; the radius is rounded up slightly.
+template <typename T>
+d2_status centroid_stats(d2_ctx* c) {
+  const int K = c->K, m = c->m, MP = c->MP, d = c->d;
+  std::vector<double> hx((size_t)K * MP * d), hw((size_t)K * MP);
+  HIPCHK(c, hipMemcpy(hx.data(), c->d_xc, hx.size() * 8,
+                      hipMemcpyDeviceToHost));
+  HIPCHK(c, hipMemcpy(hw.data(), c->d_wc, hw.size() * 8,
+                      hipMemcpyDeviceToHost));
+  std::vector<T> mu((size_t)K * d), rad(K);
+  std::vector<T> xt((size_t)K * MP * c->xs, T(0));
+  for (size_t q = 0; q < (size_t)K * MP; ++q)
+    for (int t = 0; t < d; ++t) xt[q * c->xs + t] = (T)hx[q * d + t];
+  for (int q = 0; q < K; ++q) {
+    std::vector<double> mq(d, 0.0);
+    double ws = 0.0;
+    for (int i = 0; i < m; ++i) ws += hw[(size_t)q * MP + i];
+    for (int i = 0; i < m; ++i)
+      for (int t = 0; t < d; ++t)
+        mq[t] += hw[(size_t)q * MP + i] * hx[((size_t)q * MP + i) * d + t] /
+                 (ws > 0 ? ws : 1.0);
+    double rmax = 0.0;
+    for (int i = 0; i < m; ++i) {
+      double s = 0.0;
+      for (int t = 0; t < d; ++t) {
+        double df = hx[((size_t)q * MP + i) * d + t] - mq[t];
+        s += df * df;
+      }
+      rmax = std::max(rmax, std::sqrt(s));
+    }
+    for (int t = 0; t < d; ++t) mu[(size_t)q * d + t] = (T)mq[t];
+    rad[q] = (T)(rmax * (1.0 + 1e-6) + 1e-30);
+  }
+  if (!c->d_cmu) {
+    d2_status s;
+    if ((s = dalloc(c, &c->d_cmu, sizeof(T) * (size_t)K * d))) return s;
+    if ((s = dalloc(c, &c->d_crad, sizeof(T) * (size_t)K))) return s;
+    if ((s = dalloc(c, &c->d_xct, sizeof(T) * xt.size()))) return s;
+  }
+  HIPCHK(c, hipMemcpy(c->d_xct, xt.data(), sizeof(T) * xt.size(),
+                      hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->d_cmu, mu.data(), sizeof(T) * mu.size(),
+                      hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->d_crad, rad.data(), sizeof(T) * rad.size(),
+                      hipMemcpyHostToDevice));
+  return D2_OK;
+}
+
 template <typename T>
 d2_status run_assign(d2_ctx* c, const d2_ot_params* p, float* ms_out) {
   const auto& kt = kern<T>();
@@ -757,6 +812,14 @@ d2_status run_assign(d2_ctx* c, const d2_ot_params* p, float* ms_out) {
   a.best = c->d_best;
   a.evaluated = c->d_evals;
   a.prune = p->prune ? 1 : 0;
+  a.prev_valid = c->have_labels ? 1 : 0;
+  {
+    d2_status s = centroid_stats<T>(c);
+    if (s) return s;
+  }
+  a.cmu = (const T*)c->d_cmu;
+  a.crad = (const T*)c->d_crad;
+  a.xct = (const T*)c->d_xct;
   a.N = c->N;
   a.rho0 = p->rho0;
   a.eps = p->eps;
@@ -771,8 +834,8 @@ d2_status run_assign(d2_ctx* c, const d2_ot_params* p, float* ms_out) {
                            c->stream));
   HIPCHK(c, hipEventRecord(c->ev0, c->stream));
   hipEvent_t pe = prof_begin(c);
-  hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(64 * wpb), 0, c->stream,
-                     a);
+  hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(64 * wpb),
+                     sizeof(T) * wpb * c->d, c->stream, a);
   HIPCHK(c, hipGetLastError());
   prof_end(c, kKAssign, pe);
   HIPCHK(c, hipEventRecord(c->ev1, c->stream));
@@ -897,7 +960,7 @@ d2_status d2_load_instances(d2_ctx* c, int64_t N, int32_t d,
   c->N = N;
   c->n = n;
   c->d = d;
-  c->xs = d <= 4 ? 4 : d;
+  c->xs = (d + 3) / 4 * 4;  // zero-padded stride, a multiple of 4
   c->mk_max = mkmax;
   c->h_off.assign(offsets, offsets + N + 1);
   d2_status s;

@@ -842,12 +842,15 @@ template <typename T> struct AssignArgs {
   const T* W;
   const double* xc;  // K x MP x d
   const double* wc;  // K x MP
-  int32_t* labels;
+  int32_t* labels;      // out; with prev_valid also the previous labels
   double* best;
   unsigned long long* evaluated;  // pairs run through the iterations
+  const T* cmu;         // K x d weighted mean of each centroid's support
+  const T* crad;        // K  radius of the support around that mean
+  const T* xct;         // K x MP x xs centroid supports in the device dtype
   int64_t N;
   double rho0, eps;
-  int m, d, xs, K, iters, prune;
+  int m, d, xs, K, iters, prune, prev_valid;
 };
 
 // Any coupling whose column sums are the instance weights w_j (as Pi1's are,
@@ -879,17 +882,36 @@ __device__ __forceinline__ double cost_lower_bound(const T (&cs)[NS],
   return sum_wave(lb);
 }
 
+// Costs of one (instance, centroid) tile with 4-wide loads: supports and
+// centroid rows share the zero-padded stride xs (a multiple of 4).
 template <typename T, int MP, int NS>
 __device__ __forceinline__ void pair_costs(const AssignArgs<T>& a,
                                            const Tile<T, MP>& tl, int c,
                                            const bool (&v)[NS],
                                            const int (&jc)[NS], T (&cs)[NS]) {
-  const double* xrow = a.xc + ((int64_t)c * MP + tl.ic) * a.d;
+  using V4 = typename Vec4<T>::type;
+  const V4* xrow = reinterpret_cast<const V4*>(
+      a.xct + ((int64_t)c * MP + tl.ic) * a.xs);
 #pragma unroll
-  for (int r = 0; r < NS; ++r) {
-    T cv = cost_generic<T>(xrow, a.X + (tl.o + jc[r]) * a.xs, a.d);
-    cs[r] = v[r] ? cv : T(0);
+  for (int r = 0; r < NS; ++r) cs[r] = T(0);
+  for (int t4 = 0; t4 < a.xs / 4; ++t4) {
+    const V4 xv = xrow[t4];
+#pragma unroll
+    for (int r = 0; r < NS; ++r) {
+      const V4 y =
+          reinterpret_cast<const V4*>(a.X + (tl.o + jc[r]) * a.xs)[t4];
+      T df = xv.x - y.x;
+      cs[r] = fma(df, df, cs[r]);
+      df = xv.y - y.y;
+      cs[r] = fma(df, df, cs[r]);
+      df = xv.z - y.z;
+      cs[r] = fma(df, df, cs[r]);
+      df = xv.w - y.w;
+      cs[r] = fma(df, df, cs[r]);
+    }
   }
+#pragma unroll
+  for (int r = 0; r < NS; ++r) cs[r] = v[r] ? cs[r] : T(0);
 }
 
 // B-ADMM transport value <C, Pi1> of one (instance, centroid) pair after
@@ -952,10 +974,11 @@ __device__ __forceinline__ double pair_value(const AssignArgs<T>& a,
 
 template <typename T, int MP, int NS>
 __device__ __forceinline__ void assign_tile(const AssignArgs<T>& a,
-                                            const Tile<T, MP>& tl,
-                                            double& bestv, int& bestc,
-                                            int& nevals) {
+                                            const Tile<T, MP>& tl, T* smu,
+                                            int prev, double& bestv,
+                                            int& bestc, int& nevals) {
   const T eps = (T)a.eps;
+  const int d = a.d;
   T wk[NS], el[NS], cs[NS];
   bool v[NS];
   int jc[NS];
@@ -979,29 +1002,75 @@ __device__ __forceinline__ void assign_tile(const AssignArgs<T>& a,
     }
     return;
   }
-  // 1) the centroid with the smallest lower bound is evaluated first
-  int c0 = 0;
-  double lb0 = 0.0;
-  for (int c = 0; c < a.K; ++c) {
-    pair_costs<T, MP, NS>(a, tl, c, v, jc, cs);
-    const double lb = cost_lower_bound<T, MP, NS>(cs, v, wk, tl.i);
-    if (c == 0 || lb < lb0) {
-      lb0 = lb;
-      c0 = c;
+  // Two exact lower bounds of the distance (section on pruning):
+  //   full:  sum_j w_j min_i C_ij                       (m x m_k x d work)
+  //   cheap: sum_j w_j max(0, |dist(mu_P, mu_c) - |y_j - mu_P|| - rad_c)^2
+  // from the triangle inequality around the centroid mean mu_c (support
+  // radius rad_c) and the instance mean mu_P; O(d + m_k) work.  A small
+  // relative slack keeps the cheap bound below the true one under FP32
+  // rounding.  Dimensions are split over the MP lanes of a column group.
+  for (int t = tl.i; t < d; t += MP) {
+    T sm = T(0);
+#pragma unroll
+    for (int r = 0; r < NS; ++r)
+      sm = fma(wk[r], a.X[(tl.o + jc[r]) * a.xs + t], sm);
+    sm = sum_row<MP>(sm);
+    if (tl.g == 0) smu[t] = sm;
+  }
+  __builtin_amdgcn_wave_barrier();
+  T rj[NS];
+#pragma unroll
+  for (int r = 0; r < NS; ++r) {
+    T sq = T(0);
+    for (int t = tl.i; t < d; t += MP) {
+      const T df = a.X[(tl.o + jc[r]) * a.xs + t] - smu[t];
+      sq = fma(df, df, sq);
+    }
+    rj[r] = dsqrt(sum_col<MP>(sq));
+  }
+  auto cheap_lb = [&](int c) -> double {
+    T sq = T(0);
+    for (int t = tl.i; t < d; t += MP) {
+      const T df = smu[t] - a.cmu[(int64_t)c * d + t];
+      sq = fma(df, df, sq);
+    }
+    const T dl = dsqrt(sum_col<MP>(sq));
+    const T rad = a.crad[c];
+    T acc = T(0);
+#pragma unroll
+    for (int r = 0; r < NS; ++r) {
+      T gap = fabs(dl - rj[r]) - rad - T(1e-5) * (dl + rj[r] + rad);
+      gap = gap > T(0) ? gap : T(0);
+      acc = fma(wk[r] * gap, gap, acc);
+    }
+    return sum_wave((double)(tl.i == 0 ? acc : T(0)));
+  };
+  // 1) first candidate: the previous label, else the smallest cheap bound
+  int c0 = prev;
+  if (c0 < 0 || c0 >= a.K) {
+    double lb0 = 0.0;
+    c0 = 0;
+    for (int c = 0; c < a.K; ++c) {
+      const double lb = cheap_lb(c);
+      if (c == 0 || lb < lb0) {
+        lb0 = lb;
+        c0 = c;
+      }
     }
   }
   pair_costs<T, MP, NS>(a, tl, c0, v, jc, cs);
   bestv = pair_value<T, MP, NS>(a, tl, c0, cs, wk, el, v);
   bestc = c0;
   ++nevals;
-  // 2) every other centroid unless its bound clears the best value by a
-  // margin far above FP32 rounding of the column sums (so a skipped
-  // centroid can never be the argmin; ties go to the lowest index)
+  // 2) every other centroid unless a bound clears the best value by a
+  // margin far above FP32 rounding of the column sums, so a skipped
+  // centroid can never be the argmin (ties go to the lowest index)
   for (int c = 0; c < a.K; ++c) {
     if (c == c0) continue;
+    const double cut = bestv * (1.0 + 1e-4);
+    if (cheap_lb(c) > cut) continue;
     pair_costs<T, MP, NS>(a, tl, c, v, jc, cs);
-    const double lb = cost_lower_bound<T, MP, NS>(cs, v, wk, tl.i);
-    if (lb > bestv * (1.0 + 1e-4)) continue;
+    if (cost_lower_bound<T, MP, NS>(cs, v, wk, tl.i) > cut) continue;
     const double val = pair_value<T, MP, NS>(a, tl, c, cs, wk, el, v);
     ++nevals;
     if (val < bestv || (val == bestv && c < bestc)) {
@@ -1013,16 +1082,19 @@ __device__ __forceinline__ void assign_tile(const AssignArgs<T>& a,
 
 template <typename T, int MP, int R>
 __global__ void __launch_bounds__(256) k_assign(AssignArgs<T> a) {
+  extern __shared__ unsigned char s_raw[];  // per wave: d values (mu_P)
   const int lane = threadIdx.x & (kWave - 1);
-  const int64_t k = (int64_t)blockIdx.x * (blockDim.x / kWave) +
-                    uni(threadIdx.x / kWave);
+  const int wave = uni(threadIdx.x / kWave);
+  const int64_t k = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave;
   if (k >= a.N) return;  // whole wavefront exits together
+  T* smu = reinterpret_cast<T*>(s_raw) + (int64_t)wave * a.d;
   Tile<T, MP> tl;
   tl.setup(a.off, nullptr, a.m, (int)k);
+  const int prev = a.prev_valid ? uni(a.labels[k]) : -1;
   double bestv = 0.0;
   int bestc = -1, nevals = 0;
   with_slots<R>(tl.nsl, [&]<int NS>() {
-    assign_tile<T, MP, NS>(a, tl, bestv, bestc, nevals);
+    assign_tile<T, MP, NS>(a, tl, smu, prev, bestv, bestc, nevals);
   });
   if (lane == 0) {
     a.labels[k] = bestc;

@@ -483,3 +483,27 @@ def test_assignment_lower_bound_holds(oracle_mod):
         for T in (1, 5, 100):
             assert oracle_mod.badmm_ot(x, w, y, wy, T=T) >= lb * (1 - 1e-12)
         assert oracle_mod.exact_w2(x, w, y, wy)[0] >= lb * (1 - 1e-9)
+
+
+def test_cheap_assignment_bound_below_full_bound(oracle_mod):
+    """The cheap pruning bound (triangle inequality around the centroid mean
+    mu_c with support radius rad_c and the instance mean mu_P):
+    sum_j w_j max(0, |dist(mu_P, mu_c) - |y_j - mu_P|| - rad_c)^2 never
+    exceeds sum_j w_j min_i C_ij, which never exceeds the transport value."""
+    rng = np.random.default_rng(37)
+    for _ in range(50):
+        m, mk, d = rng.integers(1, 9), rng.integers(1, 9), rng.integers(1, 6)
+        x, w = _rand_dist(rng, m, d)
+        y, wy = _rand_dist(rng, mk, d)
+        x = x + rng.normal(size=d) * rng.uniform(0, 3)
+        C = cdist(x, y, "sqeuclidean")
+        full = float(wy @ C.min(axis=0))
+        mu_c = w @ x
+        rad = np.sqrt(((x - mu_c) ** 2).sum(1)).max()
+        mu_p = wy @ y
+        dl = np.linalg.norm(mu_p - mu_c)
+        rj = np.linalg.norm(y - mu_p, axis=1)
+        gap = np.maximum(0.0, np.abs(dl - rj) - rad)
+        cheap = float(wy @ gap ** 2)
+        assert cheap <= full * (1 + 1e-12) + 1e-15
+        assert full <= oracle_mod.badmm_ot(x, w, y, wy, T=50) * (1 + 1e-12)
