@@ -231,6 +231,93 @@ d2_status d2_autotune(d2_ctx* ctx, const d2_badmm_params* p,
 d2_status d2_sizes(const d2_ctx* ctx, int64_t* N, int64_t* n, int32_t* d,
                    int32_t* K, int32_t* m);
 
+/* Barycenter objective of the current centroids under the plans of the last
+ * d2_barycenter (Eq. (badmm_prob) evaluated at a feasible point): every
+ * instance's Pi1 is rounded to a coupling whose row sums are the centroid
+ * weights and whose column sums are w^(k) exactly (rows scaled down to at
+ * most w_c, then columns to at most w^(k), then the rank-one correction
+ * err_r err_c^T / |err_r|_1), and its cost under C(x) is taken in FP64.
+ * Each value is an upper bound on W^2 between the centroid and the
+ * instance, so per_cluster[c] = (1/N_c) sum_{k in c} value_k bounds the
+ * cluster's objective from above.  per_instance (N) and per_cluster (K,
+ * 0 for empty clusters) may be NULL.  The per-cluster means are summed on
+ * the host in instance order.  D2_ESTATE if the labels changed since the
+ * last d2_barycenter. */
+d2_status d2_objective_feasible(d2_ctx* ctx, double* per_instance,
+                                double* per_cluster);
+
+/* ---- Learned warm start ------------------------------------------------
+ * Not part of the paper: a deep-sets network proposes each cluster's
+ * initial centroid for the centroid update of Sec. 3.2 from the cluster's
+ * members.  For the points y_j of member k (weights w_j, m_k points) of a
+ * cluster with weighted mean mu and RMS radius s:
+ *   f = [(y_j - mu)/s, m_k w_j] (zero padded to din = roundup(d+1, 16)),
+ *   h = relu(relu(f W1 + b1) W2 + b2),  g = sum_j (w_j / N_c) h,
+ *   o = relu(relu(g V1 + e1) V2 + e2) V3 + e3  (outp = roundup(m(d+1), 32)),
+ *   x_i = mu + s o[i d .. i d + d),  w = softmax(o[m d .. m d + m)).
+ * Matrix products take BF16 operands with FP32 accumulation (MFMA); the
+ * master parameters are FP32, one flat vector ordered W1 (din x H), b1,
+ * W2 (H x H), b2, V1 (H x H), e1, V2 (H x H), e2, V3 (H x outp), e3, each
+ * matrix row-major with the input index first.
+ * Training loss per cluster with targets (x*, w*), in standardised
+ * coordinates t_j = (x*_j - mu)/s, nn by first minimum:
+ *   sum_j w*_j |D_nn(j) - t_j|^2 + sum_i w_i |D_i - t_nn(i)|^2
+ *   - sum_i q_i log w_i,   q_i = sum of w*_j with nn(j) = i;
+ * the batch loss is the mean over the batch's clusters.
+ * Limits: m <= 64, d <= 64, m d <= 2048, H in {32, 64, 96, 128}.  A handle
+ * lives on one device and serves any context on that device whose m and d
+ * match; its calls run on the context's stream. */
+typedef struct d2_ws d2_ws;
+
+typedef struct {
+  double lr;     /* Adam step size                              */
+  double beta1;  /* first-moment decay                          */
+  double beta2;  /* second-moment decay                         */
+  double eps;    /* denominator guard                           */
+  double clip;   /* global gradient-norm clip (0: no clipping)  */
+} d2_ws_opt;
+
+/* Number of parameters for (m, d, hidden), or -1 outside the limits. */
+int64_t d2_ws_param_count(int32_t m, int32_t d, int32_t hidden);
+
+/* Create a network on `device` with initial parameters theta (host,
+ * d2_ws_param_count values, copied).  Adam state starts at zero. */
+d2_status d2_ws_create(d2_ws** out, int32_t device, int32_t m, int32_t d,
+                       int32_t hidden, const float* theta);
+void d2_ws_destroy(d2_ws* ws);
+const char* d2_ws_last_error(const d2_ws* ws);
+
+/* Copy parameters in (resets the Adam state) / out (host buffers). */
+d2_status d2_ws_params_set(d2_ws* ws, const float* theta);
+d2_status d2_ws_params_get(d2_ws* ws, float* theta);
+
+/* Take the context's current K centroids as the training targets of its
+ * clusters (cluster c of later batches is trained toward centroid c). */
+d2_status d2_ws_targets_from(d2_ws* ws, d2_ctx* ctx);
+
+/* Mean loss (may be NULL) and its gradient (host, param_count values, may
+ * be NULL) over the batch clusters[0..nb) of the context's current labels.
+ * Every listed cluster must be non-empty; D2_ESTATE without targets or if
+ * the context's K changed since d2_ws_targets_from. */
+d2_status d2_ws_grad(d2_ws* ws, d2_ctx* ctx, const int32_t* clusters,
+                     int32_t nb, double* loss, float* grad);
+
+/* One Adam step (bias-corrected, after global-norm clipping) on the batch's
+ * gradient; loss (may be NULL) gets the batch loss before the step. */
+d2_status d2_ws_train_step(d2_ws* ws, d2_ctx* ctx, const int32_t* clusters,
+                           int32_t nb, const d2_ws_opt* opt, double* loss);
+
+/* Propose a centroid for every non-empty cluster of the context's current
+ * labels.  The product-coupling bound sum_k sum_ij w_i w_j^(k) C_ij of the
+ * proposal is compared with that of the context's current centroid (the
+ * plain initial centroid); the proposal replaces it iff it is finite and,
+ * when gate != 0, its bound is not larger.  accepted[c] (K) gets 1 / 0, or
+ * -1 for empty clusters; bound_prop and bound_plain (K) the two bounds (NaN
+ * for empty clusters); any of the three may be NULL. */
+d2_status d2_ws_propose(d2_ws* ws, d2_ctx* ctx, int32_t gate,
+                        int32_t* accepted, double* bound_prop,
+                        double* bound_plain);
+
 #ifdef __cplusplus
 }
 #endif

@@ -16,6 +16,13 @@ Distribution Clustering Using Wasserstein Barycenter with Sparse Support"):
   cluster         Algorithm "D2 Clustering" with the Sec. 5 warm start
   exact_w2        Eq. (primal), solved as an LP (HiGHS)
   f_true          Eq. (centroid): (1/N) sum_k W^2(P, P^(k))
+  round_feasible  a plan rounded to exact marginals (Altschuler, Weed and
+                  Rigollet 2017, Algorithm 2), so Eq. (badmm_prob)'s cost
+                  can be evaluated at a feasible point
+  feasible_objective  (1/N) sum_k <C^(k), round(Pi1^(k))>, an upper bound
+                  on Eq. (centroid) at the current centroid
+The learned warm start (not part of the paper) has its own FP64 reference
+in oracle/deepsets.py.
 Every function here is pinned by tests/test_oracle_*.py against values that
 do not come from this module (LP solves, closed forms, invariants).
 """
@@ -271,4 +278,42 @@ def f_true(wl, members, x, w):
     for k in members:
         a, b = off[k], off[k + 1]
         tot += exact_w2(x, w, X[a:b], W[a:b])[0]
+    return tot / len(members)
+
+
+def round_feasible(P, a, b):
+    """Round a nonnegative m x m_k matrix to a coupling with row sums a and
+    column sums b (Altschuler, Weed and Rigollet 2017, Algorithm 2): scale
+    rows down to at most a, then columns down to at most b, then add the
+    rank-one correction err_r err_c^T / |err_r|_1."""
+    P = _f64(P)
+    a, b = _f64(a), _f64(b)
+    r = P.sum(1)
+    xr = np.ones_like(r)
+    big = r > a
+    xr[big] = a[big] / r[big]
+    P1 = xr[:, None] * P
+    c = P1.sum(0)
+    yc = np.ones_like(c)
+    big = c > b
+    yc[big] = b[big] / c[big]
+    P2 = P1 * yc[None, :]
+    er = a - P2.sum(1)
+    ec = b - P2.sum(0)
+    E = er.sum()
+    if E > 0:
+        P2 = P2 + np.outer(er, ec) / E
+    return P2
+
+
+def feasible_objective(wl, members, x, w, plans):
+    """(1/N) sum_k <C^(k), round(Pi1^(k))> over `members`, each Pi1 from
+    `plans` rounded to marginals (w, w^(k)) by round_feasible."""
+    off, X, W = wl["offsets"], wl["X"], wl["W"]
+    tot = 0.0
+    for k in members:
+        a, b = off[k], off[k + 1]
+        P1 = plans.block(off, k)[0]
+        R = round_feasible(P1, w, W[a:b])
+        tot += float((R * cost_block(x, X[a:b])).sum())
     return tot / len(members)

@@ -26,6 +26,8 @@ from __future__ import annotations
 
 import numpy as np
 
+from synth.generators import deepsets_init_params
+
 
 def dims(m, d, H):
     din = (d + 1 + 15) // 16 * 16
@@ -60,22 +62,8 @@ def pack(parts, m, d, H):
 
 
 def init_params(m, d, H, seed):
-    """He-style initial parameters drawn from a seeded generator."""
-    rng = np.random.Generator(np.random.PCG64(seed))
-    din, out, outp = dims(m, d, H)
-    p = {}
-    p["W1"] = np.zeros((din, H))
-    p["W1"][:d + 1] = rng.standard_normal((d + 1, H)) * np.sqrt(2.0 / (d + 1))
-    p["b1"] = np.zeros(H)
-    for w in ("W2", "V1", "V2"):
-        p[w] = rng.standard_normal((H, H)) * np.sqrt(2.0 / H)
-    p["b2"] = np.zeros(H)
-    p["e1"] = np.zeros(H)
-    p["e2"] = np.zeros(H)
-    p["V3"] = np.zeros((H, outp))
-    p["V3"][:, :out] = rng.standard_normal((H, out)) * np.sqrt(1.0 / H)
-    p["e3"] = np.zeros(outp)
-    return pack(p, m, d, H)
+    """Seeded initial parameters (drawn by the shared input generator)."""
+    return deepsets_init_params(m, d, H, seed)
 
 
 def round_bf16(a):
@@ -185,23 +173,36 @@ def forward_backward(theta, clusters, m, d, H, bf16=False):
     return total / B, pack(grads, m, d, H)
 
 
-def propose(theta, cl, m, d, H):
-    """Proposed (x, w) for one cluster (FP64)."""
+def propose(theta, cl, m, d, H, bf16=False):
+    """Proposed (x, w) for one cluster.  bf16=True rounds parameters and
+    stored activations where the GPU path stores them as BF16."""
     din, out, outp = dims(m, d, H)
+    rb = round_bf16 if bf16 else (lambda a: a)
     P = unpack(theta, m, d, H)
+    Pq = {k: rb(v) if k[0] in "WV" else v for k, v in P.items()}
     y, w, pw, mw = cl["y"], cl["w"], cl["pw"], cl["mw"]
     mu = (w @ y) / w.sum()
     s = max(np.sqrt((w * ((y - mu) ** 2).sum(1)).sum() / w.sum()), 1e-12)
     f = np.zeros((len(y), din))
     f[:, :d] = (y - mu) / s
     f[:, d] = mw
-    h1 = np.maximum(f @ P["W1"] + P["b1"], 0)
-    h2 = np.maximum(h1 @ P["W2"] + P["b2"], 0)
-    g = pw @ h2
-    u1 = np.maximum(g @ P["V1"] + P["e1"], 0)
-    u2 = np.maximum(u1 @ P["V2"] + P["e2"], 0)
-    o = u2 @ P["V3"] + P["e3"]
+    f = rb(f)
+    h1 = rb(np.maximum(f @ Pq["W1"] + P["b1"], 0))
+    h2 = rb(np.maximum(h1 @ Pq["W2"] + P["b2"], 0))
+    g = rb(pw @ h2)
+    u1 = rb(np.maximum(g @ Pq["V1"] + P["e1"], 0))
+    u2 = rb(np.maximum(u1 @ Pq["V2"] + P["e2"], 0))
+    o = u2 @ Pq["V3"] + P["e3"]
     x = mu + s * o[:m * d].reshape(m, d)
     lg = o[m * d:m * d + m]
     ex = np.exp(lg - lg.max())
     return x, ex / ex.sum()
+
+
+def product_bound(cl, x, w):
+    """sum over members k, support i, points j of w_i w_j^(k) |x_i - y_j|^2
+    (the cost of the product coupling, an upper bound on the barycenter
+    objective at (x, w)), by brute force."""
+    y, wy = cl["y"], cl["w"]
+    C = ((x[:, None, :] - y[None, :, :]) ** 2).sum(2)
+    return float(w @ C @ wy)

@@ -10,7 +10,12 @@
 #include <vector>
 
 #include "../../include/d2.h"
+#include "d2_ctx.hpp"
 #include "d2_kernels.hpp"
+
+static const char* kKindNames[kKinds] = {"rho_cost", "init_a", "iter_ba",
+                                         "b_final", "xnum_only", "assign",
+                                         "finalize"};
 
 namespace {
 
@@ -58,101 +63,6 @@ const d2k::FinFn* fin_table() {
 }
 
 }  // namespace
-
-enum KernelKind {
-  kKRho = 0, kKInitA, kKIterBA, kKBF, kKXO, kKAssign, kKFin, kKinds
-};
-static const char* kKindNames[kKinds] = {"rho_cost", "init_a", "iter_ba",
-                                         "b_final", "xnum_only", "assign",
-                                         "finalize"};
-
-struct d2_ctx {
-  int device = 0;
-  d2_dtype dt = D2_F32;
-  hipStream_t stream = nullptr;
-  bool own_stream = false;
-  std::string err;
-  // instances
-  int64_t N = 0, n = 0;
-  int d = 0, xs = 0, mk_max = 0;  // xs: row stride of X, d rounded up to 4
-  std::vector<int64_t> h_off;
-  std::vector<int64_t> h_pofs;  // plan tile offsets (128-byte aligned), N+1
-  int64_t* d_off = nullptr;
-  int64_t* d_pofs = nullptr;
-  void* d_X = nullptr;
-  void* d_W = nullptr;
-  // centroids (double on device, rows padded to MP)
-  int K = 0, m = 0, MP = 0, R = 0;
-  double* d_xc = nullptr;
-  double* d_wc = nullptr;
-  double* d_rho = nullptr;
-  int* d_cnt = nullptr;
-  // labels
-  std::vector<int32_t> h_labels, h_cache_labels;
-  bool have_labels = false, have_cache = false;
-  int32_t* d_labels = nullptr;
-  double* d_best = nullptr;
-  unsigned long long* d_evals = nullptr;
-  void* d_cmu = nullptr;   // K x d centroid means (device dtype)
-  void* d_crad = nullptr;  // K centroid support radii
-  void* d_xct = nullptr;   // K x MP x xs centroid supports (device dtype)
-  int64_t last_evals = 0, last_pairs = 0;
-  // plans
-  void* d_P1 = nullptr;
-  void* d_P2 = nullptr;
-  void* d_L = nullptr;
-  void* d_C = nullptr;
-  bool onfly = true;
-  // work lists
-  int chunk_inst = 64;  // instances per chunk
-  int waves = 4;        // wavefronts per workgroup
-  int nchunks = 0, nch_cap = 0;
-  int32_t* d_work = nullptr;
-  d2k::Chunk* d_chunks = nullptr;
-  int2* d_ctab = nullptr;
-  double* d_ninv = nullptr;
-  double* d_cinv = nullptr;
-  uint8_t* d_warm = nullptr;
-  double* d_part = nullptr;   // 2 x cap x ps (double-buffered records)
-  double* d_partx = nullptr;  // 2 x cap x MP x (d+1) support records
-  int* d_nch = nullptr;       // device copy of nchunks
-  std::vector<int2> h_ctab;
-  bool lists_valid = false;
-  // objective trace of the last barycenter
-  double* d_trace = nullptr;
-  int trace_cap = 0, trace_rows = 0;
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
-  // captured launch sequence of d2_barycenter
-  bool use_graph = true;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t gexec = nullptr;
-  std::vector<double> graph_key;
-  int graph_launches = 0;
-  // per-kernel profiling
-  bool prof = false;
-  struct Pending {
-    int kind;
-    hipEvent_t a, b;
-  };
-  std::vector<Pending> pending;
-  std::vector<hipEvent_t> ev_pool;
-  int64_t prof_launches[kKinds] = {};
-  double prof_ms[kKinds] = {};
-
-  d2_status fail(d2_status s, const std::string& msg) {
-    err = msg;
-    return s;
-  }
-  size_t esz() const { return dt == D2_F64 ? 8 : 4; }
-};
-
-#define HIPCHK(ctx, call)                                                 \
-  do {                                                                    \
-    hipError_t e_ = (call);                                               \
-    if (e_ != hipSuccess)                                                 \
-      return (ctx)->fail(D2_EDEVICE, std::string(#call) + ": " +          \
-                                         hipGetErrorString(e_));          \
-  } while (0)
 
 namespace {
 
@@ -985,6 +895,7 @@ d2_status d2_load_instances(d2_ctx* c, int64_t N, int32_t d,
     if ((s = upload_conv<float>(c, c->d_W, Wn.data(), n))) return s;
   }
   c->h_labels.assign(N, 0);
+  ++c->label_gen;
   return D2_OK;
 }
 
@@ -1095,6 +1006,7 @@ d2_status d2_labels_set(d2_ctx* c, const int32_t* labels) {
       return c->fail(D2_EINVAL, "label out of range at " + std::to_string(k));
   HIPCHK(c, hipSetDevice(c->device));
   c->h_labels.assign(labels, labels + c->N);
+  ++c->label_gen;
   HIPCHK(c, hipMemcpy(c->d_labels, labels, sizeof(int32_t) * c->N,
                       hipMemcpyHostToDevice));
   c->have_labels = true;
@@ -1127,6 +1039,7 @@ d2_status d2_assign(d2_ctx* c, const d2_ot_params* p, int32_t* labels_out,
   for (int64_t k = 0; k < c->N; ++k)
     changed += (!c->have_labels || lab[k] != c->h_labels[k]);
   c->h_labels.swap(lab);
+  ++c->label_gen;
   c->have_labels = true;
   c->lists_valid = false;
   if (labels_out) std::copy(c->h_labels.begin(), c->h_labels.end(), labels_out);

@@ -29,6 +29,10 @@ EXPORTS = [
     "d2_support_update", "d2_cluster", "d2_objective", "d2_plans_get",
     "d2_sizes", "d2_set_profiling", "d2_kernel_stats", "d2_set_schedule",
     "d2_assign_pairs", "d2_set_graph", "d2_autotune",
+    "d2_objective_feasible", "d2_ws_param_count", "d2_ws_create",
+    "d2_ws_destroy", "d2_ws_last_error", "d2_ws_params_set",
+    "d2_ws_params_get", "d2_ws_targets_from", "d2_ws_grad",
+    "d2_ws_train_step", "d2_ws_propose",
 ]
 
 
@@ -60,6 +64,12 @@ class RoundInfo(ctypes.Structure):
     _fields_ = [("round", ctypes.c_int32), ("n_changed", ctypes.c_int64),
                 ("assign_obj", ctypes.c_double), ("ms_assign", ctypes.c_double),
                 ("ms_barycenter", ctypes.c_double)]
+
+
+class WsOpt(ctypes.Structure):
+    _fields_ = [("lr", ctypes.c_double), ("beta1", ctypes.c_double),
+                ("beta2", ctypes.c_double), ("eps", ctypes.c_double),
+                ("clip", ctypes.c_double)]
 
 
 class KernelStat(ctypes.Structure):
@@ -113,6 +123,19 @@ def load_library(path: str = LIB_PATH):
                         ctypes.c_int),
         "d2_kernel_stats": ([_p, ctypes.POINTER(KernelStat), _i32, _p, _i32],
                             ctypes.c_int),
+        "d2_objective_feasible": ([_p, _p, _p], ctypes.c_int),
+        "d2_ws_param_count": ([_i32, _i32, _i32], _i64),
+        "d2_ws_create": ([ctypes.POINTER(_p), _i32, _i32, _i32, _i32, _p],
+                         ctypes.c_int),
+        "d2_ws_destroy": ([_p], None),
+        "d2_ws_last_error": ([_p], ctypes.c_char_p),
+        "d2_ws_params_set": ([_p, _p], ctypes.c_int),
+        "d2_ws_params_get": ([_p, _p], ctypes.c_int),
+        "d2_ws_targets_from": ([_p, _p], ctypes.c_int),
+        "d2_ws_grad": ([_p, _p, _p, _i32, _p, _p], ctypes.c_int),
+        "d2_ws_train_step": ([_p, _p, _p, _i32, ctypes.POINTER(WsOpt), _p],
+                             ctypes.c_int),
+        "d2_ws_propose": ([_p, _p, _i32, _p, _p, _p], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -320,8 +343,99 @@ class D2Context:
                                        float(arr[q].total_ms))
                 for q in range(min(cnt.value, 16))}
 
+    def objective_feasible(self):
+        """(per-instance, per-cluster) rounded-plan objective of the current
+        centroids under the last plans."""
+        pi = np.zeros(self.N)
+        pc = np.zeros(self.K)
+        self._chk(self.lib.d2_objective_feasible(self.h, _ptr(pi), _ptr(pc)))
+        return pi, pc
+
     def plans_get(self, k):
         mk = int(self.offsets[k + 1] - self.offsets[k])
         bufs = [np.empty(self.m * mk) for _ in range(3)]
         self._chk(self.lib.d2_plans_get(self.h, int(k), *[_ptr(b) for b in bufs]))
         return tuple(b.reshape(mk, self.m).T.copy() for b in bufs)
+
+
+def ws_param_count(m, d, hidden):
+    return int(load_library().d2_ws_param_count(int(m), int(d), int(hidden)))
+
+
+class D2WarmStart:
+    """Deep-sets warm-start network (d2_ws_* calls)."""
+
+    def __init__(self, m, d, hidden, theta, device=0):
+        self.lib = load_library()
+        self.m, self.d, self.hidden = int(m), int(d), int(hidden)
+        self.np = ws_param_count(m, d, hidden)
+        if self.np < 0:
+            raise D2Error(D2_EINVAL, "network size outside the limits")
+        th = _c(theta, np.float32)
+        if th.size != self.np:
+            raise D2Error(D2_EINVAL, f"theta has {th.size} values, "
+                          f"expected {self.np}")
+        h = _p()
+        st = self.lib.d2_ws_create(ctypes.byref(h), int(device), self.m,
+                                   self.d, self.hidden, _ptr(th))
+        if st != D2_OK:
+            raise D2Error(st, "d2_ws_create failed")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.d2_ws_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _chk(self, st):
+        if st != D2_OK:
+            msg = self.lib.d2_ws_last_error(self.h)
+            raise D2Error(st, msg.decode() if msg else "")
+
+    def params_get(self):
+        th = np.empty(self.np, dtype=np.float32)
+        self._chk(self.lib.d2_ws_params_get(self.h, _ptr(th)))
+        return th
+
+    def params_set(self, theta):
+        th = _c(theta, np.float32)
+        if th.size != self.np:
+            raise D2Error(D2_EINVAL, "theta size")
+        self._chk(self.lib.d2_ws_params_set(self.h, _ptr(th)))
+
+    def targets_from(self, ctx):
+        self._chk(self.lib.d2_ws_targets_from(self.h, ctx.h))
+
+    def grad(self, ctx, clusters):
+        ids = _c(clusters, np.int32)
+        g = np.empty(self.np, dtype=np.float32)
+        loss = ctypes.c_double(0)
+        self._chk(self.lib.d2_ws_grad(self.h, ctx.h, _ptr(ids), ids.size,
+                                      ctypes.byref(loss), _ptr(g)))
+        return loss.value, g
+
+    def train_step(self, ctx, clusters, lr=1e-3, beta1=0.9, beta2=0.999,
+                   eps=1e-8, clip=1.0, want_loss=True):
+        ids = _c(clusters, np.int32)
+        opt = WsOpt(lr=lr, beta1=beta1, beta2=beta2, eps=eps, clip=clip)
+        loss = ctypes.c_double(0)
+        self._chk(self.lib.d2_ws_train_step(
+            self.h, ctx.h, _ptr(ids), ids.size, ctypes.byref(opt),
+            ctypes.byref(loss) if want_loss else None))
+        return loss.value if want_loss else None
+
+    def propose(self, ctx, gate=True):
+        """Replace accepted clusters' centroids in ctx; returns
+        (accepted[K], bound_prop[K], bound_plain[K])."""
+        acc = np.zeros(ctx.K, dtype=np.int32)
+        bp = np.zeros(ctx.K)
+        bq = np.zeros(ctx.K)
+        self._chk(self.lib.d2_ws_propose(self.h, ctx.h, int(bool(gate)),
+                                         _ptr(acc), _ptr(bp), _ptr(bq)))
+        return acc, bp, bq

@@ -32,6 +32,8 @@ __all__ = [
     "topic_sphere_workload",
     "pick_init_members",
     "round_to_bf16",
+    "warmstart_clusters",
+    "deepsets_init_params",
 ]
 
 
@@ -189,3 +191,96 @@ def pick_init_members(offsets, K, m, seed):
         raise ValueError(f"only {len(elig)} instances have >= {m} points; need {K}")
     rng = _rng(int(seed) + 7777777)
     return np.sort(rng.choice(elig, size=K, replace=False)).astype(np.int64)
+
+
+def _loguniform_int(rng, lo, hi, size):
+    return np.floor(np.exp(rng.uniform(np.log(lo), np.log(hi + 1), size=size))
+                    ).astype(np.int64).clip(lo, hi)
+
+
+def warmstart_clusters(family, n_clusters, seed, nc_lo=64, nc_hi=2048,
+                       contam_max=0.2):
+    """Whole clusters for training / evaluating the learned warm start.
+
+    Every cluster is its own small world, so that a network has to infer
+    the barycenter from the members rather than memorise a fixed set of
+    classes.  Cluster c has N_c ~ log-uniform{nc_lo..nc_hi} member
+    instances; a fraction f_c ~ U[0, contam_max] of them are contaminated
+    (drawn from other classes).  Instances of a cluster are stored
+    contiguously; `labels` gives each instance's cluster.  The first member
+    of every cluster has the maximal support size, so that a member with at
+    least m points exists for the plain initial centroid.
+
+    family "gmm3" (the colour-like cfg2 family): d = 3, m_k ~ U{4..16};
+      own class = 2 Gaussian components with means ~ U[0,1]^3, sigma 0.05;
+      contamination = 2 further components; weights Dirichlet(0.5).
+    family "topic64" (the word-vector-like cfg3 family): d = 64,
+      m_k = 7 + Zipf(1.2) <= 64; own class = 8 unit topic vectors,
+      contamination = 8 more; points normalise(t + (0.3/8) N(0, I)),
+      rounded to bf16; weights Zipf(1.2) counts <= 1000.
+
+    Draw order: N_c, f_c, class centres, contamination flags, support
+    sizes, component choice, noise, weights.
+    """
+    rng = _rng(seed)
+    C = int(n_clusters)
+    nc = _loguniform_int(rng, nc_lo, nc_hi, C)
+    frac = rng.uniform(0.0, contam_max, size=C)
+    N = int(nc.sum())
+    labels = np.repeat(np.arange(C, dtype=np.int32), nc)
+    first = np.concatenate([[0], np.cumsum(nc)[:-1]])
+    if family == "gmm3":
+        d, ncomp, mk_lo, mk_hi = 3, 2, 4, 16
+        centres = rng.uniform(0.0, 1.0, size=(C, 2 * ncomp, d))
+    elif family == "topic64":
+        d, ncomp, mk_hi = 64, 8, 64
+        centres = rng.standard_normal(size=(C, 2 * ncomp, d))
+        centres /= np.linalg.norm(centres, axis=2, keepdims=True)
+    else:
+        raise ValueError(family)
+    contam = rng.uniform(size=N) < frac[labels]
+    if family == "gmm3":
+        sizes = rng.integers(mk_lo, mk_hi + 1, size=N).astype(np.int64)
+    else:
+        sizes = 7 + _zipf_bounded(rng, 1.2, mk_hi - 7, N)
+    sizes[first] = mk_hi
+    contam[first] = False
+    n = int(sizes.sum())
+    pt_cl = np.repeat(labels, sizes)
+    pt_off = np.repeat(contam.astype(np.int64) * ncomp, sizes)
+    comp = pt_off + rng.integers(0, ncomp, size=n)
+    mean = centres[pt_cl, comp]
+    if family == "gmm3":
+        X = mean + 0.05 * rng.standard_normal(size=(n, d))
+        W = _ragged_dirichlet(rng, sizes, 0.5)
+    else:
+        X = mean + (0.3 / np.sqrt(d)) * rng.standard_normal(size=(n, d))
+        X /= np.linalg.norm(X, axis=1, keepdims=True)
+        X = round_to_bf16(X)
+        counts = _zipf_bounded(rng, 1.2, 1000, n).astype(np.float64)
+        offs = np.concatenate([[0], np.cumsum(sizes)])
+        W = counts / np.repeat(np.add.reduceat(counts, offs[:-1]), sizes)
+    offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    return {"offsets": offsets, "X": np.ascontiguousarray(X, dtype=np.float64),
+            "W": W.astype(np.float64), "labels": labels, "K": C, "d": d,
+            "first": first.astype(np.int64), "family": family, "seed": seed}
+
+
+def deepsets_init_params(m, d, H, seed):
+    """Initial parameters of the warm-start network (flat float64 vector in
+    the order W1 (din x H), b1, W2, b2, V1, e1, V2, e2, V3 (H x outp), e3,
+    din = roundup(d+1, 16), outp = roundup(m(d+1), 32)): He-normal
+    matrices, zero biases, zero padding rows / columns."""
+    rng = _rng(seed)
+    din = (d + 1 + 15) // 16 * 16
+    out = m * (d + 1)
+    outp = (out + 31) // 32 * 32
+    W1 = np.zeros((din, H))
+    W1[:d + 1] = rng.standard_normal((d + 1, H)) * np.sqrt(2.0 / (d + 1))
+    mats = [rng.standard_normal((H, H)) * np.sqrt(2.0 / H) for _ in range(3)]
+    V3 = np.zeros((H, outp))
+    V3[:, :out] = rng.standard_normal((H, out)) * np.sqrt(1.0 / H)
+    z = np.zeros
+    parts = [W1, z(H), mats[0], z(H), mats[1], z(H), mats[2], z(H), V3,
+             z(outp)]
+    return np.concatenate([q.reshape(-1) for q in parts])
