@@ -185,7 +185,8 @@ def main():
     rec_sched = None if args.autotune else d2.tuned_schedule(key)
     if rec_sched:
         ctx.set_schedule(*rec_sched)
-        sched.update(chunk=rec_sched[0], waves=rec_sched[1], source="recorded")
+        sched.update(chunk=rec_sched[0], waves=rec_sched[1],
+                     bucket=rec_sched[2], source="recorded")
         log(f"[bench] recorded schedule {sched} for {key}")
 
     def step(first):
@@ -277,6 +278,7 @@ def main():
         "barycenter_graph": graphed,
         "schedule": {"chunk_instances": sched.get("chunk"),
                      "waves_per_group": sched.get("waves"),
+                     "bucketing_min_pct": sched.get("bucket"),
                      "source": sched.get("source")},
         "assign_pairs_evaluated_frac": ev / tot if tot else None,
         "kernel_timing": "HIP events around each launch on the context "

@@ -189,7 +189,9 @@ d2_status d2_plans_get(d2_ctx* ctx, int64_t k, double* P1, double* P2,
  * context is bracketed by two HIP events recorded on the context's stream,
  * and the elapsed times are accumulated per kernel kind when the call that
  * launched them synchronises.  Kinds: "rho_cost", "init_a", "iter_ba",
- * "b_final", "xnum_only", "assign", "finalize". */
+ * "b_final", "xnum_only", "assign", "finalize".  One "iter_ba" unit is one
+ * B-ADMM iteration: the launches of all slot buckets (d2_set_bucketing)
+ * inside one event pair. */
 typedef struct {
   char name[24];
   int64_t launches;
@@ -216,16 +218,29 @@ d2_status d2_set_graph(d2_ctx* ctx, int32_t on);
 d2_status d2_set_schedule(d2_ctx* ctx, int32_t chunk_instances,
                           int32_t waves_per_group);
 
+/* Slot buckets of the per-iteration plan-update kernel.  An instance's
+ * tile needs ceil(m_k / (64 / pad(m))) register slots per lane; instances
+ * are grouped by the power of two above that count, and each group runs as
+ * its own launch of a kernel specialised for it (fewer registers, more
+ * wavefronts in flight for small instances).  A group holding fewer than
+ * min_pct % of the plan entries joins the next larger group; 100 gives one
+ * launch for all instances (the default: on the measured workloads the
+ * extra launches cost more than the higher occupancy gains), 0 one launch
+ * per group present.
+ * Results depend on it only through floating-point summation order. */
+d2_status d2_set_bucketing(d2_ctx* ctx, int32_t min_pct);
+
 /* Autotuner: times d2_barycenter (`iters` iterations, product start) on the
  * current labels for each candidate schedule -- instances per chunk in
- * {16, 32, 64, 128, 256} x wavefronts per workgroup in {2, 4} -- keeps the
- * fastest (set as the context's schedule) and reports it.  Centroids are
- * restored afterwards; any warm-start plan cache is dropped, so call it
- * before the first centroid update.  ms_best (may be NULL) gets the best
+ * {16, 32, 64, 128, 256} x wavefronts per workgroup in {2, 4} x slot
+ * bucketing threshold in {100, 10} (d2_set_bucketing) -- keeps the fastest
+ * (set on the context) and reports it.  Centroids are restored afterwards;
+ * any warm-start plan cache is dropped, so call it before the first
+ * centroid update.  Any output pointer may be NULL; ms_best gets the best
  * device time. */
 d2_status d2_autotune(d2_ctx* ctx, const d2_badmm_params* p,
-                      int32_t* chunk_instances, int32_t* waves_per_group,
-                      double* ms_best);
+                      int32_t* chunk_out, int32_t* waves_out,
+                      int32_t* bucket_out, double* ms_best);
 
 /* Sizes: N, n, d, K, m of the context (any pointer may be NULL). */
 d2_status d2_sizes(const d2_ctx* ctx, int64_t* N, int64_t* n, int32_t* d,

@@ -111,7 +111,11 @@ void free_lists(d2_ctx* c) {
   dfree(c->d_part);
   dfree(c->d_partx);
   dfree(c->d_nch);
+  dfree(c->d_blist);
+  dfree(c->d_bcnt);
   c->nch_cap = 0;
+  c->blist_cap = 0;
+  c->nbk = 0;
   c->lists_valid = false;
   drop_graph(c);
 }
@@ -259,36 +263,85 @@ d2_status set_centroids_host(d2_ctx* c, int K, int m, const double* Xc,
   return D2_OK;
 }
 
+// Slot class of an instance: log2 of the register slots (columns per lane)
+// its tile needs, i.e. the hot-kernel specialisation R = 1 << class.
+int slot_class(const d2_ctx* c, int64_t k) {
+  const int cps = 64 / c->MP;
+  const int mk = (int)(c->h_off[k + 1] - c->h_off[k]);
+  return ilog2(std::max(1, (mk + cps - 1) / cps));
+}
+
 // Cluster-sorted work list, chunks and per-cluster tables for the labels.
+// Inside a cluster, instances are ordered by slot bucket and every chunk
+// holds one bucket, so a cluster's chunks stay contiguous (the per-cluster
+// record sums are unchanged) while each bucket runs in a kernel sized for
+// its own slot count.
 d2_status build_lists(d2_ctx* c, bool warm_start) {
   const int K = c->K;
   const int64_t N = c->N;
-  std::vector<int64_t> cnt(K, 0), ncols(K, 0);
+  // buckets: slot classes present, a class with fewer than
+  // bucket_min_pct % of the entries joins the next larger bucket
+  double ent[6] = {0, 0, 0, 0, 0, 0}, tot = 0.0;
+  std::vector<uint8_t> cls(N);
   for (int64_t k = 0; k < N; ++k) {
-    int l = c->h_labels[k];
+    cls[k] = (uint8_t)slot_class(c, k);
+    const double e = (double)(c->h_off[k + 1] - c->h_off[k]);
+    ent[cls[k]] += e;
+    tot += e;
+  }
+  int bmap[6];
+  std::vector<int> bR;
+  {
+    int cur = -1;
+    for (int q = 5; q >= 0; --q) {
+      if (ent[q] > 0 &&
+          (cur < 0 || ent[q] * 100.0 >= c->bucket_min_pct * tot)) {
+        cur = q;
+        bR.insert(bR.begin(), 1 << q);
+      }
+      bmap[q] = cur;
+    }
+  }
+  const int nbk = std::max<int>(1, (int)bR.size());
+  if (bR.empty()) bR.push_back(1);
+  std::vector<int> bidx_of(6, 0);
+  for (int q = 0; q < 6; ++q)
+    for (int b = 0; b < nbk; ++b)
+      if (bmap[q] >= 0 && (1 << bmap[q]) == bR[b]) bidx_of[q] = b;
+  std::vector<int64_t> cnt(K, 0), ncols(K, 0);
+  std::vector<int64_t> kcnt((size_t)K * nbk, 0);
+  for (int64_t k = 0; k < N; ++k) {
+    const int l = c->h_labels[k];
     cnt[l]++;
     ncols[l] += c->h_off[k + 1] - c->h_off[k];
+    kcnt[(size_t)l * nbk + bidx_of[cls[k]]]++;
   }
-  std::vector<int64_t> start(K + 1, 0);
-  for (int q = 0; q < K; ++q) start[q + 1] = start[q] + cnt[q];
+  std::vector<int64_t> start((size_t)K * nbk + 1, 0);
+  for (size_t q = 0; q < (size_t)K * nbk; ++q) start[q + 1] = start[q] + kcnt[q];
   std::vector<int32_t> work(N);
   {
     std::vector<int64_t> pos(start.begin(), start.end() - 1);
-    for (int64_t k = 0; k < N; ++k) work[pos[c->h_labels[k]]++] = (int32_t)k;
+    for (int64_t k = 0; k < N; ++k)
+      work[pos[(size_t)c->h_labels[k] * nbk + bidx_of[cls[k]]]++] = (int32_t)k;
   }
   std::vector<d2k::Chunk> chunks;
+  std::vector<std::vector<int32_t>> blists(nbk);
   c->h_ctab.assign(K, make_int2(0, 0));
   std::vector<double> ninv(K, 0.0), cinv(K, 0.0);
   const int CH = c->chunk_inst;
   for (int q = 0; q < K; ++q) {
     c->h_ctab[q].x = (int)chunks.size();
-    for (int64_t b = start[q]; b < start[q + 1]; b += CH) {
-      d2k::Chunk ck;
-      ck.cluster = q;
-      ck.begin = (int32_t)b;
-      ck.end = (int32_t)std::min<int64_t>(b + CH, start[q + 1]);
-      ck.pad = 0;
-      chunks.push_back(ck);
+    for (int b = 0; b < nbk; ++b) {
+      const size_t g = (size_t)q * nbk + b;
+      for (int64_t e = start[g]; e < start[g + 1]; e += CH) {
+        d2k::Chunk ck;
+        ck.cluster = q;
+        ck.begin = (int32_t)e;
+        ck.end = (int32_t)std::min<int64_t>(e + CH, start[g + 1]);
+        ck.pad = b;
+        blists[b].push_back((int32_t)chunks.size());
+        chunks.push_back(ck);
+      }
     }
     c->h_ctab[q].y = (int)chunks.size() - c->h_ctab[q].x;
     if (cnt[q] > 0) {
@@ -297,7 +350,7 @@ d2_status build_lists(d2_ctx* c, bool warm_start) {
     }
   }
   c->nchunks = (int)chunks.size();
-  int cap = (int)((N + CH - 1) / CH) + K;
+  int cap = (int)((N + CH - 1) / CH) + K * 6;
   if (cap > c->nch_cap || !c->d_work) {
     free_lists(c);
     d2_status s;
@@ -313,10 +366,39 @@ d2_status build_lists(d2_ctx* c, bool warm_start) {
                     sizeof(double) * 2 * cap * (c->MP + 2))))
       return s;
     if ((s = dalloc(c, (void**)&c->d_nch, sizeof(int)))) return s;
+    if ((s = dalloc(c, (void**)&c->d_bcnt, sizeof(int) * 6))) return s;
     if ((s = dalloc(c, (void**)&c->d_partx,
                     sizeof(double) * 2 * cap * c->MP * (c->d + 1))))
       return s;
   }
+  // bucket grids: kept while the bucket set is unchanged and the counts
+  // fit (a captured launch sequence stays valid), else resized with slack
+  bool same = nbk == c->nbk;
+  for (int b = 0; same && b < nbk; ++b)
+    same = bR[b] == c->bk_R[b] && (int)blists[b].size() <= c->bk_cap[b];
+  if (!same) {
+    drop_graph(c);
+    int total = 0;
+    for (int b = 0; b < 6; ++b) {
+      c->bk_R[b] = b < nbk ? bR[b] : 0;
+      c->bk_cap[b] = b < nbk ? (int)(blists[b].size() * 5 / 4) + 8 : 0;
+      c->bk_off[b] = total;
+      total += c->bk_cap[b];
+    }
+    c->nbk = nbk;
+    if (total > c->blist_cap) {
+      dfree(c->d_blist);
+      d2_status s = dalloc(c, (void**)&c->d_blist, sizeof(int32_t) * total);
+      if (s) return s;
+      c->blist_cap = total;
+    }
+  }
+  std::vector<int32_t> hbl(std::max(1, c->blist_cap), 0);
+  for (int b = 0; b < nbk; ++b) {
+    c->bk_cnt[b] = (int)blists[b].size();
+    std::copy(blists[b].begin(), blists[b].end(), hbl.begin() + c->bk_off[b]);
+  }
+  for (int b = nbk; b < 6; ++b) c->bk_cnt[b] = 0;
   std::vector<uint8_t> warm(N, 0);
   if (warm_start && c->have_cache)
     for (int64_t k = 0; k < N; ++k)
@@ -334,6 +416,10 @@ d2_status build_lists(d2_ctx* c, bool warm_start) {
                       hipMemcpyHostToDevice));
   HIPCHK(c, hipMemcpy(c->d_warm, warm.data(), N, hipMemcpyHostToDevice));
   HIPCHK(c, hipMemcpy(c->d_nch, &c->nchunks, sizeof(int),
+                      hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->d_bcnt, c->bk_cnt, sizeof(int) * 6,
+                      hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->d_blist, hbl.data(), sizeof(int32_t) * hbl.size(),
                       hipMemcpyHostToDevice));
   c->lists_valid = true;
   return D2_OK;
@@ -422,6 +508,10 @@ d2k::Args<T> make_args(d2_ctx* c, const d2_badmm_params* p) {
   a.work = c->d_work;
   a.chunks = c->d_chunks;
   a.nch = c->d_nch;
+  a.blist = nullptr;
+  a.bcnt = c->d_bcnt;
+  a.bidx = 0;
+  a.boff = 0;
   a.ctab = c->d_ctab;
   a.ninv = c->d_ninv;
   a.P1 = (T*)c->d_P1;
@@ -438,6 +528,7 @@ d2k::Args<T> make_args(d2_ctx* c, const d2_badmm_params* p) {
   a.xout = nullptr;
   a.trace = nullptr;
   a.recost = 0;
+  a.xstage = 0;
   a.eps = p ? p->eps : 1e-16;
   a.m = c->m;
   a.d = c->d;
@@ -475,16 +566,24 @@ d2_status launch_fin(d2_ctx* c, const d2k::FinArgs& f, int mode, int& nl) {
 }
 
 template <typename T>
-d2_status launch_aux(d2_ctx* c, const d2k::Args<T>& a, int mode, int& nl) {
+d2_status launch_aux(d2_ctx* c, const d2k::Args<T>& a0, int mode, int& nl) {
   const auto& kt = kern<T>();
   auto fn = kt.aux[ilog2(c->MP) - 3][ilog2(c->R)];
   if (!fn) return c->fail(D2_EINVAL, "no kernel for this tile shape");
+  d2k::Args<T> a = a0;
   int waves = c->waves;
   size_t per_wave = sizeof(double) * c->MP * (c->d + 1);
   bool xnum = (mode == d2k::kXO) || (mode == d2k::kA0 && a.xout);
   if (xnum)
     while (waves > 1 && per_wave * waves > 64 * 1024) --waves;
   size_t shm = xnum ? per_wave * waves : 0;
+  // large d: the cost pass reads the centroid support from LDS
+  const size_t stage = (size_t)c->MP * (c->xs + 4) * sizeof(T);
+  a.xstage = 0;
+  if (mode == d2k::kRho && !c->onfly && stage <= 64 * 1024) {
+    a.xstage = 1;
+    shm = stage;
+  }
   hipEvent_t pe = prof_begin(c);
   hipLaunchKernelGGL(fn, dim3(c->nch_cap), dim3(64 * waves), shm, c->stream,
                      a, mode);
@@ -494,22 +593,38 @@ d2_status launch_aux(d2_ctx* c, const d2k::Args<T>& a, int mode, int& nl) {
   return D2_OK;
 }
 
+// One B-ADMM iteration: a launch per slot bucket, each kernel specialised
+// for its bucket's register slots (profiled as one "iter_ba" unit).
 template <typename T>
 d2_status launch_ba(d2_ctx* c, const d2k::Args<T>& a, int& nl) {
   const auto& kt = kern<T>();
-  auto fn = kt.ba[c->onfly ? 1 : 0][ilog2(c->MP) - 3][ilog2(c->R)];
-  if (!fn) return c->fail(D2_EINVAL, "no kernel for this tile shape");
   int waves = c->waves;
   size_t per_wave = sizeof(double) * c->MP * (c->d + 1);
-  if (a.xout)
-    while (waves > 1 && per_wave * waves > 64 * 1024) --waves;
+  // large d, first launch after a support update: the cost is recomputed
+  // from the centroid support staged in LDS after the support records
+  const bool want_stage = a.recost && !c->onfly;
+  const size_t stage =
+      want_stage ? (size_t)c->MP * (c->xs + 4) * sizeof(T) : 0;
+  auto lds = [&](int wv) { return (a.xout ? per_wave * wv : 0) + stage; };
+  while (waves > 1 && lds(waves) > 64 * 1024) --waves;
+  const int xstage = (want_stage && lds(waves) <= 64 * 1024) ? 1 : 0;
   size_t shm = a.xout ? per_wave * waves : 0;
+  if (xstage) shm += stage;
   hipEvent_t pe = prof_begin(c);
-  hipLaunchKernelGGL(fn, dim3(c->nch_cap), dim3(64 * waves), shm, c->stream,
-                     a);
-  HIPCHK(c, hipGetLastError());
+  for (int b = 0; b < c->nbk; ++b) {
+    auto fn = kt.ba[c->onfly ? 1 : 0][ilog2(c->MP) - 3][ilog2(c->bk_R[b])];
+    if (!fn) return c->fail(D2_EINVAL, "no kernel for this tile shape");
+    d2k::Args<T> ab = a;
+    ab.blist = c->d_blist;
+    ab.xstage = xstage;
+    ab.bidx = b;
+    ab.boff = c->bk_off[b];
+    hipLaunchKernelGGL(fn, dim3(c->bk_cap[b]), dim3(64 * waves), shm,
+                       c->stream, ab);
+    HIPCHK(c, hipGetLastError());
+    ++nl;
+  }
   prof_end(c, kKIterBA, pe);
-  ++nl;
   return D2_OK;
 }
 
@@ -568,7 +683,11 @@ std::vector<double> graph_key(const d2_ctx* c, const d2_badmm_params* p) {
   return {(double)p->iters, (double)p->tau, (double)p->fixed_support,
           (double)p->rule, p->eps, p->rho0, (double)c->waves,
           (double)c->nch_cap, (double)c->MP, (double)c->R, (double)c->onfly,
-          (double)c->dt, (double)c->K};
+          (double)c->dt, (double)c->K, (double)c->nbk,
+          (double)c->bk_R[0], (double)c->bk_R[1], (double)c->bk_R[2],
+          (double)c->bk_R[3], (double)c->bk_R[4], (double)c->bk_R[5],
+          (double)c->bk_cap[0], (double)c->bk_cap[1], (double)c->bk_cap[2],
+          (double)c->bk_cap[3], (double)c->bk_cap[4], (double)c->bk_cap[5]};
 }
 
 template <typename T>
@@ -1218,8 +1337,21 @@ d2_status d2_set_schedule(d2_ctx* c, int32_t chunk_instances,
   return D2_OK;
 }
 
+d2_status d2_set_bucketing(d2_ctx* c, int32_t min_pct) {
+  if (!c) return D2_EINVAL;
+  if (min_pct < 0 || min_pct > 100)
+    return c->fail(D2_EINVAL, "bucketing threshold must be in [0, 100]");
+  if (min_pct != c->bucket_min_pct) {
+    c->bucket_min_pct = min_pct;
+    c->lists_valid = false;
+    drop_graph(c);
+  }
+  return D2_OK;
+}
+
 d2_status d2_autotune(d2_ctx* c, const d2_badmm_params* p,
-                      int32_t* chunk_out, int32_t* waves_out, double* ms_out) {
+                      int32_t* chunk_out, int32_t* waves_out,
+                      int32_t* bucket_out, double* ms_out) {
   if (!c) return D2_EINVAL;
   if (!c->N || !c->K || !c->have_labels)
     return c->fail(D2_ESTATE, "need instances, centroids and labels");
@@ -1235,12 +1367,15 @@ d2_status d2_autotune(d2_ctx* c, const d2_badmm_params* p,
   c->prof = false;
   static const int kChunks[] = {16, 32, 64, 128, 256};
   static const int kWaves[] = {2, 4};
+  static const int kBuckets[] = {100, 10};
   double best = INFINITY;
-  int bc = c->chunk_inst, bw = c->waves;
+  int bc = c->chunk_inst, bw = c->waves, bb = c->bucket_min_pct;
   d2_status s = D2_OK;
   for (int ch : kChunks)
-    for (int wv : kWaves) {
+    for (int wv : kWaves)
+      for (int bk : kBuckets) {
       if ((s = d2_set_schedule(c, ch, wv))) break;
+      if ((s = d2_set_bucketing(c, bk))) break;
       double tmin = INFINITY;
       for (int rep = 0; rep < 2 && !s; ++rep) {  // first call captures
         d2_badmm_stats st;
@@ -1256,6 +1391,7 @@ d2_status d2_autotune(d2_ctx* c, const d2_badmm_params* p,
         best = tmin;
         bc = ch;
         bw = wv;
+        bb = bk;
       }
     }
   c->prof = prof;
@@ -1264,8 +1400,10 @@ d2_status d2_autotune(d2_ctx* c, const d2_badmm_params* p,
   c->have_cache = false;
   if (s) return s;
   if ((s = d2_set_schedule(c, bc, bw))) return s;
+  if ((s = d2_set_bucketing(c, bb))) return s;
   if (chunk_out) *chunk_out = bc;
   if (waves_out) *waves_out = bw;
+  if (bucket_out) *bucket_out = bb;
   if (ms_out) *ms_out = best;
   return D2_OK;
 }

@@ -64,6 +64,15 @@ struct d2_ctx {
   double* d_part = nullptr;   // 2 x cap x ps (double-buffered records)
   double* d_partx = nullptr;  // 2 x cap x MP x (d+1) support records
   int* d_nch = nullptr;       // device copy of nchunks
+  // Slot buckets of the hot kernel: chunks hold instances of one bucket;
+  // bucket b (register slots bk_R[b]) is one launch over the chunk ids
+  // d_blist[bk_off[b] .. bk_off[b] + d_bcnt[b]) with grid bk_cap[b].
+  int nbk = 0;
+  int bk_R[6] = {}, bk_cap[6] = {}, bk_off[6] = {}, bk_cnt[6] = {};
+  int32_t* d_blist = nullptr;
+  int* d_bcnt = nullptr;
+  int blist_cap = 0;
+  int bucket_min_pct = 100;  // slot classes under this % of entries merge up
   std::vector<int2> h_ctab;
   bool lists_valid = false;
   // objective trace of the last barycenter

@@ -184,6 +184,9 @@ template <typename T> struct Args {
   const int32_t* work;  // instance ids sorted by cluster
   const Chunk* chunks;  // per workgroup
   const int* nch;       // number of chunks (the grid may be larger)
+  const int32_t* blist; // hot kernel: chunk ids of its slot bucket, or null
+  const int* bcnt;      // per bucket: number of chunk ids
+  int bidx, boff;       // this launch's bucket and its offset in blist
   const int2* ctab;     // per cluster {first chunk, number of chunks}
   const double* ninv;   // per cluster 1 / N_c
   T* P1;
@@ -202,6 +205,7 @@ template <typename T> struct Args {
   double eps;
   int m, d, xs, rule, ps;
   int recost;             // cached cost: recompute from xc and store
+  int xstage;             // centroid support staged in LDS for cost work
 };
 
 struct FinArgs {
@@ -499,18 +503,83 @@ __device__ __forceinline__ void add_support_terms(const Args<T>& a,
                                                   const Tile<T, MP>& tl,
                                                   const T (&b)[NS], T rr,
                                                   double* acc) {
+  using V4 = typename Vec4<T>::type;
   const int lane = threadIdx.x & (kWave - 1);
   const int d = a.d;
   const T ir = rcp_sum(rr);
-  for (int t = 0; t < d; ++t) {
-    T s = T(0);
+  const V4* yv[NS];
 #pragma unroll
-    for (int r = 0; r < NS; ++r)
-      s = fma(b[r], a.X[(tl.o + tl.colc(r)) * a.xs + t], s);
-    s = sum_row<MP>(s);
-    if (lane < MP) acc[lane * (d + 1) + t] += (double)(s * ir);
+  for (int r = 0; r < NS; ++r)
+    yv[r] = reinterpret_cast<const V4*>(a.X + (tl.o + tl.colc(r)) * a.xs);
+  // four coordinates per step (rows of X are xs = roundup(d, 4) long)
+  for (int q = 0; q < (a.xs >> 2); ++q) {
+    T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0);
+#pragma unroll
+    for (int r = 0; r < NS; ++r) {
+      const V4 y = yv[r][q];
+      s0 = fma(b[r], y.x, s0);
+      s1 = fma(b[r], y.y, s1);
+      s2 = fma(b[r], y.z, s2);
+      s3 = fma(b[r], y.w, s3);
+    }
+    s0 = sum_row<MP>(s0);
+    s1 = sum_row<MP>(s1);
+    s2 = sum_row<MP>(s2);
+    s3 = sum_row<MP>(s3);
+    if (lane < MP) {
+      double* ap = acc + lane * (d + 1) + 4 * q;
+      const int t = 4 * q;
+      ap[0] += (double)(s0 * ir);
+      if (t + 1 < d) ap[1] += (double)(s1 * ir);
+      if (t + 2 < d) ap[2] += (double)(s2 * ir);
+      if (t + 3 < d) ap[3] += (double)(s3 * ir);
+    }
   }
   if (lane < MP && rr > T(0)) acc[lane * (d + 1) + d] += 1.0;
+}
+
+// The cluster's support rows in LDS as T, row stride xs + 4 (zero padded
+// past d), for the cost work of a launch (one cluster per workgroup).
+template <typename T, int MP>
+__device__ __forceinline__ void stage_support(const Args<T>& a, int c, T* xl) {
+  const int xsl = a.xs + 4, d = a.d;
+  for (int q = threadIdx.x; q < MP * xsl; q += blockDim.x) {
+    const int i = q / xsl, t = q % xsl;
+    xl[q] = t < d ? (T)a.xc[((int64_t)c * MP + i) * d + t] : T(0);
+  }
+  __syncthreads();
+}
+
+// C_ij = sum_t (x_it - y_jt)^2 for the lane's row and every slot, with x
+// from the LDS stage and y as 4-wide loads (the same sequential sum over t
+// as cost_generic; the zero padding adds exact zeros).
+template <typename T, int MP, int NS>
+__device__ __forceinline__ void cost_tile(const Args<T>& a,
+                                          const Tile<T, MP>& tl, const T* xl,
+                                          T (&cs)[NS]) {
+  using V4 = typename Vec4<T>::type;
+  const V4* xv = reinterpret_cast<const V4*>(xl + tl.ic * (a.xs + 4));
+  const V4* yv[NS];
+#pragma unroll
+  for (int r = 0; r < NS; ++r) {
+    yv[r] = reinterpret_cast<const V4*>(a.X + (tl.o + tl.colc(r)) * a.xs);
+    cs[r] = T(0);
+  }
+  for (int q = 0; q < (a.xs >> 2); ++q) {
+    const V4 x = xv[q];
+#pragma unroll
+    for (int r = 0; r < NS; ++r) {
+      const V4 y = yv[r][q];
+      T df = x.x - y.x;
+      cs[r] = fma(df, df, cs[r]);
+      df = x.y - y.y;
+      cs[r] = fma(df, df, cs[r]);
+      df = x.z - y.z;
+      cs[r] = fma(df, df, cs[r]);
+      df = x.w - y.w;
+      cs[r] = fma(df, df, cs[r]);
+    }
+  }
 }
 
 // Sum the per-wave support accumulators into this chunk's record.
@@ -531,7 +600,7 @@ __device__ __forceinline__ void write_x_record(const double* acc, int nrec,
 template <typename T, int MP, int NS, bool ONFLY>
 __device__ __forceinline__ void ba_tile(const Args<T>& a, const Tile<T, MP>& tl,
                                         const T (&xr)[4], const double* xrow,
-                                        T wi, T rho, T a2, T eps,
+                                        const T* xl, T wi, T rho, T a2, T eps,
                                         double& accw, double& accf,
                                         double* accx) {
   using V4 = typename Vec4<T>::type;
@@ -549,9 +618,14 @@ __device__ __forceinline__ void ba_tile(const Args<T>& a, const Tile<T, MP>& tl,
       const V4 y = reinterpret_cast<const V4*>(a.X)[tl.o + jc];
       cs[r] = cost4<T>(xr, y);
     } else {
-      cs[r] = a.recost ? cost_generic<T>(xrow, a.X + (tl.o + jc) * a.xs, a.d)
-                       : a.Cc[e];
+      if (!a.recost)
+        cs[r] = a.Cc[e];
+      else if (!xl)
+        cs[r] = cost_generic<T>(xrow, a.X + (tl.o + jc) * a.xs, a.d);
     }
+  }
+  if constexpr (!ONFLY) {
+    if (a.recost && xl) cost_tile<T, MP, NS>(a, tl, xl, cs);
   }
 #pragma unroll
   for (int r = 0; r < NS; ++r) {
@@ -583,8 +657,13 @@ __global__ void __launch_bounds__(256) k_iter_ba(Args<T> a) {
   extern __shared__ double s_dyn[];  // [nwaves][MP][d+1] support terms
   __shared__ double s_w[MP];
   __shared__ double s_x[MP * 4];
-  const int ch = blockIdx.x;
-  if (ch >= *a.nch) return;
+  int ch = blockIdx.x;
+  if (a.blist) {
+    if (ch >= a.bcnt[a.bidx]) return;
+    ch = uni(a.blist[a.boff + ch]);
+  } else if (ch >= *a.nch) {
+    return;
+  }
   const Chunk cj = a.chunks[ch];
   const int c = cj.cluster;
   const int2 ct = a.ctab[c];
@@ -615,6 +694,13 @@ __global__ void __launch_bounds__(256) k_iter_ba(Args<T> a) {
     }
   }
   const double* xrow = a.xc + ((int64_t)c * MP + (rowok ? i : 0)) * a.d;
+  T* xl = nullptr;
+  if constexpr (!ONFLY) {
+    if (a.recost && a.xstage) {
+      xl = reinterpret_cast<T*>(s_dyn + (a.xout ? nwaves * nrec : 0));
+      stage_support<T, MP>(a, c, xl);
+    }
+  }
   double accw = 0.0, accf = 0.0;
   // the next tile's offsets (a chain of dependent scalar loads) are fetched
   // while the current tile is loaded and computed
@@ -637,7 +723,7 @@ __global__ void __launch_bounds__(256) k_iter_ba(Args<T> a) {
       pb = a.pofs[k];
     }
     with_slots<R>(tl.nsl, [&]<int NS>() {
-      ba_tile<T, MP, NS, ONFLY>(a, tl, xr, xrow, wi, rho, a2, eps, accw,
+      ba_tile<T, MP, NS, ONFLY>(a, tl, xr, xrow, xl, wi, rho, a2, eps, accw,
                                 accf, accx);
     });
   }
@@ -651,7 +737,7 @@ __global__ void __launch_bounds__(256) k_iter_ba(Args<T> a) {
 template <typename T, int MP, int NS>
 __device__ __forceinline__ void aux_tile(const Args<T>& a, const Tile<T, MP>& tl,
                                          int k, int mode, const double* xrow,
-                                         T wi, T rho, T a2, T eps,
+                                         const T* xl, T wi, T rho, T a2, T eps,
                                          double& accw, double& accf,
                                          double* accx) {
   const int d = a.d;
@@ -666,9 +752,11 @@ __device__ __forceinline__ void aux_tile(const Args<T>& a, const Tile<T, MP>& tl
   }
   if (mode == kRho) {
     T s = T(0);
+    if (xl) cost_tile<T, MP, NS>(a, tl, xl, cs);
 #pragma unroll
     for (int r = 0; r < NS; ++r) {
-      T cv = cost_generic<T>(xrow, a.X + (tl.o + tl.colc(r)) * a.xs, d);
+      T cv = xl ? cs[r]
+                : cost_generic<T>(xrow, a.X + (tl.o + tl.colc(r)) * a.xs, d);
       if (v[r]) {
         if (a.Cc) a.Cc[tl.eidx(r, a.m)] = cv;
         s += cv;
@@ -771,14 +859,19 @@ __global__ void __launch_bounds__(256) k_aux(Args<T> a, int mode) {
   double* accx = s_dyn + (int64_t)wave * nrec;
   if (xrecs)
     for (int q = lane; q < nrec; q += kWave) accx[q] = 0.0;
+  T* xl = nullptr;
+  if (mode == kRho && a.xstage) {
+    xl = reinterpret_cast<T*>(s_dyn);
+    stage_support<T, MP>(a, c, xl);
+  }
   double accw = 0.0, accf = 0.0;
   for (int pos = cj.begin + wave; pos < cj.end; pos += nwaves) {
     Tile<T, MP> tl;
     const int k = uni(a.work[pos]);
     tl.setup(a.off, a.pofs, a.m, k);
     with_slots<R>(tl.nsl, [&]<int NS>() {
-      aux_tile<T, MP, NS>(a, tl, k, mode, xrow, wi, rho, a2, eps, accw, accf,
-                          accx);
+      aux_tile<T, MP, NS>(a, tl, k, mode, xrow, xl, wi, rho, a2, eps, accw,
+                          accf, accx);
     });
   }
   if (mode == kRho) {

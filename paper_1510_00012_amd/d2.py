@@ -29,7 +29,7 @@ EXPORTS = [
     "d2_support_update", "d2_cluster", "d2_objective", "d2_plans_get",
     "d2_sizes", "d2_set_profiling", "d2_kernel_stats", "d2_set_schedule",
     "d2_assign_pairs", "d2_set_graph", "d2_autotune",
-    "d2_objective_feasible", "d2_ws_param_count", "d2_ws_create",
+    "d2_set_bucketing", "d2_objective_feasible", "d2_ws_param_count", "d2_ws_create",
     "d2_ws_destroy", "d2_ws_last_error", "d2_ws_params_set",
     "d2_ws_params_get", "d2_ws_targets_from", "d2_ws_grad",
     "d2_ws_train_step", "d2_ws_propose",
@@ -117,9 +117,10 @@ def load_library(path: str = LIB_PATH):
         "d2_sizes": ([_p, _p, _p, _p, _p, _p], ctypes.c_int),
         "d2_set_profiling": ([_p, _i32], ctypes.c_int),
         "d2_set_schedule": ([_p, _i32, _i32], ctypes.c_int),
+        "d2_set_bucketing": ([_p, _i32], ctypes.c_int),
         "d2_assign_pairs": ([_p, _p, _p], ctypes.c_int),
         "d2_set_graph": ([_p, _i32], ctypes.c_int),
-        "d2_autotune": ([_p, ctypes.POINTER(BadmmParams), _p, _p, _p],
+        "d2_autotune": ([_p, ctypes.POINTER(BadmmParams), _p, _p, _p, _p],
                         ctypes.c_int),
         "d2_kernel_stats": ([_p, ctypes.POINTER(KernelStat), _i32, _p, _i32],
                             ctypes.c_int),
@@ -172,14 +173,16 @@ def schedule_key(offsets, K, m, d, dtype="f32", arch="gfx950"):
 
 
 def tuned_schedule(key):
-    """(chunk, waves) recorded for a workload signature, or None."""
+    """(chunk, waves, bucketing) recorded for a workload signature, or
+    None."""
     import json
     try:
         tab = json.load(open(SCHEDULES))
     except OSError:
         return None
     ent = tab.get(key)
-    return None if ent is None else (int(ent["chunk"]), int(ent["waves"]))
+    return None if ent is None else (int(ent["chunk"]), int(ent["waves"]),
+                                     int(ent.get("bucket", 100)))
 
 
 class D2Context:
@@ -315,20 +318,28 @@ class D2Context:
         return tr, rho
 
     def autotune(self, iters=20, tau=10, rho0=2.0, eps=1e-16, rule=1):
-        """Pick the fastest (chunk, waves) schedule on the current labels."""
+        """Pick the fastest (chunk, waves, bucketing) schedule on the
+        current labels."""
         p = badmm_params(iters, tau, rho0, eps, rule, D2_INIT_PRODUCT)
-        ch, wv, ms = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_double(0)
+        ch, wv, bk = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0)
+        ms = ctypes.c_double(0)
         self._chk(self.lib.d2_autotune(self.h, ctypes.byref(p),
                                        ctypes.byref(ch), ctypes.byref(wv),
-                                       ctypes.byref(ms)))
-        return {"chunk": ch.value, "waves": wv.value, "ms": ms.value}
+                                       ctypes.byref(bk), ctypes.byref(ms)))
+        return {"chunk": ch.value, "waves": wv.value, "bucket": bk.value,
+                "ms": ms.value}
 
     def set_graph(self, on=True):
         self._chk(self.lib.d2_set_graph(self.h, int(bool(on))))
 
-    def set_schedule(self, chunk_instances, waves_per_group):
+    def set_schedule(self, chunk_instances, waves_per_group, bucket=None):
         self._chk(self.lib.d2_set_schedule(self.h, int(chunk_instances),
                                            int(waves_per_group)))
+        if bucket is not None:
+            self.set_bucketing(bucket)
+
+    def set_bucketing(self, min_pct):
+        self._chk(self.lib.d2_set_bucketing(self.h, int(min_pct)))
 
     def set_profiling(self, on=True):
         self._chk(self.lib.d2_set_profiling(self.h, int(bool(on))))

@@ -336,6 +336,7 @@ def test_autotune_then_parity(d2):
         sch = ctx.autotune(iters=10)
         assert sch["chunk"] in (16, 32, 64, 128, 256)
         assert sch["waves"] in (2, 4) and sch["ms"] > 0
+        assert sch["bucket"] in (100, 10)
         X0, W0 = ctx.centroids_get()
         assert np.array_equal(X0, Xc)
         np.testing.assert_allclose(W0, Wc / Wc.sum(1, keepdims=True),
