@@ -140,6 +140,8 @@ void free_instances(d2_ctx* c) {
   dfree(c->d_labels);
   dfree(c->d_best);
   dfree(c->d_evals);
+  dfree(c->d_alist);
+  c->alist_MP = 0;
   dfree(c->d_trace);
   c->trace_cap = 0;
   c->N = c->n = 0;
@@ -857,15 +859,65 @@ d2_status run_assign(d2_ctx* c, const d2_ot_params* p, float* ms_out) {
   a.xs = c->xs;
   a.K = c->K;
   a.iters = p->iters;
+  if (c->alist_MP != c->MP) {
+    // Instance ids grouped by slot class (stable).  The classes run as
+    // separate launches only when the largest needs 8 or more slots (its
+    // kernel holds few wavefronts per SIMD); a class with under 10 % of
+    // the instances then joins the next larger one.  Otherwise one launch.
+    std::vector<uint8_t> cls(c->N);
+    int64_t hist[6] = {0, 0, 0, 0, 0, 0};
+    int top = 0;
+    for (int64_t k = 0; k < c->N; ++k) {
+      cls[k] = (uint8_t)slot_class(c, k);
+      hist[cls[k]]++;
+      top = std::max(top, (int)cls[k]);
+    }
+    int map[6];
+    for (int q = 5, cur = top; q >= 0; --q) {
+      if ((1 << top) >= 8 && hist[q] > 0 && q < top &&
+          hist[q] * 10 >= c->N)
+        cur = q;
+      map[q] = std::min(cur, top);
+    }
+    std::vector<int64_t> cnt(7, 0);
+    for (int64_t k = 0; k < c->N; ++k) {
+      cls[k] = (uint8_t)map[cls[k]];
+      cnt[cls[k] + 1]++;
+    }
+    for (int q = 0; q < 6; ++q) {
+      c->acnt[q] = cnt[q + 1];
+      cnt[q + 1] += cnt[q];
+      c->aofs[q] = cnt[q];
+    }
+    std::vector<int32_t> lst(c->N);
+    std::vector<int64_t> pos(cnt.begin(), cnt.end() - 1);
+    for (int64_t k = 0; k < c->N; ++k) lst[pos[cls[k]]++] = (int32_t)k;
+    if (!c->d_alist) {
+      d2_status s = dalloc(c, (void**)&c->d_alist, sizeof(int32_t) * c->N);
+      if (s) return s;
+    }
+    HIPCHK(c, hipMemcpy(c->d_alist, lst.data(), sizeof(int32_t) * c->N,
+                        hipMemcpyHostToDevice));
+    c->alist_MP = c->MP;
+  }
   const int wpb = 4;
-  int64_t blocks = (c->N + wpb - 1) / wpb;
   HIPCHK(c, hipMemsetAsync(c->d_evals, 0, sizeof(unsigned long long),
                            c->stream));
   HIPCHK(c, hipEventRecord(c->ev0, c->stream));
   hipEvent_t pe = prof_begin(c);
-  hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(64 * wpb),
-                     sizeof(T) * wpb * c->d, c->stream, a);
-  HIPCHK(c, hipGetLastError());
+  // one launch per slot class, each kernel sized for its class
+  for (int q = 0; q < 6; ++q) {
+    if (!c->acnt[q]) continue;
+    auto fq = kt.asg[ilog2(c->MP) - 3][q];
+    if (!fq) return c->fail(D2_EINVAL, "no kernel for this tile shape");
+    d2k::AssignArgs<T> aq = a;
+    aq.list = c->d_alist + c->aofs[q];
+    aq.N = c->acnt[q];
+    const int64_t blocks = (aq.N + wpb - 1) / wpb;
+    hipLaunchKernelGGL(fq, dim3((unsigned)blocks), dim3(64 * wpb),
+                       sizeof(T) * wpb * c->d, c->stream, aq);
+    HIPCHK(c, hipGetLastError());
+  }
   prof_end(c, kKAssign, pe);
   HIPCHK(c, hipEventRecord(c->ev1, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));

@@ -45,6 +45,11 @@ struct d2_ctx {
   void* d_crad = nullptr;  // K centroid support radii
   void* d_xct = nullptr;   // K x MP x xs centroid supports (device dtype)
   int64_t last_evals = 0, last_pairs = 0;
+  // assignment: instance ids grouped by slot class (one launch per class,
+  // each kernel specialised for its class), built for the current pad(m)
+  int32_t* d_alist = nullptr;
+  int alist_MP = 0;
+  int64_t acnt[6] = {}, aofs[6] = {};
   // plans
   void* d_P1 = nullptr;
   void* d_P2 = nullptr;

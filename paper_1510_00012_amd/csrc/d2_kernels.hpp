@@ -941,7 +941,8 @@ template <typename T> struct AssignArgs {
   const T* cmu;         // K x d weighted mean of each centroid's support
   const T* crad;        // K  radius of the support around that mean
   const T* xct;         // K x MP x xs centroid supports in the device dtype
-  int64_t N;
+  const int32_t* list;  // instance ids of this launch (one slot class)
+  int64_t N;            // instances in this launch
   double rho0, eps;
   int m, d, xs, K, iters, prune, prev_valid;
 };
@@ -1178,8 +1179,9 @@ __global__ void __launch_bounds__(256) k_assign(AssignArgs<T> a) {
   extern __shared__ unsigned char s_raw[];  // per wave: d values (mu_P)
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = uni(threadIdx.x / kWave);
-  const int64_t k = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave;
-  if (k >= a.N) return;  // whole wavefront exits together
+  const int64_t q = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave;
+  if (q >= a.N) return;  // whole wavefront exits together
+  const int64_t k = uni(a.list[q]);
   T* smu = reinterpret_cast<T*>(s_raw) + (int64_t)wave * a.d;
   Tile<T, MP> tl;
   tl.setup(a.off, nullptr, a.m, (int)k);
