@@ -597,6 +597,43 @@ __device__ __forceinline__ void write_x_record(const double* acc, int nrec,
 // ---------------------------------------------------------------------------
 // Hot kernel: one launch per B-ADMM iteration (phase B of n, phase A of n+1)
 // ---------------------------------------------------------------------------
+// Raw buffer access (range-checked by the hardware: an offset at or past
+// the resource's size reads 0 and drops a store).  A resource covers one
+// tile, so lanes outside the tile need no clamping, masking or branches.
+using Rsrc = __amdgpu_buffer_rsrc_t;
+constexpr int kRsrcWord3 = 0x00020000;  // 32-bit data format, raw access
+constexpr uint32_t kOob = 0x80000000u;  // an offset past every tile
+
+__device__ __forceinline__ Rsrc make_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0,
+                                           (int)bytes, kRsrcWord3);
+}
+template <typename T> __device__ __forceinline__ T bload(Rsrc r, uint32_t o);
+template <> __device__ __forceinline__ float bload<float>(Rsrc r, uint32_t o) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, o, 0, 0));
+}
+template <> __device__ __forceinline__ double bload<double>(Rsrc r, uint32_t o) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, o, 0, 0));
+}
+template <> __device__ __forceinline__ float4 bload<float4>(Rsrc r, uint32_t o) {
+  return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, o, 0, 0));
+}
+template <> __device__ __forceinline__ double4 bload<double4>(Rsrc r, uint32_t o) {
+  const double2 lo = __builtin_bit_cast(
+      double2, __builtin_amdgcn_raw_buffer_load_b128(r, o, 0, 0));
+  const double2 hi = __builtin_bit_cast(
+      double2, __builtin_amdgcn_raw_buffer_load_b128(r, o + 16u, 0, 0));
+  return make_double4(lo.x, lo.y, hi.x, hi.y);
+}
+__device__ __forceinline__ void bstore(float v, Rsrc r, uint32_t o) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, o, 0, 0);
+}
+__device__ __forceinline__ void bstore(double v, Rsrc r, uint32_t o) {
+  __builtin_amdgcn_raw_buffer_store_b64(
+      __builtin_bit_cast(__attribute__((ext_vector_type(2))) uint32_t, v), r, o,
+      0, 0);
+}
+
 template <typename T, int MP, int NS, bool ONFLY>
 __device__ __forceinline__ void ba_tile(const Args<T>& a, const Tile<T, MP>& tl,
                                         const T (&xr)[4], const double* xrow,
@@ -604,35 +641,37 @@ __device__ __forceinline__ void ba_tile(const Args<T>& a, const Tile<T, MP>& tl,
                                         double& accw, double& accf,
                                         double* accx) {
   using V4 = typename Vec4<T>::type;
+  constexpr uint32_t es = sizeof(T);
+  // one resource per array over this tile (uniform), 32-bit lane offsets;
+  // lanes on rows >= m and columns >= m_k get offsets past the tile
+  const uint32_t tb = (uint32_t)(a.m * tl.mk) * es;
+  const Rsrc rP = make_rsrc(a.P1 + tl.base, tb);
+  const Rsrc rL = make_rsrc(a.L + tl.base, tb);
+  const Rsrc rW = make_rsrc(a.W + tl.o, (uint32_t)tl.mk * es);
+  const Rsrc rX = make_rsrc(a.X + tl.o * a.xs, (uint32_t)(tl.mk * a.xs) * es);
+  Rsrc rC = rP;
+  if constexpr (!ONFLY) rC = make_rsrc(a.Cc + tl.base, tb);
   T p[NS], l[NS], cs[NS], wk[NS], el[NS], b[NS];
-  bool v[NS];
+  uint32_t eo[NS];
 #pragma unroll
   for (int r = 0; r < NS; ++r) {
-    const int64_t e = tl.eidx(r, a.m);
-    const int jc = tl.colc(r);
-    v[r] = tl.valid(r);
-    p[r] = a.P1[e];
-    l[r] = a.L[e];
-    wk[r] = a.W[tl.o + jc];
+    const uint32_t j = (uint32_t)tl.col(r);
+    eo[r] = tl.rowok ? (j * (uint32_t)a.m + (uint32_t)tl.i) * es : kOob;
+    el[r] = tl.valid(r) ? eps : T(0);
+    p[r] = bload<T>(rP, eo[r]);
+    l[r] = bload<T>(rL, eo[r]);
+    wk[r] = bload<T>(rW, j * es);
     if constexpr (ONFLY) {
-      const V4 y = reinterpret_cast<const V4*>(a.X)[tl.o + jc];
-      cs[r] = cost4<T>(xr, y);
+      cs[r] = cost4<T>(xr, bload<V4>(rX, j * (uint32_t)sizeof(V4)));
     } else {
       if (!a.recost)
-        cs[r] = a.Cc[e];
+        cs[r] = bload<T>(rC, eo[r]);
       else if (!xl)
-        cs[r] = cost_generic<T>(xrow, a.X + (tl.o + jc) * a.xs, a.d);
+        cs[r] = cost_generic<T>(xrow, a.X + (tl.o + tl.colc(r)) * a.xs, a.d);
     }
   }
   if constexpr (!ONFLY) {
     if (a.recost && xl) cost_tile<T, MP, NS>(a, tl, xl, cs);
-  }
-#pragma unroll
-  for (int r = 0; r < NS; ++r) {
-    p[r] = v[r] ? p[r] : T(0);
-    l[r] = v[r] ? l[r] : T(0);
-    wk[r] = v[r] ? wk[r] : T(0);
-    el[r] = v[r] ? eps : T(0);
   }
   phase_b<T, MP, NS>(el, p, l, wi, rho, a2);
   T rr, f = T(0);
@@ -641,15 +680,16 @@ __device__ __forceinline__ void ba_tile(const Args<T>& a, const Tile<T, MP>& tl,
   accf += (double)f;
   if (a.xout) add_support_terms<T, MP, NS>(a, tl, b, rr, accx);
 #pragma unroll
-  for (int r = 0; r < NS; ++r)
-    if (v[r]) {
-      const int64_t e = tl.eidx(r, a.m);
-      a.P1[e] = p[r];
-      a.L[e] = l[r];
-      if constexpr (!ONFLY) {
-        if (a.recost) a.Cc[e] = cs[r];
-      }
+  for (int r = 0; r < NS; ++r) {
+    bstore(p[r], rP, eo[r]);
+    bstore(l[r], rL, eo[r]);
+  }
+  if constexpr (!ONFLY) {
+    if (a.recost) {
+#pragma unroll
+      for (int r = 0; r < NS; ++r) bstore(cs[r], rC, eo[r]);
     }
+  }
 }
 
 template <typename T, int MP, int R, bool ONFLY>
