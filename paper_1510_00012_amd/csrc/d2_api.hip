@@ -142,6 +142,7 @@ void free_instances(d2_ctx* c) {
   dfree(c->d_evals);
   dfree(c->d_alist);
   c->alist_MP = 0;
+  c->cls_MP = 0;
   dfree(c->d_trace);
   c->trace_cap = 0;
   c->N = c->n = 0;
@@ -265,6 +266,39 @@ d2_status set_centroids_host(d2_ctx* c, int K, int m, const double* Xc,
   return D2_OK;
 }
 
+struct Upload {
+  void* dst;
+  const void* src;
+  size_t bytes;
+};
+
+// Copy the sources into pinned staging memory and issue the transfers on
+// the context's stream without waiting (later launches on the stream see
+// the data).  The staging memory is reused once the previous batch ended.
+d2_status stage_uploads(d2_ctx* c, const std::vector<Upload>& ups) {
+  size_t total = 0;
+  for (const Upload& u : ups) total += (u.bytes + 255) / 256 * 256;
+  if (c->stage_ev) HIPCHK(c, hipEventSynchronize(c->stage_ev));
+  if (total > c->stage_cap) {
+    if (c->h_stage) HIPCHK(c, hipHostFree(c->h_stage));
+    c->h_stage = nullptr;
+    c->stage_cap = 0;
+    HIPCHK(c, hipHostMalloc((void**)&c->h_stage, total));
+    c->stage_cap = total;
+  }
+  if (!c->stage_ev) HIPCHK(c, hipEventCreateWithFlags(&c->stage_ev,
+                                                      hipEventDisableTiming));
+  size_t o = 0;
+  for (const Upload& u : ups) {
+    std::memcpy(c->h_stage + o, u.src, u.bytes);
+    HIPCHK(c, hipMemcpyAsync(u.dst, c->h_stage + o, u.bytes,
+                             hipMemcpyHostToDevice, c->stream));
+    o += (u.bytes + 255) / 256 * 256;
+  }
+  HIPCHK(c, hipEventRecord(c->stage_ev, c->stream));
+  return D2_OK;
+}
+
 // Slot class of an instance: log2 of the register slots (columns per lane)
 // its tile needs, i.e. the hot-kernel specialisation R = 1 << class.
 int slot_class(const d2_ctx* c, int64_t k) {
@@ -281,16 +315,22 @@ int slot_class(const d2_ctx* c, int64_t k) {
 d2_status build_lists(d2_ctx* c, bool warm_start) {
   const int K = c->K;
   const int64_t N = c->N;
+  if (c->cls_MP != c->MP) {
+    // slot class of every instance and the plan entries per class
+    c->h_cls.resize(N);
+    for (int q = 0; q < 6; ++q) c->cls_ent[q] = 0.0;
+    for (int64_t k = 0; k < N; ++k) {
+      c->h_cls[k] = (uint8_t)slot_class(c, k);
+      c->cls_ent[c->h_cls[k]] += (double)(c->h_off[k + 1] - c->h_off[k]);
+    }
+    c->cls_MP = c->MP;
+  }
+  const uint8_t* cls = c->h_cls.data();
   // buckets: slot classes present, a class with fewer than
   // bucket_min_pct % of the entries joins the next larger bucket
-  double ent[6] = {0, 0, 0, 0, 0, 0}, tot = 0.0;
-  std::vector<uint8_t> cls(N);
-  for (int64_t k = 0; k < N; ++k) {
-    cls[k] = (uint8_t)slot_class(c, k);
-    const double e = (double)(c->h_off[k + 1] - c->h_off[k]);
-    ent[cls[k]] += e;
-    tot += e;
-  }
+  const double* ent = c->cls_ent;
+  double tot = 0.0;
+  for (int q = 0; q < 6; ++q) tot += ent[q];
   int bmap[6];
   std::vector<int> bR;
   {
@@ -306,25 +346,32 @@ d2_status build_lists(d2_ctx* c, bool warm_start) {
   }
   const int nbk = std::max<int>(1, (int)bR.size());
   if (bR.empty()) bR.push_back(1);
-  std::vector<int> bidx_of(6, 0);
+  int bidx_of[6] = {0, 0, 0, 0, 0, 0};
   for (int q = 0; q < 6; ++q)
     for (int b = 0; b < nbk; ++b)
       if (bmap[q] >= 0 && (1 << bmap[q]) == bR[b]) bidx_of[q] = b;
+  // one pass: (cluster, bucket) key per instance and the counts
   std::vector<int64_t> cnt(K, 0), ncols(K, 0);
   std::vector<int64_t> kcnt((size_t)K * nbk, 0);
+  c->h_key.resize(N);
+  uint32_t* key = c->h_key.data();
+  const int32_t* lab = c->h_labels.data();
+  const int64_t* off = c->h_off.data();
   for (int64_t k = 0; k < N; ++k) {
-    const int l = c->h_labels[k];
+    const int l = lab[k];
+    const uint32_t g = (uint32_t)l * nbk + bidx_of[cls[k]];
+    key[k] = g;
     cnt[l]++;
-    ncols[l] += c->h_off[k + 1] - c->h_off[k];
-    kcnt[(size_t)l * nbk + bidx_of[cls[k]]]++;
+    ncols[l] += off[k + 1] - off[k];
+    kcnt[g]++;
   }
   std::vector<int64_t> start((size_t)K * nbk + 1, 0);
   for (size_t q = 0; q < (size_t)K * nbk; ++q) start[q + 1] = start[q] + kcnt[q];
-  std::vector<int32_t> work(N);
+  c->h_work.resize(N);
+  int32_t* work = c->h_work.data();
   {
     std::vector<int64_t> pos(start.begin(), start.end() - 1);
-    for (int64_t k = 0; k < N; ++k)
-      work[pos[(size_t)c->h_labels[k] * nbk + bidx_of[cls[k]]]++] = (int32_t)k;
+    for (int64_t k = 0; k < N; ++k) work[pos[key[k]]++] = (int32_t)k;
   }
   std::vector<d2k::Chunk> chunks;
   std::vector<std::vector<int32_t>> blists(nbk);
@@ -395,34 +442,32 @@ d2_status build_lists(d2_ctx* c, bool warm_start) {
       c->blist_cap = total;
     }
   }
-  std::vector<int32_t> hbl(std::max(1, c->blist_cap), 0);
-  for (int b = 0; b < nbk; ++b) {
-    c->bk_cnt[b] = (int)blists[b].size();
-    std::copy(blists[b].begin(), blists[b].end(), hbl.begin() + c->bk_off[b]);
-  }
+  for (int b = 0; b < nbk; ++b) c->bk_cnt[b] = (int)blists[b].size();
   for (int b = nbk; b < 6; ++b) c->bk_cnt[b] = 0;
-  std::vector<uint8_t> warm(N, 0);
-  if (warm_start && c->have_cache)
+  const bool any_warm = warm_start && c->have_cache;
+  if (any_warm) {
+    c->h_warm.resize(N);
     for (int64_t k = 0; k < N; ++k)
-      warm[k] = c->h_labels[k] == c->h_cache_labels[k];
-  HIPCHK(c, hipMemcpy(c->d_work, work.data(), sizeof(int32_t) * N,
-                      hipMemcpyHostToDevice));
-  HIPCHK(c, hipMemcpy(c->d_chunks, chunks.data(),
-                      sizeof(d2k::Chunk) * std::max<size_t>(1, chunks.size()),
-                      hipMemcpyHostToDevice));
-  HIPCHK(c, hipMemcpy(c->d_ctab, c->h_ctab.data(), sizeof(int2) * K,
-                      hipMemcpyHostToDevice));
-  HIPCHK(c, hipMemcpy(c->d_ninv, ninv.data(), sizeof(double) * K,
-                      hipMemcpyHostToDevice));
-  HIPCHK(c, hipMemcpy(c->d_cinv, cinv.data(), sizeof(double) * K,
-                      hipMemcpyHostToDevice));
-  HIPCHK(c, hipMemcpy(c->d_warm, warm.data(), N, hipMemcpyHostToDevice));
-  HIPCHK(c, hipMemcpy(c->d_nch, &c->nchunks, sizeof(int),
-                      hipMemcpyHostToDevice));
-  HIPCHK(c, hipMemcpy(c->d_bcnt, c->bk_cnt, sizeof(int) * 6,
-                      hipMemcpyHostToDevice));
-  HIPCHK(c, hipMemcpy(c->d_blist, hbl.data(), sizeof(int32_t) * hbl.size(),
-                      hipMemcpyHostToDevice));
+      c->h_warm[k] = lab[k] == c->h_cache_labels[k];
+  } else {
+    HIPCHK(c, hipMemsetAsync(c->d_warm, 0, N, c->stream));
+  }
+  std::vector<Upload> ups = {
+      {c->d_work, work, sizeof(int32_t) * N},
+      {c->d_chunks, chunks.data(),
+       sizeof(d2k::Chunk) * std::max<size_t>(1, chunks.size())},
+      {c->d_ctab, c->h_ctab.data(), sizeof(int2) * K},
+      {c->d_ninv, ninv.data(), sizeof(double) * K},
+      {c->d_cinv, cinv.data(), sizeof(double) * K},
+      {c->d_nch, &c->nchunks, sizeof(int)},
+      {c->d_bcnt, c->bk_cnt, sizeof(int) * 6}};
+  if (any_warm) ups.push_back({c->d_warm, c->h_warm.data(), (size_t)N});
+  for (int b = 0; b < nbk; ++b)
+    if (!blists[b].empty())
+      ups.push_back({c->d_blist + c->bk_off[b], blists[b].data(),
+                     sizeof(int32_t) * blists[b].size()});
+  d2_status su = stage_uploads(c, ups);
+  if (su) return su;
   c->lists_valid = true;
   return D2_OK;
 }
@@ -781,50 +826,60 @@ int slots_for(const d2_ctx* c) {
 
 // Per-centroid mean (weights of the centroid) and support radius around it,
 // for the cheap assignment lower bound; the radius is rounded up slightly.
+// Per-centroid quantities of the assignment's lower bounds: the weighted
+// mean of the support, the largest distance of a support point from it
+// (inflated by 1e-6 relative so that rounding cannot make a bound
+// invalid), and the support in the device dtype with row stride xs.  One
+// wavefront per centroid, FP64 sums in index order.
+template <typename T>
+__global__ void __launch_bounds__(64)
+    k_cstats(const double* xc, const double* wc, int m, int MP, int d,
+             int xs, T* cmu, T* crad, T* xct) {
+  extern __shared__ double s_mu[];  // d
+  const int q = blockIdx.x, l = threadIdx.x;
+  const double* xq = xc + (size_t)q * MP * d;
+  const double* wq = wc + (size_t)q * MP;
+  for (int e = l; e < MP * xs; e += 64) {
+    const int i = e / xs, t = e % xs;
+    xct[(size_t)q * MP * xs + e] = t < d ? (T)xq[(size_t)i * d + t] : T(0);
+  }
+  double ws = 0.0;
+  for (int i = 0; i < m; ++i) ws += wq[i];
+  const double div = ws > 0 ? ws : 1.0;
+  for (int t = l; t < d; t += 64) {
+    double s = 0.0;
+    for (int i = 0; i < m; ++i) s += wq[i] * xq[(size_t)i * d + t] / div;
+    s_mu[t] = s;
+    cmu[(size_t)q * d + t] = (T)s;
+  }
+  __syncthreads();
+  double r = 0.0;
+  for (int i = l; i < m; i += 64) {
+    double s = 0.0;
+    for (int t = 0; t < d; ++t) {
+      const double df = xq[(size_t)i * d + t] - s_mu[t];
+      s += df * df;
+    }
+    r = fmax(r, sqrt(s));
+  }
+  for (int o = 32; o > 0; o >>= 1) r = fmax(r, __shfl_xor(r, o));
+  if (l == 0) crad[q] = (T)(r * (1.0 + 1e-6) + 1e-30);
+}
+
 template <typename T>
 d2_status centroid_stats(d2_ctx* c) {
-  const int K = c->K, m = c->m, MP = c->MP, d = c->d;
-  std::vector<double> hx((size_t)K * MP * d), hw((size_t)K * MP);
-  HIPCHK(c, hipMemcpy(hx.data(), c->d_xc, hx.size() * 8,
-                      hipMemcpyDeviceToHost));
-  HIPCHK(c, hipMemcpy(hw.data(), c->d_wc, hw.size() * 8,
-                      hipMemcpyDeviceToHost));
-  std::vector<T> mu((size_t)K * d), rad(K);
-  std::vector<T> xt((size_t)K * MP * c->xs, T(0));
-  for (size_t q = 0; q < (size_t)K * MP; ++q)
-    for (int t = 0; t < d; ++t) xt[q * c->xs + t] = (T)hx[q * d + t];
-  for (int q = 0; q < K; ++q) {
-    std::vector<double> mq(d, 0.0);
-    double ws = 0.0;
-    for (int i = 0; i < m; ++i) ws += hw[(size_t)q * MP + i];
-    for (int i = 0; i < m; ++i)
-      for (int t = 0; t < d; ++t)
-        mq[t] += hw[(size_t)q * MP + i] * hx[((size_t)q * MP + i) * d + t] /
-                 (ws > 0 ? ws : 1.0);
-    double rmax = 0.0;
-    for (int i = 0; i < m; ++i) {
-      double s = 0.0;
-      for (int t = 0; t < d; ++t) {
-        double df = hx[((size_t)q * MP + i) * d + t] - mq[t];
-        s += df * df;
-      }
-      rmax = std::max(rmax, std::sqrt(s));
-    }
-    for (int t = 0; t < d; ++t) mu[(size_t)q * d + t] = (T)mq[t];
-    rad[q] = (T)(rmax * (1.0 + 1e-6) + 1e-30);
-  }
+  const int K = c->K, MP = c->MP, d = c->d;
   if (!c->d_cmu) {
     d2_status s;
     if ((s = dalloc(c, &c->d_cmu, sizeof(T) * (size_t)K * d))) return s;
     if ((s = dalloc(c, &c->d_crad, sizeof(T) * (size_t)K))) return s;
-    if ((s = dalloc(c, &c->d_xct, sizeof(T) * xt.size()))) return s;
+    if ((s = dalloc(c, &c->d_xct, sizeof(T) * (size_t)K * MP * c->xs)))
+      return s;
   }
-  HIPCHK(c, hipMemcpy(c->d_xct, xt.data(), sizeof(T) * xt.size(),
-                      hipMemcpyHostToDevice));
-  HIPCHK(c, hipMemcpy(c->d_cmu, mu.data(), sizeof(T) * mu.size(),
-                      hipMemcpyHostToDevice));
-  HIPCHK(c, hipMemcpy(c->d_crad, rad.data(), sizeof(T) * rad.size(),
-                      hipMemcpyHostToDevice));
+  hipLaunchKernelGGL(k_cstats<T>, dim3(K), dim3(64), sizeof(double) * d,
+                     c->stream, c->d_xc, c->d_wc, c->m, MP, d, c->xs,
+                     (T*)c->d_cmu, (T*)c->d_crad, (T*)c->d_xct);
+  HIPCHK(c, hipGetLastError());
   return D2_OK;
 }
 
@@ -990,6 +1045,8 @@ void d2_destroy(d2_ctx* c) {
     (void)hipEventDestroy(p.b);
   }
   for (auto e : c->ev_pool) (void)hipEventDestroy(e);
+  if (c->stage_ev) (void)hipEventDestroy(c->stage_ev);
+  if (c->h_stage) (void)hipHostFree(c->h_stage);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);

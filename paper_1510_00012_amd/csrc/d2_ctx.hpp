@@ -77,7 +77,19 @@ struct d2_ctx {
   int32_t* d_blist = nullptr;
   int* d_bcnt = nullptr;
   int blist_cap = 0;
-  int bucket_min_pct = 100;  // slot classes under this % of entries merge up
+  int bucket_min_pct = 100;
+  // pinned staging for the per-call list uploads (one host copy, async
+  // transfers; stage_ev marks the end of the last batch of transfers)
+  uint8_t* h_stage = nullptr;
+  size_t stage_cap = 0;
+  hipEvent_t stage_ev = nullptr;
+  // per-instance slot class for the current pad(m), and reused host lists
+  std::vector<uint8_t> h_cls;
+  int cls_MP = 0;
+  double cls_ent[6] = {};
+  std::vector<uint32_t> h_key;
+  std::vector<int32_t> h_work;
+  std::vector<uint8_t> h_warm;  // slot classes under this % of entries merge up
   std::vector<int2> h_ctab;
   bool lists_valid = false;
   // objective trace of the last barycenter
