@@ -346,3 +346,57 @@ def test_autotune_then_parity(d2):
         for c in range(4):
             if tr[c] is not None:
                 assert _rel(g_tr[:, c], tr[c]) < 1e-5
+
+
+@pytest.mark.parametrize("name,N,K,m", [("cfg3", 1200, 5, 32),
+                                        ("cfg4", 1500, 4, 16)])
+def test_assignment_split_by_slot_class(d2, name, N, K, m):
+    """Larger tiles (d = 64 / 16, m_k up to 64 / 32): the assignment runs
+    one launch per slot class; labels and distances as in
+    test_assignment."""
+    print(f"[assign split {name}]", flush=True)
+    wl = make_workload(name, N=N)
+    mem = pick_init_members(wl["offsets"], K, m, 21)
+    Xc, Wc = oracle.init_centroids(wl, mem, m)
+    lab_o, best_o, dist_o = oracle.assign(wl, Xc, Wc, T=100, want_dist=True)
+    srt = np.sort(dist_o, axis=1)
+    margin = (srt[:, 1] - srt[:, 0]) / srt[:, 0]
+    with _ctx(d2, wl, "f32") as ctx:
+        ctx.centroids_set(Xc, Wc)
+        lab_g, best_g, _ = ctx.assign(iters=100)
+    assert _rel(best_g, best_o) < 1e-5
+    ok = (lab_g == lab_o) | (margin < 1e-5)
+    assert ok.all(), np.nonzero(~ok)
+
+
+def test_slot_buckets_match_oracle(d2):
+    """The plan update split into one launch per slot bucket (threshold 0:
+    every class present its own launch; 100: one launch) gives the same
+    centroids and objective trace, against the oracle, on the d = 64
+    shape whose m_k spans four slot classes."""
+    print("[slot buckets]", flush=True)
+    wl = make_workload("cfg3", N=1500)
+    mem = pick_init_members(wl["offsets"], 3, 32, 4)
+    Xc, Wc = oracle.init_centroids(wl, mem, 32)
+    lab, _, _ = oracle.assign(wl, Xc, Wc, T=30)
+    Xo, Wo, tr, _, plans = oracle_barycenters(wl, lab, Xc, Wc, T=30, tau=10)
+    res = {}
+    with _ctx(d2, wl, "f32") as ctx:
+        for pct in (0, 10, 100):
+            ctx.set_bucketing(pct)
+            ctx.centroids_set(Xc, Wc)
+            ctx.labels_set(lab)
+            st = ctx.barycenter(iters=30, tau=10, init=d2.D2_INIT_PRODUCT)
+            g_tr, _ = ctx.objective(30)
+            Xg, Wg = ctx.centroids_get()
+            for c in range(3):
+                if tr[c] is not None:
+                    assert _rel(g_tr[:, c], tr[c]) < 1e-5, (pct, c)
+            assert np.abs(Wg - Wo).max() < 1e-5, pct
+            assert np.abs(Xg - Xo).max() < 1e-5, pct
+            me = marginal_errors(ctx, wl, plans, range(0, 1500, 50))
+            assert me < 1e-6, pct
+            res[pct] = (st["launches"], Xg)
+    # more buckets, more launches per iteration
+    assert res[0][0] > res[100][0]
+    np.testing.assert_allclose(res[0][1], res[100][1], rtol=0, atol=1e-6)
