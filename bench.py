@@ -218,7 +218,7 @@ def main():
     # per-kernel durations: further rounds with every launch bracketed by
     # HIP events on the context's stream (kernels inside a replayed graph
     # cannot be bracketed individually)
-    ev, tot = ctx.assign_pairs()
+    ev_pairs, all_pairs = ctx.assign_pairs()
     ctx.set_profiling(True)
     ctx.kernel_stats(reset=True)
     for _ in range(args.profile_rounds):
@@ -240,7 +240,8 @@ def main():
         avg_s = tot / launches / 1000.0
         if kind == "assign":
             ach = assign_exps(wl, K, m, T_assign,
-                              ev / tot if tot else 1.0) / avg_s / 1e9
+                              ev_pairs / all_pairs if all_pairs else 1.0
+                              ) / avg_s / 1e9
             return {"bound": "alu", "achieved": ach, "peak": EXP_PEAK_GOPS,
                     "unit": "Gexp/s", "frac": ach / EXP_PEAK_GOPS,
                     "traffic": None, "kernel": "k_assign",
@@ -283,7 +284,8 @@ def main():
                      "waves_per_group": sched.get("waves"),
                      "bucketing_min_pct": sched.get("bucket"),
                      "source": sched.get("source")},
-        "assign_pairs_evaluated_frac": ev / tot if tot else None,
+        "assign_pairs_evaluated_frac": (ev_pairs / all_pairs
+                                        if all_pairs else None),
         "kernel_timing": "HIP events around each launch on the context "
                          f"stream, {args.profile_rounds} host-issued rounds "
                          "after the timed rounds",
