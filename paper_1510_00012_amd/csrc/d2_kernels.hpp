@@ -475,7 +475,12 @@ template <typename T, int MP>
 __device__ __forceinline__ double consensus_term(T rr, bool rowok, int rule) {
   T tot = sum_col<MP>(rowok ? rr : T(0));
   T wt = rowok ? rr * rcp_sum(tot) : T(0);
-  return (double)(rule == 2 ? dsqrt(wt) : wt);
+  // R2 takes the square root (hardware sqrt for FP32, about 1 ulp: a
+  // select over the IEEE-rounded expansion would run on every tile)
+  if constexpr (sizeof(T) == 4)
+    return (double)(rule == 2 ? __builtin_amdgcn_sqrtf(wt) : wt);
+  else
+    return (double)(rule == 2 ? dsqrt(wt) : wt);
 }
 
 // chunk record: per-row weight sums (lanes < MP of each wave) + objective
