@@ -180,6 +180,13 @@ d2_status d2_cluster(d2_ctx* ctx, int32_t rounds, const d2_badmm_params* bp,
 d2_status d2_objective(d2_ctx* ctx, double* trace, int32_t max_iters,
                        double* rho);
 
+/* Primal residual trace of the last d2_barycenter: residual[n*K + c] =
+ * (1/N_c) sum_k sum_ij |Pi1^(k)_ij - Pi2^(k)_ij| after iteration n, the
+ * violation of the splitting constraint Pi1 = Pi2 whose multiplier
+ * Eq. (badmm2) updates (0 for empty clusters); `max_iters` bounds the rows
+ * written. */
+d2_status d2_residual(d2_ctx* ctx, double* residual, int32_t max_iters);
+
 /* Plans of instance k after the last d2_barycenter, each m x m_k
  * column-major (Pi1, Pi2, Lambda); any pointer may be NULL. */
 d2_status d2_plans_get(d2_ctx* ctx, int64_t k, double* P1, double* P2,

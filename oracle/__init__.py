@@ -71,7 +71,8 @@ def _load():
     lib.orc_barycenter.argtypes = [
         ctypes.c_int64, _i64p, _i64p, ctypes.c_int, _f64p, _f64p, ctypes.c_int,
         _f64p, _f64p, _u8p, _f64p, _f64p, _f64p, ctypes.c_double, ctypes.c_int,
-        ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int, _f64p, _f64p]
+        ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int, _f64p, _f64p,
+        _f64p]
     lib.orc_barycenter.restype = ctypes.c_int
     lib.orc_ot.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _f64p,
                            _f64p, _f64p, _f64p, ctypes.c_double, ctypes.c_int,
@@ -160,7 +161,8 @@ def barycenter(wl, members, x, w, plans=None, warm=None, rho0=2.0, tau=10,
                T=100, eps=1e-16, rule=1, xplan=0):
     """B-ADMM barycenter of the instances `members` (Algorithm B-ADMM).
 
-    Returns dict(x, w, ftrace, rho, plans).  `plans` (a Plans) is updated in
+    Returns dict(x, w, ftrace, rtrace, rho, plans); rtrace[n] is the
+    residual (1/N) sum_k sum_ij |Pi1 - Pi2| after iteration n.  `plans` (a Plans) is updated in
     place; warm[q] != 0 starts member q from its cached Pi2 in plans.P2.
     """
     off, X, W = wl["offsets"], wl["X"], wl["W"]
@@ -172,16 +174,18 @@ def barycenter(wl, members, x, w, plans=None, warm=None, rho0=2.0, tau=10,
     xo, wo = _f64(x).copy(), _f64(w).copy()
     wa = None if warm is None else np.ascontiguousarray(warm, dtype=np.uint8)
     ftr = np.zeros(max(T, 1))
+    rtr = np.zeros(max(T, 1))
     rho = np.zeros(1)
     rc = _load().orc_barycenter(
         len(mem), _p(mem, _i64p), _p(off, _i64p), d, _p(X, _f64p), _p(W, _f64p),
         m, _p(xo, _f64p), _p(wo, _f64p), _p(wa, _u8p), _p(plans.P1, _f64p),
         _p(plans.P2, _f64p), _p(plans.L, _f64p), float(rho0), int(tau), int(T),
-        float(eps), int(rule), int(xplan), _p(ftr, _f64p), _p(rho, _f64p))
+        float(eps), int(rule), int(xplan), _p(ftr, _f64p), _p(rtr, _f64p),
+        _p(rho, _f64p))
     if rc != 0:
         raise ValueError("orc_barycenter: bad arguments")
-    return {"x": xo, "w": wo, "ftrace": ftr[:T], "rho": float(rho[0]),
-            "plans": plans}
+    return {"x": xo, "w": wo, "ftrace": ftr[:T], "rtrace": rtr[:T],
+            "rho": float(rho[0]), "plans": plans}
 
 
 def badmm_ot(x, w, y, wy, rho0=2.0, T=100, eps=1e-16, return_plans=False):

@@ -129,14 +129,18 @@ int orc_ward_merge(int mk, int d, const double* y, const double* wy, int m,
  * cached plan when warm[k] != 0 (warm may be NULL); otherwise Pi2^0 is the
  * product w_i w^(k)_j.  On exit P1, P2, L hold the last iterate, x and w the
  * new centroid, ftrace[n] = (1/N) sum_k <C^(k), Pi1^(k)> of iteration n with
- * the cost used in that iteration, and *rho_out the rho used.
+ * the cost used in that iteration, rtrace[n] = (1/N) sum_k sum_ij
+ * |Pi1_ij - Pi2_ij| (the residual of the splitting constraint Pi1 = Pi2
+ * whose multiplier Eq. (badmm2) updates) after iteration n, and *rho_out the
+ * rho used.  ftrace and rtrace may be NULL.
  * Returns 0, or -1 on bad arguments.
  */
 int orc_barycenter(int64_t nmem, const int64_t* mem, const int64_t* off, int d,
                    const double* X, const double* W, int m, double* x,
                    double* w, const uint8_t* warm, double* P1, double* P2,
                    double* L, double rho0, int tau, int T, double eps, int rule,
-                   int xplan, double* ftrace, double* rho_out) {
+                   int xplan, double* ftrace, double* rtrace,
+                   double* rho_out) {
   if (nmem <= 0 || m < 1 || d < 1 || T < 0 || tau < 1) return -1;
   /* local cost storage: member q's block starts at coff[q] */
   int64_t* coff = (int64_t*)malloc(sizeof(int64_t) * (size_t)(nmem + 1));
@@ -151,6 +155,7 @@ int orc_barycenter(int64_t nmem, const int64_t* mem, const int64_t* off, int d,
   double* R = (double*)malloc(sizeof(double) * (size_t)nmem * m);  /* r^(k) */
   double* Wt = (double*)malloc(sizeof(double) * (size_t)nmem * m); /* w~^(k) */
   double* Fq = (double*)malloc(sizeof(double) * (size_t)nmem);
+  double* Rq = (double*)malloc(sizeof(double) * (size_t)nmem);
 
   /* cost blocks at the initial support */
 #pragma omp parallel for schedule(static)
@@ -239,19 +244,27 @@ int orc_barycenter(int64_t nmem, const int64_t* mem, const int64_t* off, int d,
       int64_t k = mem[q];
       int mk = (int)(off[k + 1] - off[k]);
       int64_t base = (int64_t)m * off[k];
+      double rq = 0.0;
       for (int j = 0; j < mk; ++j)
         for (int i = 0; i < m; ++i) {
           int64_t e = base + (int64_t)j * m + i;
           double p2 = P2[e] / R[q * m + i] * w[i];
           P2[e] = p2;
           L[e] += rho * (P1[e] - p2);
+          rq += fabs(P1[e] - p2);
         }
+      Rq[q] = rq;
     }
 
     if (ftrace) {
       double f = 0.0;
       for (int64_t q = 0; q < nmem; ++q) f += Fq[q];
       ftrace[n] = f / (double)nmem;
+    }
+    if (rtrace) {
+      double r = 0.0;
+      for (int64_t q = 0; q < nmem; ++q) r += Rq[q];
+      rtrace[n] = r / (double)nmem;
     }
 
     /* support update, Eq. (updatex), every tau iterations */
@@ -287,6 +300,7 @@ int orc_barycenter(int64_t nmem, const int64_t* mem, const int64_t* off, int d,
   free(R);
   free(Wt);
   free(Fq);
+  free(Rq);
   return 0;
 }
 

@@ -144,6 +144,7 @@ void free_instances(d2_ctx* c) {
   c->alist_MP = 0;
   c->cls_MP = 0;
   dfree(c->d_trace);
+  dfree(c->d_rtrace);
   c->trace_cap = 0;
   c->N = c->n = 0;
   c->have_labels = false;
@@ -574,6 +575,8 @@ d2k::Args<T> make_args(d2_ctx* c, const d2_badmm_params* p) {
   a.xin = nullptr;
   a.xout = nullptr;
   a.trace = nullptr;
+  a.rtrace = nullptr;
+  a.rlast = 0;
   a.recost = 0;
   a.xstage = 0;
   a.eps = p ? p->eps : 1e-16;
@@ -588,6 +591,8 @@ d2k::Args<T> make_args(d2_ctx* c, const d2_badmm_params* p) {
 d2k::FinArgs make_fin(d2_ctx* c, const d2_badmm_params* p) {
   d2k::FinArgs f;
   f.ctab = c->d_ctab;
+  f.ninv = c->d_ninv;
+  f.rtr = nullptr;
   f.cinv = c->d_cinv;
   f.part = c->d_part;
   f.xrec = c->d_partx;
@@ -705,6 +710,8 @@ d2_status issue_barycenter(d2_ctx* c, const d2_badmm_params* p, int& nl) {
     a.part_in = rec[n & 1];      // records of A_n -> w^{n+1}, F(n)
     a.part = rec[(n + 1) & 1];   // records of A_{n+1}
     a.trace = c->d_trace + (size_t)n * K;
+    // residual of phase B_{n-1} (computed by the previous launch)
+    a.rtrace = n > 0 ? c->d_rtrace + (size_t)(n - 1) * K : nullptr;
     // support records of A_n (support update after iteration n)
     const bool xin = xupd(n);
     a.xin = (xin && c->onfly) ? xrec[n & 1] : nullptr;
@@ -718,7 +725,12 @@ d2_status issue_barycenter(d2_ctx* c, const d2_badmm_params* p, int& nl) {
       a.recost = 1;
     }
     if (n == T_ - 1) {
+      a.rlast = 1;
       if ((s = launch_aux<T>(c, a, d2k::kBF, nl))) return s;
+      a.rlast = 0;
+      f.part = a.part;
+      f.rtr = c->d_rtrace + (size_t)n * K;
+      if ((s = launch_fin(c, f, d2k::kFinRes, nl))) return s;
     } else {
       if ((s = launch_ba<T>(c, a, nl))) return s;
     }
@@ -744,11 +756,16 @@ d2_status run_barycenter(d2_ctx* c, const d2_badmm_params* p,
   if (T_ > c->trace_cap) {
     drop_graph(c);
     dfree(c->d_trace);
+    dfree(c->d_rtrace);
     d2_status s = dalloc(c, (void**)&c->d_trace, sizeof(double) * T_ * K);
     if (s) return s;
+    if ((s = dalloc(c, (void**)&c->d_rtrace, sizeof(double) * T_ * K)))
+      return s;
     c->trace_cap = T_;
   }
   HIPCHK(c, hipMemsetAsync(c->d_trace, 0, sizeof(double) * T_ * K,
+                           c->stream));
+  HIPCHK(c, hipMemsetAsync(c->d_rtrace, 0, sizeof(double) * T_ * K,
                            c->stream));
   int nl = 0;
   bool graphed = false;
@@ -1369,6 +1386,19 @@ d2_status d2_objective(d2_ctx* c, double* trace, int32_t max_iters,
                         hipMemcpyDeviceToHost));
   if (rho)
     HIPCHK(c, hipMemcpy(rho, c->d_rho, sizeof(double) * c->K,
+                        hipMemcpyDeviceToHost));
+  return D2_OK;
+}
+
+d2_status d2_residual(d2_ctx* c, double* residual, int32_t max_iters) {
+  if (!c) return D2_EINVAL;
+  if (!c->trace_rows) return c->fail(D2_ESTATE, "no barycenter yet");
+  if (!residual) return c->fail(D2_EINVAL, "null output");
+  HIPCHK(c, hipSetDevice(c->device));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  int rows = std::min(max_iters, c->trace_rows);
+  if (rows > 0)
+    HIPCHK(c, hipMemcpy(residual, c->d_rtrace, sizeof(double) * rows * c->K,
                         hipMemcpyDeviceToHost));
   return D2_OK;
 }

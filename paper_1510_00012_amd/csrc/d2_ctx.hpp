@@ -94,6 +94,7 @@ struct d2_ctx {
   bool lists_valid = false;
   // objective trace of the last barycenter
   double* d_trace = nullptr;
+  double* d_rtrace = nullptr;  // residual trace, same shape as d_trace
   int trace_cap = 0, trace_rows = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   // captured launch sequence of d2_barycenter

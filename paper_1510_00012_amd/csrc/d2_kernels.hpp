@@ -170,7 +170,7 @@ enum Mode : int {
   kXO = 5,   // support records from the stored Pi2 only
 };
 // Finalisation modes (per-cluster launches).
-enum FinMode : int { kFinRho = 1, kFinX = 2 };
+enum FinMode : int { kFinRho = 1, kFinX = 2, kFinRes = 3 };
 
 struct Chunk {
   int32_t cluster, begin, end, pad;
@@ -202,6 +202,8 @@ template <typename T> struct Args {
   const double* xin;      // support records of the previous phase A or null
   double* xout;           // support records of this launch's phase A or null
   double* trace;          // K objective values of the previous phase A
+  double* rtrace;         // K residuals of the previous launch's phase B
+  int rlast;              // kBF: write this launch's residual records
   double eps;
   int m, d, xs, rule, ps;
   int recost;             // cached cost: recompute from xc and store
@@ -210,6 +212,8 @@ template <typename T> struct Args {
 
 struct FinArgs {
   const int2* ctab;     // per cluster {first chunk, number of chunks}
+  const double* ninv;   // per cluster 1 / N_c
+  double* rtr;          // kFinRes: K residuals of the last phase B
   const double* cinv;   // per cluster 1 / (m * sum_k m_k)
   const double* part;
   const double* xrec;
@@ -359,10 +363,10 @@ __device__ __forceinline__ void cluster_weights(const Args<T>& a, int c,
                                                 int2 ct, bool publish,
                                                 double* s_w) {
   __shared__ double s_red[256];
-  __shared__ double s_out[MP + 1];
+  __shared__ double s_out[MP + 2];
   __shared__ double s_vs;
   const int tid = threadIdx.x, nt = blockDim.x;
-  sum_cluster_records(a.part_in + (int64_t)ct.x * a.ps, a.ps, ct.y, MP + 1,
+  sum_cluster_records(a.part_in + (int64_t)ct.x * a.ps, a.ps, ct.y, MP + 2,
                       s_red, s_out);
   const double ni = a.ninv[c];
   for (int q = tid; q < MP; q += nt) {
@@ -375,6 +379,7 @@ __device__ __forceinline__ void cluster_weights(const Args<T>& a, int c,
     for (int q = 0; q < MP; ++q) vs += s_w[q];
     s_vs = vs;
     if (publish && a.trace) a.trace[c] = s_out[MP] * ni;
+    if (publish && a.rtrace) a.rtrace[c] = s_out[MP + 1] * ni;
   }
   __syncthreads();
   for (int q = tid; q < MP; q += nt) {
@@ -425,7 +430,8 @@ __device__ __forceinline__ void cluster_support(const Args<T>& a, int c,
 // Pi2 = Pi1~ w_i / r_i, Lambda += rho (Pi1 - Pi2).  In: p = Pi1; out: p = Pi2.
 template <typename T, int MP, int NS>
 __device__ __forceinline__ void phase_b(const T (&el)[NS], T (&p)[NS],
-                                        T (&l)[NS], T wi, T rho, T a2) {
+                                        T (&l)[NS], T wi, T rho, T a2,
+                                        T& res) {
   T bv[NS];
   T rs = T(0);
 #pragma unroll
@@ -438,7 +444,9 @@ __device__ __forceinline__ void phase_b(const T (&el)[NS], T (&p)[NS],
 #pragma unroll
   for (int r = 0; r < NS; ++r) {
     T p2 = bv[r] * coef;
-    l[r] = fma(rho, p[r] - p2, l[r]);
+    const T dp = p[r] - p2;
+    l[r] = fma(rho, dp, l[r]);
+    res += fabs(dp);
     p[r] = p2;
   }
 }
@@ -486,15 +494,20 @@ __device__ __forceinline__ double consensus_term(T rr, bool rowok, int rule) {
 // chunk record: per-row weight sums (lanes < MP of each wave) + objective
 template <int MP>
 __device__ __forceinline__ void write_w_record(double accw, double accf,
-                                               double* part, int ps, int ch) {
-  __shared__ double s_w[4][MP + 1];
+                                               double accr, double* part,
+                                               int ps, int ch) {
+  __shared__ double s_w[4][MP + 2];
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = threadIdx.x / kWave, nwaves = blockDim.x / kWave;
   accf = sum_wave(accf);
+  accr = sum_wave(accr);
   if (lane < MP) s_w[wave][lane] = accw;
-  if (lane == 0) s_w[wave][MP] = accf;
+  if (lane == 0) {
+    s_w[wave][MP] = accf;
+    s_w[wave][MP + 1] = accr;
+  }
   __syncthreads();
-  if (threadIdx.x <= MP) {
+  if (threadIdx.x <= MP + 1) {
     double s = 0.0;
     for (int q = 0; q < nwaves; ++q) s += s_w[q][threadIdx.x];
     part[(int64_t)ch * ps + threadIdx.x] = s;
@@ -644,7 +657,7 @@ __device__ __forceinline__ void ba_tile(const Args<T>& a, const Tile<T, MP>& tl,
                                         const T (&xr)[4], const double* xrow,
                                         const T* xl, T wi, T rho, T a2, T eps,
                                         double& accw, double& accf,
-                                        double* accx) {
+                                        double& accr, double* accx) {
   using V4 = typename Vec4<T>::type;
   constexpr uint32_t es = sizeof(T);
   // one resource per array over this tile (uniform), 32-bit lane offsets;
@@ -678,7 +691,9 @@ __device__ __forceinline__ void ba_tile(const Args<T>& a, const Tile<T, MP>& tl,
   if constexpr (!ONFLY) {
     if (a.recost && xl) cost_tile<T, MP, NS>(a, tl, xl, cs);
   }
-  phase_b<T, MP, NS>(el, p, l, wi, rho, a2);
+  T res = T(0);
+  phase_b<T, MP, NS>(el, p, l, wi, rho, a2, res);
+  accr += (double)res;
   T rr, f = T(0);
   phase_a<T, MP, NS>(el, p, l, cs, wk, a2, b, rr, f);
   accw += consensus_term<T, MP>(rr, tl.rowok, a.rule);
@@ -746,7 +761,7 @@ __global__ void __launch_bounds__(256) k_iter_ba(Args<T> a) {
       stage_support<T, MP>(a, c, xl);
     }
   }
-  double accw = 0.0, accf = 0.0;
+  double accw = 0.0, accf = 0.0, accr = 0.0;
   // the next tile's offsets (a chain of dependent scalar loads) are fetched
   // while the current tile is loaded and computed
   int pos = cj.begin + wave;
@@ -769,10 +784,10 @@ __global__ void __launch_bounds__(256) k_iter_ba(Args<T> a) {
     }
     with_slots<R>(tl.nsl, [&]<int NS>() {
       ba_tile<T, MP, NS, ONFLY>(a, tl, xr, xrow, xl, wi, rho, a2, eps, accw,
-                                accf, accx);
+                                accf, accr, accx);
     });
   }
-  write_w_record<MP>(accw, accf, a.part, a.ps, ch);
+  write_w_record<MP>(accw, accf, accr, a.part, a.ps, ch);
   if (a.xout) write_x_record(s_dyn, nrec, a.xout, ch);
 }
 
@@ -784,7 +799,7 @@ __device__ __forceinline__ void aux_tile(const Args<T>& a, const Tile<T, MP>& tl
                                          int k, int mode, const double* xrow,
                                          const T* xl, T wi, T rho, T a2, T eps,
                                          double& accw, double& accf,
-                                         double* accx) {
+                                         double& accr, double* accx) {
   const int d = a.d;
   const int lane = threadIdx.x & (kWave - 1);
   T p[NS], l[NS], cs[NS], wk[NS], el[NS], b[NS];
@@ -846,7 +861,9 @@ __device__ __forceinline__ void aux_tile(const Args<T>& a, const Tile<T, MP>& tl
       p[r] = v[r] ? p[r] : T(0);
       l[r] = v[r] ? l[r] : T(0);
     }
-    phase_b<T, MP, NS>(el, p, l, wi, rho, a2);
+    T res = T(0);
+    phase_b<T, MP, NS>(el, p, l, wi, rho, a2, res);
+    accr += (double)res;
 #pragma unroll
     for (int r = 0; r < NS; ++r)
       if (v[r]) {
@@ -909,14 +926,14 @@ __global__ void __launch_bounds__(256) k_aux(Args<T> a, int mode) {
     xl = reinterpret_cast<T*>(s_dyn);
     stage_support<T, MP>(a, c, xl);
   }
-  double accw = 0.0, accf = 0.0;
+  double accw = 0.0, accf = 0.0, accr = 0.0;
   for (int pos = cj.begin + wave; pos < cj.end; pos += nwaves) {
     Tile<T, MP> tl;
     const int k = uni(a.work[pos]);
     tl.setup(a.off, a.pofs, a.m, k);
     with_slots<R>(tl.nsl, [&]<int NS>() {
       aux_tile<T, MP, NS>(a, tl, k, mode, xrow, xl, wi, rho, a2, eps, accw,
-                          accf, accx);
+                          accf, accr, accx);
     });
   }
   if (mode == kRho) {
@@ -930,7 +947,10 @@ __global__ void __launch_bounds__(256) k_aux(Args<T> a, int mode) {
       a.part[(int64_t)ch * a.ps] = s;
     }
   } else if (mode == kA0) {
-    write_w_record<MP>(accw, accf, a.part, a.ps, ch);
+    write_w_record<MP>(accw, accf, 0.0, a.part, a.ps, ch);
+  } else if (mode == kBF && a.rlast) {
+    // residual of the last phase B (summed per cluster by k_fin kFinRes)
+    write_w_record<MP>(0.0, 0.0, accr, a.part, a.ps, ch);
   }
   if (xrecs) write_x_record(s_dyn, nrec, a.xout, ch);
 }
@@ -957,6 +977,18 @@ __global__ void __launch_bounds__(256) k_fin(FinArgs f, int mode) {
       const double den = s_x[ii * (f.d + 1) + f.d];
       if (ii < f.m && den > 0.0)
         f.xc[((int64_t)c * MP + ii) * f.d + t] = s_x[ii * (f.d + 1) + t] / den;
+    }
+    return;
+  }
+  if (mode == kFinRes) {
+    // residual of the last phase B: column MP + 1 of its records
+    s_red[tid] = sum_strided(f.part + (int64_t)ct.x * f.ps + MP + 1, f.ps, tid,
+                             ct.y, nt);
+    __syncthreads();
+    if (tid == 0) {
+      double t = 0.0;
+      for (int gI = 0; gI < nt; ++gI) t += s_red[gI];
+      f.rtr[c] = t * f.ninv[c];
     }
     return;
   }

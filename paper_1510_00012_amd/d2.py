@@ -29,7 +29,7 @@ EXPORTS = [
     "d2_support_update", "d2_cluster", "d2_objective", "d2_plans_get",
     "d2_sizes", "d2_set_profiling", "d2_kernel_stats", "d2_set_schedule",
     "d2_assign_pairs", "d2_set_graph", "d2_autotune",
-    "d2_set_bucketing", "d2_objective_feasible", "d2_ws_param_count", "d2_ws_create",
+    "d2_set_bucketing", "d2_objective_feasible", "d2_residual", "d2_ws_param_count", "d2_ws_create",
     "d2_ws_destroy", "d2_ws_last_error", "d2_ws_params_set",
     "d2_ws_params_get", "d2_ws_targets_from", "d2_ws_grad",
     "d2_ws_train_step", "d2_ws_propose",
@@ -113,6 +113,7 @@ def load_library(path: str = LIB_PATH):
         "d2_cluster": ([_p, _i32, ctypes.POINTER(BadmmParams),
                         ctypes.POINTER(OtParams), ROUND_CB, _p], ctypes.c_int),
         "d2_objective": ([_p, _p, _i32, _p], ctypes.c_int),
+        "d2_residual": ([_p, _p, _i32], ctypes.c_int),
         "d2_plans_get": ([_p, _i64, _p, _p, _p], ctypes.c_int),
         "d2_sizes": ([_p, _p, _p, _p, _p, _p], ctypes.c_int),
         "d2_set_profiling": ([_p, _i32], ctypes.c_int),
@@ -316,6 +317,12 @@ class D2Context:
         self._chk(self.lib.d2_objective(self.h, _ptr(tr), int(iters),
                                         _ptr(rho)))
         return tr, rho
+
+    def residual(self, iters):
+        """(iters, K) primal residual trace of the last barycenter."""
+        r = np.zeros((iters, self.K))
+        self._chk(self.lib.d2_residual(self.h, _ptr(r), int(iters)))
+        return r
 
     def autotune(self, iters=20, tau=10, rho0=2.0, eps=1e-16, rule=1):
         """Pick the fastest (chunk, waves, bucketing) schedule on the

@@ -4,16 +4,21 @@ import numpy as np
 import oracle
 
 
-def oracle_barycenters(wl, labels, Xc, Wc, plans=None, warm=None, **kw):
+def oracle_barycenters(wl, labels, Xc, Wc, plans=None, warm=None,
+                       residuals=None, **kw):
     """Oracle B-ADMM for every non-empty cluster of `labels`.
 
-    Returns (Xc', Wc', traces[K] (T each, None when empty), rhos, plans)."""
+    Returns (Xc', Wc', traces[K] (T each, None when empty), rhos, plans);
+    if `residuals` is a list it receives the residual traces (per cluster,
+    None when empty)."""
     K, m, d = Xc.shape
     n = int(wl["offsets"][-1])
     if plans is None:
         plans = oracle.Plans(m, n)
     Xo, Wo = Xc.copy(), Wc.copy()
     traces, rhos = [None] * K, np.zeros(K)
+    if residuals is not None:
+        residuals.extend([None] * K)
     for c in range(K):
         mem = np.nonzero(labels == c)[0]
         if len(mem) == 0:
@@ -23,6 +28,8 @@ def oracle_barycenters(wl, labels, Xc, Wc, plans=None, warm=None, **kw):
                                 **kw)
         Xo[c], Wo[c] = out["x"], out["w"]
         traces[c], rhos[c] = out["ftrace"], out["rho"]
+        if residuals is not None:
+            residuals[c] = out["rtrace"]
     return Xo, Wo, traces, rhos, plans
 
 

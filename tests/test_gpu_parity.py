@@ -44,12 +44,18 @@ def test_single_cluster_barycenter(d2, dtype, tol):
     mem = pick_init_members(wl["offsets"], 1, 8, wl["seed"])
     Xc, Wc = oracle.init_centroids(wl, mem, 8)
     lab = np.zeros(256, dtype=np.int32)
-    Xo, Wo, tr, rhos, plans = oracle_barycenters(wl, lab, Xc, Wc, T=200)
+    res_o = []
+    Xo, Wo, tr, rhos, plans = oracle_barycenters(wl, lab, Xc, Wc, T=200,
+                                                 residuals=res_o)
     with _ctx(d2, wl, dtype) as ctx:
         ctx.centroids_set(Xc, Wc)
         ctx.labels_set(lab)
         st = ctx.barycenter(iters=200, tau=10, init=d2.D2_INIT_PRODUCT)
         g_tr, g_rho = ctx.objective(200)
+        g_res = ctx.residual(200)
+        # primal residual (1/N) sum |Pi1 - Pi2| after every iteration
+        assert np.abs(g_res[:, 0] - res_o[0]).max() < (
+            1e-12 if dtype == "f64" else 1e-6)
         Xg, Wg = ctx.centroids_get()
         assert _rel(g_rho, rhos) < (1e-12 if dtype == "f64" else 1e-6)
         assert _rel(g_tr[:, 0], tr[0]) < tol, np.max(np.abs(g_tr[:, 0] / tr[0] - 1))
@@ -70,8 +76,9 @@ def test_multi_cluster_barycenter_ragged(d2, dtype):
     mem = pick_init_members(wl["offsets"], K, 16, 11)
     Xc, Wc = oracle.init_centroids(wl, mem, 16)
     lab, _, _ = oracle.assign(wl, Xc[:4], Wc[:4], T=50)
+    res_o = []
     Xo, Wo, tr, rhos, plans = oracle_barycenters(wl, lab, Xc, Wc, T=60,
-                                                 tau=10)
+                                                 tau=10, residuals=res_o)
     tol = 1e-10 if dtype == "f64" else 1e-5
     with _ctx(d2, wl, dtype) as ctx:
         ctx.centroids_set(Xc, Wc)
@@ -79,6 +86,11 @@ def test_multi_cluster_barycenter_ragged(d2, dtype):
         st = ctx.barycenter(iters=60, tau=10, init=d2.D2_INIT_PRODUCT)
         assert st["n_empty"] == 1
         g_tr, _ = ctx.objective(60)
+        g_res = ctx.residual(60)
+        for c in range(4):
+            assert np.abs(g_res[:, c] - res_o[c]).max() < (
+                1e-12 if dtype == "f64" else 1e-6), c
+        assert np.all(g_res[:, 4] == 0)
         Xg, Wg = ctx.centroids_get()
         for c in range(4):
             assert _rel(g_tr[:, c], tr[c]) < tol, (c, _rel(g_tr[:, c], tr[c]))
