@@ -10,7 +10,7 @@ if ROOT not in sys.path:
 
 def pytest_configure(config):
     config.addinivalue_line(
-        "markers", "gpu: needs an MI355X (gfx950) GPU; run on the GPU box")
+        "markers", "gpu: needs an MI355X (gfx950) GPU")
     config.addinivalue_line(
         "markers", "slow: a CPU test that takes more than a few seconds")
 
