@@ -663,8 +663,17 @@ d2_status launch_ba(d2_ctx* c, const d2k::Args<T>& a, int& nl) {
   size_t shm = a.xout ? per_wave * waves : 0;
   if (xstage) shm += stage;
   hipEvent_t pe = prof_begin(c);
+  // support-update launches (d >= 32) and cost-recomputation launches
+  // (MP = 32, d <= 64) of large-d FP32 contexts use the MFMA kernels
+  const bool xo = a.xout && !a.recost && !c->onfly && c->d >= 32 &&
+                  c->d <= 64 && kt.bax[ilog2(c->MP) - 3][0] != nullptr;
+  const bool cx = a.recost && xstage && !a.xout && c->d <= 64 &&
+                  c->MP == 32 && kt.bcx[0] != nullptr;
   for (int b = 0; b < c->nbk; ++b) {
-    auto fn = kt.ba[c->onfly ? 1 : 0][ilog2(c->MP) - 3][ilog2(c->bk_R[b])];
+    const int rb = ilog2(c->bk_R[b]);
+    auto fn = xo   ? kt.bax[ilog2(c->MP) - 3][rb]
+              : cx ? kt.bcx[rb]
+                   : kt.ba[c->onfly ? 1 : 0][ilog2(c->MP) - 3][rb];
     if (!fn) return c->fail(D2_EINVAL, "no kernel for this tile shape");
     d2k::Args<T> ab = a;
     ab.blist = c->d_blist;

@@ -17,9 +17,12 @@
 // 64-entry run of the column-major tile.  Column sums reduce over the MP
 // lanes of a column group with DPP row operations; row sums add the slots
 // in-lane and then combine column groups (DPP row_ror / ds_swizzle /
-// bpermute).  Loads of a tile are issued unconditionally (inactive lanes read
-// a clamped in-bounds element and are masked afterwards) so that all of a
-// tile's loads are in flight together.
+// bpermute).  The hot kernel reads and writes a tile through buffer
+// resources that cover exactly the tile, so lanes outside it read zeros and
+// drop their stores without clamps or branches, and all of a tile's loads
+// are in flight together (other kernels clamp to an in-bounds element and
+// mask).  For d > 4 the support-update sums of a tile run on the matrix
+// cores (FP32 MFMA), the tile layout being the A operand.
 //
 // A workgroup processes one "chunk": a run of instances of one cluster from
 // the cluster-sorted work list, and writes double records per chunk
@@ -41,6 +44,8 @@
 //   BF       last launch: prologue, B_{T-1}, store Pi2 (the warm-start cache)
 #pragma once
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 #include <stdint.h>
 
 namespace d2k {
@@ -652,12 +657,123 @@ __device__ __forceinline__ void bstore(double v, Rsrc r, uint32_t o) {
       0, 0);
 }
 
-template <typename T, int MP, int NS, bool ONFLY>
+// Support-update sums on the matrix cores (FP32 MFMA, d <= 64, MP = 32 or
+// 16, cost cached): u_i = sum_j Pi1~_ij y_j / r_i for all rows of a tile
+// is the product (MP x m_k) . (m_k x d).  The register layout of the tile
+// is already the A operand: lane l holds row l % MP of column
+// (l / MP) + (64 / MP) r in slot r, i.e. A[i][k] of a K = 64 / MP step.
+// The B operand is each lane's own column's coordinates, so one slot is one
+// MFMA per 32 (or 16) coordinates.  The tile's sums are added to the
+// wavefront's FP64 accumulators in LDS.
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+constexpr int kMfmaMaxD = 64;
+constexpr int kVarNone = 0, kVarSupport = 1, kVarCost = 2;
+
+template <int MP, int NS>
+__device__ __forceinline__ void support_mfma(const Args<float>& a,
+                                             const Tile<float, MP>& tl,
+                                             const float (&b)[NS], float rr,
+                                             Rsrc rX, double* acc) {
+  static_assert(MP == 16 || MP == 32, "MFMA support sums: MP 16 or 32");
+  constexpr int NT = kMfmaMaxD / MP;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int d = a.d;
+  const float ir = rcp_sum(rr);
+  const int tn = lane % MP;
+  using Acc = typename std::conditional<MP == 32, f32x16, f32x4>::type;
+  constexpr int NV = MP == 32 ? 16 : 4;
+  Acc s[NT];
+#pragma unroll
+  for (int q = 0; q < NT; ++q)
+#pragma unroll
+    for (int v = 0; v < NV; ++v) s[q][v] = 0.0f;
+#pragma unroll
+  for (int r = 0; r < NS; ++r) {
+    const float av = b[r] * ir;
+    const uint32_t j = (uint32_t)tl.col(r);
+#pragma unroll
+    for (int q = 0; q < NT; ++q) {
+      if (q * MP < d) {
+        const int t = q * MP + tn;
+        const uint32_t o =
+            t < d ? (j * (uint32_t)a.xs + (uint32_t)t) * 4u : kOob;
+        const float yv = bload<float>(rX, o);
+        if constexpr (MP == 32)
+          s[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, yv, s[q], 0, 0, 0);
+        else
+          s[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, yv, s[q], 0, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < NT; ++q) {
+    const int t = q * MP + tn;
+    if (q * MP < d && t < d) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const int i = MP == 32 ? 8 * (v / 4) + 4 * (lane / 32) + (v % 4)
+                               : 4 * (lane / 16) + v;
+        acc[i * (d + 1) + t] += (double)s[q][v];
+      }
+    }
+  }
+  if (lane < MP && rr > 0.0f) acc[lane * (d + 1) + d] += 1.0;
+}
+
+// Cost recomputation on the matrix cores (FP32 MFMA 32x32x2, MP = 32,
+// d <= 64): C_ij = |x_i|^2 + |y_j|^2 - 2 x_i . y_j for a 32-column block
+// as D^T = Y' X^T with Y' = the block's points in a permuted order, chosen
+// so that the accumulator layout (lane: row i = l % 32; register v: column
+// 8 (v/4) + 4 (l/32) + v % 4 of the block) is the tile's slot layout
+// (register v holds slot 16 b + v, column 32 b + l / 32 + 2 v).  The point
+// norms are summed from the loaded coordinates; one more MFMA step with
+// K = (|y|^2, 1) x (1, |x|^2) adds the norms.  Negative rounding residue is
+// clamped to 0.
+template <int NS>
+__device__ __forceinline__ void cost_mfma(const Args<float>& a,
+                                          const Tile<float, 32>& tl,
+                                          const float* xl, float xnorm,
+                                          Rsrc rX, float (&cs)[NS]) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int n = lane & 31, h = lane >> 5;
+  const int xsl = a.xs + 4;
+  const float* xrow = xl + n * xsl;  // B operand: x_i, i = lane % 32
+  constexpr int NB = (NS + 15) / 16;
+#pragma unroll
+  for (int bk = 0; bk < NB; ++bk) {
+    // A operand row n: column 32 bk + g + 8 q + 2 s of the tile
+    const int q = n >> 3, g = (n >> 2) & 1, sI = n & 3;
+    const uint32_t jn = (uint32_t)(32 * bk + g + 8 * q + 2 * sI);
+    const uint32_t base = jn * (uint32_t)a.xs * 4u;
+    f32x16 acc;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
+    float yy = 0.0f;
+    for (int k0 = 0; k0 < a.d; k0 += 2) {
+      const int t = k0 + h;
+      const float y = bload<float>(rX, base + (uint32_t)t * 4u);
+      yy = fmaf(y, y, yy);
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(-2.0f * y, xrow[t], acc, 0,
+                                                 0, 0);
+    }
+    yy += __shfl_xor(yy, 32);
+    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(h == 0 ? yy : 1.0f,
+                                               h == 0 ? 1.0f : xnorm, acc, 0,
+                                               0, 0);
+#pragma unroll
+    for (int v = 0; v < 16; ++v)
+      if (16 * bk + v < NS) cs[16 * bk + v] = fmaxf(acc[v], 0.0f);
+  }
+}
+
+template <typename T, int MP, int NS, bool ONFLY, int VAR>
 __device__ __forceinline__ void ba_tile(const Args<T>& a, const Tile<T, MP>& tl,
                                         const T (&xr)[4], const double* xrow,
-                                        const T* xl, T wi, T rho, T a2, T eps,
-                                        double& accw, double& accf,
-                                        double& accr, double* accx) {
+                                        const T* xl, T xnorm, T wi, T rho,
+                                        T a2, T eps, double& accw,
+                                        double& accf, double& accr,
+                                        double* accx) {
   using V4 = typename Vec4<T>::type;
   constexpr uint32_t es = sizeof(T);
   // one resource per array over this tile (uniform), 32-bit lane offsets;
@@ -684,11 +800,14 @@ __device__ __forceinline__ void ba_tile(const Args<T>& a, const Tile<T, MP>& tl,
     } else {
       if (!a.recost)
         cs[r] = bload<T>(rC, eo[r]);
-      else if (!xl)
+      else if (VAR != kVarCost && !xl)
         cs[r] = cost_generic<T>(xrow, a.X + (tl.o + tl.colc(r)) * a.xs, a.d);
     }
   }
-  if constexpr (!ONFLY) {
+  if constexpr (VAR == kVarCost) {
+    // cost recomputation launch of a d <= 64 FP32 context (matrix cores)
+    cost_mfma<NS>(a, tl, xl, xnorm, rX, cs);
+  } else if constexpr (!ONFLY) {
     if (a.recost && xl) cost_tile<T, MP, NS>(a, tl, xl, cs);
   }
   T res = T(0);
@@ -698,7 +817,6 @@ __device__ __forceinline__ void ba_tile(const Args<T>& a, const Tile<T, MP>& tl,
   phase_a<T, MP, NS>(el, p, l, cs, wk, a2, b, rr, f);
   accw += consensus_term<T, MP>(rr, tl.rowok, a.rule);
   accf += (double)f;
-  if (a.xout) add_support_terms<T, MP, NS>(a, tl, b, rr, accx);
 #pragma unroll
   for (int r = 0; r < NS; ++r) {
     bstore(p[r], rP, eo[r]);
@@ -710,9 +828,20 @@ __device__ __forceinline__ void ba_tile(const Args<T>& a, const Tile<T, MP>& tl,
       for (int r = 0; r < NS; ++r) bstore(cs[r], rC, eo[r]);
     }
   }
+  if constexpr (VAR == kVarSupport) {
+    // support-update launch of a large-d FP32 context (matrix cores)
+    support_mfma<MP, NS>(a, tl, b, rr, rX, accx);
+  } else {
+    if (a.xout) add_support_terms<T, MP, NS>(a, tl, b, rr, accx);
+  }
 }
 
-template <typename T, int MP, int R, bool ONFLY>
+// VAR: kVarSupport / kVarCost are kernels only for the launches that form
+// the support-update sums / recompute the cost (each once per tau
+// iterations) of FP32 contexts with large d, on the matrix cores; separate
+// kernels so that their registers do not lower the occupancy of the other
+// iterations.
+template <typename T, int MP, int R, bool ONFLY, int VAR = kVarNone>
 __global__ void __launch_bounds__(256) k_iter_ba(Args<T> a) {
   extern __shared__ double s_dyn[];  // [nwaves][MP][d+1] support terms
   __shared__ double s_w[MP];
@@ -755,10 +884,18 @@ __global__ void __launch_bounds__(256) k_iter_ba(Args<T> a) {
   }
   const double* xrow = a.xc + ((int64_t)c * MP + (rowok ? i : 0)) * a.d;
   T* xl = nullptr;
+  T xnorm = T(0);
   if constexpr (!ONFLY) {
     if (a.recost && a.xstage) {
       xl = reinterpret_cast<T*>(s_dyn + (a.xout ? nwaves * nrec : 0));
       stage_support<T, MP>(a, c, xl);
+      if constexpr (VAR == kVarCost) {
+        // |x_i|^2 of the lane's row, in index order
+        for (int t = 0; t < a.d; ++t) {
+          const T v = xl[i * (a.xs + 4) + t];
+          xnorm = fma(v, v, xnorm);
+        }
+      }
     }
   }
   double accw = 0.0, accf = 0.0, accr = 0.0;
@@ -783,8 +920,8 @@ __global__ void __launch_bounds__(256) k_iter_ba(Args<T> a) {
       pb = a.pofs[k];
     }
     with_slots<R>(tl.nsl, [&]<int NS>() {
-      ba_tile<T, MP, NS, ONFLY>(a, tl, xr, xrow, xl, wi, rho, a2, eps, accw,
-                                accf, accr, accx);
+      ba_tile<T, MP, NS, ONFLY, VAR>(a, tl, xr, xrow, xl, xnorm, wi, rho, a2,
+                                     eps, accw, accf, accr, accx);
     });
   }
   write_w_record<MP>(accw, accf, accr, a.part, a.ps, ch);
@@ -1283,6 +1420,8 @@ template <typename T> struct KernTable {
   using AX = void (*)(Args<T>, int);
   using AS = void (*)(AssignArgs<T>);
   BA ba[2][4][6] = {};  // [onfly][mp][r]
+  BA bax[4][6] = {};    // support-update launches, FP32, d > 4, MP 16 / 32
+  BA bcx[6] = {};       // cost-recomputation launches, FP32, d <= 64, MP 32
   AX aux[4][6] = {};
   AS asg[4][6] = {};
 };

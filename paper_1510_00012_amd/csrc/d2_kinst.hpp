@@ -11,6 +11,10 @@ template <typename T, int MP, int R> void add_kernels(KernTable<T>& t) {
   constexpr int a = clog2(MP) - 3, b = clog2(R);
   t.ba[0][a][b] = &k_iter_ba<T, MP, R, false>;
   t.ba[1][a][b] = &k_iter_ba<T, MP, R, true>;
+  if constexpr (sizeof(T) == 4 && (MP == 16 || MP == 32))
+    t.bax[a][b] = &k_iter_ba<T, MP, R, false, kVarSupport>;
+  if constexpr (sizeof(T) == 4 && MP == 32)
+    t.bcx[b] = &k_iter_ba<T, MP, R, false, kVarCost>;
   t.aux[a][b] = &k_aux<T, MP, R>;
   t.asg[a][b] = &k_assign<T, MP, R>;
 }

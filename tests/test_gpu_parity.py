@@ -139,13 +139,16 @@ def test_edge_shapes(d2):
             assert me < 1e-6
 
 
-def test_large_d_cached_cost_path(d2):
+@pytest.mark.parametrize("name,m", [("cfg3", 32), ("cfg4", 16)])
+def test_large_d_cached_cost_path(d2, name, m):
     """d=64 (word-vector-bag shape, bf16-exact unit vectors), m=32, m_k in
-    [8,64]: the cost is cached per support update instead of recomputed."""
-    print("[large_d]", flush=True)
-    wl = make_workload("cfg3", N=1500)
-    mem = pick_init_members(wl["offsets"], 3, 32, 4)
-    Xc, Wc = oracle.init_centroids(wl, mem, 32)
+    [8,64], and d=16 (m=16, m_k in [4,32]): the cost is cached per support
+    update instead of recomputed, and the support-update sums run on the
+    matrix cores."""
+    print(f"[large_d {name}]", flush=True)
+    wl = make_workload(name, N=1500)
+    mem = pick_init_members(wl["offsets"], 3, m, 4)
+    Xc, Wc = oracle.init_centroids(wl, mem, m)
     lab, _, _ = oracle.assign(wl, Xc, Wc, T=30)
     Xo, Wo, tr, _, plans = oracle_barycenters(wl, lab, Xc, Wc, T=30, tau=10)
     with _ctx(d2, wl, "f32") as ctx:
