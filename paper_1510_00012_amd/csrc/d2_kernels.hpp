@@ -670,24 +670,52 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int kMfmaMaxD = 64;
 constexpr int kVarNone = 0, kVarSupport = 1, kVarCost = 2;
 
+// Per-wavefront FP32 accumulators of the support sums (MFMA layout) and of
+// the row indicators, added to the wavefront's FP64 LDS record once after
+// its last tile.
+template <int MP> struct SupAcc {
+  static constexpr int NT = kMfmaMaxD / MP;
+  static constexpr int NV = MP == 32 ? 16 : 4;
+  using V = typename std::conditional<MP == 32, f32x16, f32x4>::type;
+  V s[NT];
+  float den;
+  __device__ __forceinline__ void zero() {
+#pragma unroll
+    for (int q = 0; q < NT; ++q)
+#pragma unroll
+      for (int v = 0; v < NV; ++v) s[q][v] = 0.0f;
+    den = 0.0f;
+  }
+  __device__ __forceinline__ void flush(int d, double* acc) const {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int tn = lane % MP;
+#pragma unroll
+    for (int q = 0; q < NT; ++q) {
+      const int t = q * MP + tn;
+      if (q * MP < d && t < d) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          const int i = MP == 32 ? 8 * (v / 4) + 4 * (lane / 32) + (v % 4)
+                                 : 4 * (lane / 16) + v;
+          acc[i * (d + 1) + t] += (double)s[q][v];
+        }
+      }
+    }
+    if (lane < MP) acc[lane * (d + 1) + d] += (double)den;
+  }
+};
+
 template <int MP, int NS>
 __device__ __forceinline__ void support_mfma(const Args<float>& a,
                                              const Tile<float, MP>& tl,
                                              const float (&b)[NS], float rr,
-                                             Rsrc rX, double* acc) {
+                                             Rsrc rX, SupAcc<MP>& sa) {
   static_assert(MP == 16 || MP == 32, "MFMA support sums: MP 16 or 32");
-  constexpr int NT = kMfmaMaxD / MP;
+  constexpr int NT = SupAcc<MP>::NT;
   const int lane = threadIdx.x & (kWave - 1);
   const int d = a.d;
   const float ir = rcp_sum(rr);
   const int tn = lane % MP;
-  using Acc = typename std::conditional<MP == 32, f32x16, f32x4>::type;
-  constexpr int NV = MP == 32 ? 16 : 4;
-  Acc s[NT];
-#pragma unroll
-  for (int q = 0; q < NT; ++q)
-#pragma unroll
-    for (int v = 0; v < NV; ++v) s[q][v] = 0.0f;
 #pragma unroll
   for (int r = 0; r < NS; ++r) {
     const float av = b[r] * ir;
@@ -700,25 +728,15 @@ __device__ __forceinline__ void support_mfma(const Args<float>& a,
             t < d ? (j * (uint32_t)a.xs + (uint32_t)t) * 4u : kOob;
         const float yv = bload<float>(rX, o);
         if constexpr (MP == 32)
-          s[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, yv, s[q], 0, 0, 0);
+          sa.s[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, yv, sa.s[q], 0, 0,
+                                                         0);
         else
-          s[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, yv, s[q], 0, 0, 0);
+          sa.s[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, yv, sa.s[q], 0, 0,
+                                                         0);
       }
     }
   }
-#pragma unroll
-  for (int q = 0; q < NT; ++q) {
-    const int t = q * MP + tn;
-    if (q * MP < d && t < d) {
-#pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        const int i = MP == 32 ? 8 * (v / 4) + 4 * (lane / 32) + (v % 4)
-                               : 4 * (lane / 16) + v;
-        acc[i * (d + 1) + t] += (double)s[q][v];
-      }
-    }
-  }
-  if (lane < MP && rr > 0.0f) acc[lane * (d + 1) + d] += 1.0;
+  if (lane < MP && rr > 0.0f) sa.den += 1.0f;
 }
 
 // Cost recomputation on the matrix cores (FP32 MFMA 32x32x2, MP = 32,
@@ -773,7 +791,7 @@ __device__ __forceinline__ void ba_tile(const Args<T>& a, const Tile<T, MP>& tl,
                                         const T* xl, T xnorm, T wi, T rho,
                                         T a2, T eps, double& accw,
                                         double& accf, double& accr,
-                                        double* accx) {
+                                        double* accx, SupAcc<MP>* sa) {
   using V4 = typename Vec4<T>::type;
   constexpr uint32_t es = sizeof(T);
   // one resource per array over this tile (uniform), 32-bit lane offsets;
@@ -830,7 +848,7 @@ __device__ __forceinline__ void ba_tile(const Args<T>& a, const Tile<T, MP>& tl,
   }
   if constexpr (VAR == kVarSupport) {
     // support-update launch of a large-d FP32 context (matrix cores)
-    support_mfma<MP, NS>(a, tl, b, rr, rX, accx);
+    support_mfma<MP, NS>(a, tl, b, rr, rX, *sa);
   } else {
     if (a.xout) add_support_terms<T, MP, NS>(a, tl, b, rr, accx);
   }
@@ -899,6 +917,12 @@ __global__ void __launch_bounds__(256) k_iter_ba(Args<T> a) {
     }
   }
   double accw = 0.0, accf = 0.0, accr = 0.0;
+  SupAcc<(MP == 16 || MP == 32) ? MP : 32> sacc;
+  SupAcc<MP>* sap = nullptr;
+  if constexpr (VAR == kVarSupport) {
+    sacc.zero();
+    sap = &sacc;
+  }
   // the next tile's offsets (a chain of dependent scalar loads) are fetched
   // while the current tile is loaded and computed
   int pos = cj.begin + wave;
@@ -921,9 +945,10 @@ __global__ void __launch_bounds__(256) k_iter_ba(Args<T> a) {
     }
     with_slots<R>(tl.nsl, [&]<int NS>() {
       ba_tile<T, MP, NS, ONFLY, VAR>(a, tl, xr, xrow, xl, xnorm, wi, rho, a2,
-                                     eps, accw, accf, accr, accx);
+                                     eps, accw, accf, accr, accx, sap);
     });
   }
+  if constexpr (VAR == kVarSupport) sacc.flush(a.d, accx);
   write_w_record<MP>(accw, accf, accr, a.part, a.ps, ch);
   if (a.xout) write_x_record(s_dyn, nrec, a.xout, ch);
 }
