@@ -415,3 +415,30 @@ def test_slot_buckets_match_oracle(d2):
     # more buckets, more launches per iteration
     assert res[0][0] > res[100][0]
     np.testing.assert_allclose(res[0][1], res[100][1], rtol=0, atol=1e-6)
+
+
+@pytest.mark.parametrize("d,m,mk_hi", [(37, 20, 40), (33, 13, 50)])
+def test_matrix_core_paths_ragged(d2, d, m, mk_hi):
+    """Odd d in the matrix-core range (support sums for d >= 32, cost for
+    pad(m) = 32 or 16 with d <= 64), m below its padding, ragged m_k: the
+    padded rows, coordinates and columns must not leak into the result."""
+    from synth.generators import gaussian_mixture_workload
+    print(f"[mfma ragged d={d} m={m}]", flush=True)
+    wl = gaussian_mixture_workload(77 + d, 900, d, 4, mk_hi, 12, 3, 0.1, 1.0)
+    mem = pick_init_members(wl["offsets"], 3, m, 5)
+    Xc, Wc = oracle.init_centroids(wl, mem, m)
+    lab, _, _ = oracle.assign(wl, Xc, Wc, T=30)
+    Xo, Wo, tr, _, plans = oracle_barycenters(wl, lab, Xc, Wc, T=30, tau=10)
+    with _ctx(d2, wl, "f32") as ctx:
+        ctx.centroids_set(Xc, Wc)
+        ctx.labels_set(lab)
+        ctx.barycenter(iters=30, tau=10, init=d2.D2_INIT_PRODUCT)
+        g_tr, _ = ctx.objective(30)
+        Xg, Wg = ctx.centroids_get()
+        for c in range(3):
+            if tr[c] is not None:
+                assert _rel(g_tr[:, c], tr[c]) < 1e-5, c
+        assert np.abs(Wg - Wo).max() < 1e-5
+        assert np.abs(Xg - Xo).max() < 1e-5
+        me = marginal_errors(ctx, wl, plans, range(0, 900, 30))
+        assert me < 1e-6
