@@ -219,6 +219,7 @@ def main():
     # HIP events on the context's stream (kernels inside a replayed graph
     # cannot be bracketed individually)
     ev_pairs, all_pairs = ctx.assign_pairs()
+    costed_pairs = ctx.assign_pairs_costed()
     ctx.set_profiling(True)
     ctx.kernel_stats(reset=True)
     for _ in range(args.profile_rounds):
@@ -286,6 +287,8 @@ def main():
                      "source": sched.get("source")},
         "assign_pairs_evaluated_frac": (ev_pairs / all_pairs
                                         if all_pairs else None),
+        "assign_pairs_costed_frac": (costed_pairs / all_pairs
+                                     if all_pairs else None),
         "kernel_timing": "HIP events around each launch on the context "
                          f"stream, {args.profile_rounds} host-issued rounds "
                          "after the timed rounds",

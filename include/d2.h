@@ -137,10 +137,12 @@ d2_status d2_labels_get(d2_ctx* ctx, int32_t* labels);
 d2_status d2_assign(d2_ctx* ctx, const d2_ot_params* p, int32_t* labels_out,
                     double* dist_out, int64_t* n_changed);
 
-/* Pairs run through the transport iterations by the last d2_assign and the
- * total number of (instance, centroid) pairs. */
+/* Pair counts of the last d2_assign: pairs run through the transport
+ * iterations, pairs whose m x m_k cost block was formed (those passing the
+ * cheap bound of the pruning; every pair without pruning) and the total
+ * number of (instance, centroid) pairs.  Any pointer may be NULL. */
 d2_status d2_assign_pairs(const d2_ctx* ctx, int64_t* evaluated,
-                          int64_t* total);
+                          int64_t* costed, int64_t* total);
 
 /* Centroid update (Sec. 3.2, Algorithm "Centroid Update with B-ADMM") for
  * all K clusters of the current labels in one batched pass: Lambda = 0,

@@ -860,7 +860,7 @@ int slots_for(const d2_ctx* c) {
 template <typename T>
 __global__ void __launch_bounds__(64)
     k_cstats(const double* xc, const double* wc, int m, int MP, int d,
-             int xs, T* cmu, T* crad, T* xct) {
+             int xs, int K, T* cmu, T* crad, T* xct) {
   extern __shared__ double s_mu[];  // d
   const int q = blockIdx.x, l = threadIdx.x;
   const double* xq = xc + (size_t)q * MP * d;
@@ -876,7 +876,7 @@ __global__ void __launch_bounds__(64)
     double s = 0.0;
     for (int i = 0; i < m; ++i) s += wq[i] * xq[(size_t)i * d + t] / div;
     s_mu[t] = s;
-    cmu[(size_t)q * d + t] = (T)s;
+    cmu[(size_t)t * K + q] = (T)s;
   }
   __syncthreads();
   double r = 0.0;
@@ -903,7 +903,7 @@ d2_status centroid_stats(d2_ctx* c) {
       return s;
   }
   hipLaunchKernelGGL(k_cstats<T>, dim3(K), dim3(64), sizeof(double) * d,
-                     c->stream, c->d_xc, c->d_wc, c->m, MP, d, c->xs,
+                     c->stream, c->d_xc, c->d_wc, c->m, MP, d, c->xs, K,
                      (T*)c->d_cmu, (T*)c->d_crad, (T*)c->d_xct);
   HIPCHK(c, hipGetLastError());
   return D2_OK;
@@ -923,6 +923,7 @@ d2_status run_assign(d2_ctx* c, const d2_ot_params* p, float* ms_out) {
   a.labels = c->d_labels;
   a.best = c->d_best;
   a.evaluated = c->d_evals;
+  a.costed = c->d_evals + 1;
   a.prune = p->prune ? 1 : 0;
   a.prev_valid = c->have_labels ? 1 : 0;
   {
@@ -982,7 +983,7 @@ d2_status run_assign(d2_ctx* c, const d2_ot_params* p, float* ms_out) {
     c->alist_MP = c->MP;
   }
   const int wpb = 4;
-  HIPCHK(c, hipMemsetAsync(c->d_evals, 0, sizeof(unsigned long long),
+  HIPCHK(c, hipMemsetAsync(c->d_evals, 0, 2 * sizeof(unsigned long long),
                            c->stream));
   HIPCHK(c, hipEventRecord(c->ev0, c->stream));
   hipEvent_t pe = prof_begin(c);
@@ -995,8 +996,10 @@ d2_status run_assign(d2_ctx* c, const d2_ot_params* p, float* ms_out) {
     aq.list = c->d_alist + c->aofs[q];
     aq.N = c->acnt[q];
     const int64_t blocks = (aq.N + wpb - 1) / wpb;
-    hipLaunchKernelGGL(fq, dim3((unsigned)blocks), dim3(64 * wpb),
-                       sizeof(T) * wpb * c->d, c->stream, aq);
+    // per wave: the instance mean, then |y_j - mu_P| and w_j per column
+    const size_t lds = sizeof(T) * wpb * (c->d + 2 * (64 / c->MP) * (1 << q));
+    hipLaunchKernelGGL(fq, dim3((unsigned)blocks), dim3(64 * wpb), lds,
+                       c->stream, aq);
     HIPCHK(c, hipGetLastError());
   }
   prof_end(c, kKAssign, pe);
@@ -1006,9 +1009,10 @@ d2_status run_assign(d2_ctx* c, const d2_ot_params* p, float* ms_out) {
   float ms = 0.f;
   HIPCHK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
   if (ms_out) *ms_out = ms;
-  unsigned long long ev = 0;
-  HIPCHK(c, hipMemcpy(&ev, c->d_evals, sizeof(ev), hipMemcpyDeviceToHost));
-  c->last_evals = (int64_t)ev;
+  unsigned long long ev[2] = {0, 0};
+  HIPCHK(c, hipMemcpy(ev, c->d_evals, sizeof(ev), hipMemcpyDeviceToHost));
+  c->last_evals = (int64_t)ev[0];
+  c->last_costed = (int64_t)ev[1];
   c->last_pairs = c->N * (int64_t)c->K;
   return D2_OK;
 }
@@ -1133,7 +1137,7 @@ d2_status d2_load_instances(d2_ctx* c, int64_t N, int32_t d,
   if ((s = dalloc(c, &c->d_W, c->esz() * n))) return s;
   if ((s = dalloc(c, (void**)&c->d_labels, sizeof(int32_t) * N))) return s;
   if ((s = dalloc(c, (void**)&c->d_best, sizeof(double) * N))) return s;
-  if ((s = dalloc(c, (void**)&c->d_evals, sizeof(unsigned long long))))
+  if ((s = dalloc(c, (void**)&c->d_evals, 2 * sizeof(unsigned long long))))
     return s;
   HIPCHK(c, hipMemcpy(c->d_off, offsets, sizeof(int64_t) * (N + 1),
                       hipMemcpyHostToDevice));
@@ -1305,9 +1309,10 @@ d2_status d2_assign(d2_ctx* c, const d2_ot_params* p, int32_t* labels_out,
 }
 
 d2_status d2_assign_pairs(const d2_ctx* c, int64_t* evaluated,
-                          int64_t* total) {
+                          int64_t* costed, int64_t* total) {
   if (!c) return D2_EINVAL;
   if (evaluated) *evaluated = c->last_evals;
+  if (costed) *costed = c->last_costed;
   if (total) *total = c->last_pairs;
   return D2_OK;
 }

@@ -312,6 +312,15 @@ template <typename T, int MP> struct Tile {
   __device__ __forceinline__ int64_t eidx(int r, int m) const {
     return base + (int64_t)colc(r) * m + ic;
   }
+  // A copy whose column group the compiler cannot see through: the
+  // per-slot columns, masks and addresses derived from it are formed again
+  // where they are used instead of being hoisted out of a loop and held in
+  // registers across it.
+  __device__ __forceinline__ Tile fresh() const {
+    Tile t = *this;
+    asm volatile("" : "+v"(t.g));
+    return t;
+  }
 };
 
 // Calls f.template operator()<NS>() with the smallest specialised slot
@@ -1177,7 +1186,8 @@ template <typename T> struct AssignArgs {
   int32_t* labels;      // out; with prev_valid also the previous labels
   double* best;
   unsigned long long* evaluated;  // pairs run through the iterations
-  const T* cmu;         // K x d weighted mean of each centroid's support
+  unsigned long long* costed;     // pairs whose cost block was formed
+  const T* cmu;         // d x K weighted mean of each centroid's support
   const T* crad;        // K  radius of the support around that mean
   const T* xct;         // K x MP x xs centroid supports in the device dtype
   const int32_t* list;  // instance ids of this launch (one slot class)
@@ -1186,18 +1196,30 @@ template <typename T> struct AssignArgs {
   int m, d, xs, K, iters, prune, prev_valid;
 };
 
+// value of v in lane `src` (src uniform), for 32- and 64-bit types
+__device__ __forceinline__ float lane_value(float v, int src) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
+}
+__device__ __forceinline__ double lane_value(double v, int src) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), src);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // Any coupling whose column sums are the instance weights w_j (as Pi1's are,
 // Eq. (badmmc0)) has cost sum_j w_j sum_i (Pi1_ij / w_j) C_ij >=
 // sum_j w_j min_i C_ij.  This lower bound of the assignment distance lets a
 // centroid be skipped when it exceeds the best distance found so far.
 template <typename T, int MP, int NS>
-__device__ __forceinline__ double cost_lower_bound(const T (&cs)[NS],
-                                                   const bool (&v)[NS],
-                                                   const T (&wk)[NS], int i) {
+__device__ __forceinline__ double cost_lower_bound(const Tile<T, MP>& tl0,
+                                                   const T (&cs)[NS],
+                                                   const T (&wk)[NS]) {
+  const Tile<T, MP> tl = tl0.fresh();
   const T big = T(3.0e38);
   T mn[NS];
 #pragma unroll
-  for (int r = 0; r < NS; ++r) mn[r] = v[r] ? cs[r] : big;
+  for (int r = 0; r < NS; ++r) mn[r] = tl.valid(r) ? cs[r] : big;
   // column minimum over the MP lanes of each column group
 #pragma unroll
   for (int r = 0; r < NS; ++r) {
@@ -1208,55 +1230,76 @@ __device__ __forceinline__ double cost_lower_bound(const T (&cs)[NS],
     if constexpr (MP >= 32) mn[r] = fmin(mn[r], xswz16(mn[r]));
     if constexpr (MP >= 64) mn[r] = fmin(mn[r], x32(mn[r]));
   }
-  double lb = 0.0;
+  // per lane at most NS non-negative terms: the FP32 sum is within a few
+  // ulps, far inside the pruning margin
+  T lb = T(0);
 #pragma unroll
-  for (int r = 0; r < NS; ++r)
-    if (i == 0 && wk[r] > T(0)) lb += (double)wk[r] * (double)mn[r];
-  return sum_wave(lb);
+  for (int r = 0; r < NS; ++r) lb = fma(wk[r] > T(0) ? wk[r] : T(0), mn[r] < big ? mn[r] : T(0), lb);
+  return sum_wave((double)(tl.i == 0 ? lb : T(0)));
 }
 
 // Costs of one (instance, centroid) tile with 4-wide loads: supports and
-// centroid rows share the zero-padded stride xs (a multiple of 4).
+// centroid rows share the zero-padded stride xs (a multiple of 4).  Slots
+// go in chunks, each over all coordinates, so that only one chunk's loads
+// are in flight; columns past m_k read 0 through the buffer bounds, and
+// entries outside the tile are 0.
 template <typename T, int MP, int NS>
 __device__ __forceinline__ void pair_costs(const AssignArgs<T>& a,
-                                           const Tile<T, MP>& tl, int c,
-                                           const bool (&v)[NS],
-                                           const int (&jc)[NS], T (&cs)[NS]) {
+                                           const Tile<T, MP>& tl0, int c,
+                                           T (&cs)[NS]) {
   using V4 = typename Vec4<T>::type;
-  const V4* xrow = reinterpret_cast<const V4*>(
-      a.xct + ((int64_t)c * MP + tl.ic) * a.xs);
+  const Tile<T, MP> tl = tl0.fresh();
+  const uint32_t rowb = (uint32_t)a.xs * (uint32_t)sizeof(T);
+  const Rsrc rY = make_rsrc(a.X + tl.o * a.xs, (uint32_t)tl.mk * rowb);
+  const Rsrc rC = make_rsrc(a.xct + (int64_t)c * MP * a.xs, MP * rowb);
+  const uint32_t xo = (uint32_t)tl.ic * rowb;
+  const int n4 = a.xs / 4;
+  constexpr int CH = NS <= 8 ? NS : (NS % 8 == 0 ? 8 : 4);
 #pragma unroll
-  for (int r = 0; r < NS; ++r) cs[r] = T(0);
-  for (int t4 = 0; t4 < a.xs / 4; ++t4) {
-    const V4 xv = xrow[t4];
+  for (int r0 = 0; r0 < NS; r0 += CH) {
+    T acc[CH];
+    uint32_t yo[CH];
 #pragma unroll
-    for (int r = 0; r < NS; ++r) {
-      const V4 y =
-          reinterpret_cast<const V4*>(a.X + (tl.o + jc[r]) * a.xs)[t4];
-      T df = xv.x - y.x;
-      cs[r] = fma(df, df, cs[r]);
-      df = xv.y - y.y;
-      cs[r] = fma(df, df, cs[r]);
-      df = xv.z - y.z;
-      cs[r] = fma(df, df, cs[r]);
-      df = xv.w - y.w;
-      cs[r] = fma(df, df, cs[r]);
+    for (int u = 0; u < CH; ++u) {
+      acc[u] = T(0);
+      yo[u] = (uint32_t)tl.col(r0 + u) * rowb;
     }
-  }
+    for (int t4 = 0; t4 < n4; ++t4) {
+      const uint32_t tb = (uint32_t)t4 * (uint32_t)sizeof(V4);
+      const V4 xv = bload<V4>(rC, xo + tb);
 #pragma unroll
-  for (int r = 0; r < NS; ++r) cs[r] = v[r] ? cs[r] : T(0);
+      for (int u = 0; u < CH; ++u) {
+        const V4 y = bload<V4>(rY, yo[u] + tb);
+        T df = xv.x - y.x;
+        acc[u] = fma(df, df, acc[u]);
+        df = xv.y - y.y;
+        acc[u] = fma(df, df, acc[u]);
+        df = xv.z - y.z;
+        acc[u] = fma(df, df, acc[u]);
+        df = xv.w - y.w;
+        acc[u] = fma(df, df, acc[u]);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < CH; ++u)
+      cs[r0 + u] = tl.valid(r0 + u) ? acc[u] : T(0);
+  }
 }
 
 // B-ADMM transport value <C, Pi1> of one (instance, centroid) pair after
-// `iters` iterations with both marginals fixed.
+// `iters` iterations with both marginals fixed (Eqs. (badmmc0b)-(badmm2)
+// with the centroid's weights held).  Carried per entry: Pi2, Lambda and
+// the scaled cost C/rho (in base-2 units), from which exp(-(C + Lambda)/rho)
+// is one exponential; Pi1 lives only within an iteration, and the last
+// one's value is the transport value.  Padded columns of a row carry the
+// smoothing eps in Pi2 with no other effect; their share of the row sum,
+// eps times the padded column count, is taken out again.
 template <typename T, int MP, int NS>
 __device__ __forceinline__ double pair_value(const AssignArgs<T>& a,
-                                             const Tile<T, MP>& tl, int c,
+                                             const Tile<T, MP>& tl0, int c,
                                              const T (&cs)[NS],
-                                             const T (&wk)[NS],
-                                             const T (&el)[NS],
-                                             const bool (&v)[NS]) {
-  T p1[NS], p2[NS], l[NS], kc[NS], av[NS], s[NS], E[NS];
+                                             const T (&wk)[NS]) {
+  const Tile<T, MP> tl = tl0.fresh();
   T csum = T(0);
 #pragma unroll
   for (int r = 0; r < NS; ++r) csum += cs[r];
@@ -1265,175 +1308,215 @@ __device__ __forceinline__ double pair_value(const AssignArgs<T>& a,
   const T rho = (T)rhod;
   const T a2 = (T)(kLog2e / rhod);
   const T wi = tl.rowok ? (T)a.wc[c * MP + tl.i] : T(0);
-  // exp(-(C + Lambda)/rho) = K / E with K = exp(-C/rho) fixed for the
-  // pair and E = exp(Lambda/rho), which the Pi1~ step needs anyway
+  const T elr = tl.rowok ? (T)a.eps : T(0);
+  const T pad = elr * (T)(NS * Tile<T, MP>::CPS - tl.mk);
+  T ca[NS], p2[NS], l[NS], q[NS];
 #pragma unroll
   for (int r = 0; r < NS; ++r) {
+    // exp2(-1e30) = 0: an entry outside the tile never takes mass
+    ca[r] = tl.valid(r) ? cs[r] * a2 : T(1.0e30);
     p2[r] = wi * wk[r];
     l[r] = T(0);
-    p1[r] = T(0);
-    kc[r] = v[r] ? dexp2(-cs[r] * a2) : T(0);
+    q[r] = T(0);
   }
+  // slots in chunks of CH: exp(Lambda/rho) and the column sums are held
+  // for one chunk at a time
+  constexpr int CH = NS <= 8 ? NS : (NS % 8 == 0 ? 8 : 4);
   for (int it = 0; it < a.iters; ++it) {
-#pragma unroll
-    for (int r = 0; r < NS; ++r) {
-      E[r] = dexp2(l[r] * a2);
-      av[r] = fma(p2[r] * kc[r], drcp(E[r]), el[r]);
-      s[r] = av[r];
-    }
-    sum_col_n<MP, NS>(s);
     T rr = T(0);
 #pragma unroll
-    for (int r = 0; r < NS; ++r) {
-      const T q = av[r] * (wk[r] * rcp_sum(s[r]));
-      p1[r] = q;
-      p2[r] = fma(q, E[r], el[r]);
-      rr += p2[r];
+    for (int r0 = 0; r0 < NS; r0 += CH) {
+      T E[CH], s[CH];
+#pragma unroll
+      for (int u = 0; u < CH; ++u) {
+        const int r = r0 + u;
+        E[u] = dexp2(l[r] * a2);
+        q[r] = fma(p2[r], dexp2(-fma(l[r], a2, ca[r])), elr);
+        s[u] = q[r];
+      }
+      sum_col_n<MP, CH>(s);
+#pragma unroll
+      for (int u = 0; u < CH; ++u) {
+        const int r = r0 + u;
+        q[r] *= wk[r] * rcp_sum(s[u]);
+        p2[r] = fma(q[r], E[u], elr);
+        rr += p2[r];
+      }
     }
-    rr = sum_row<MP>(rr);
+    rr = sum_row<MP>(rr) - pad;
     const T coef = wi * rcp_sum(rr);
 #pragma unroll
     for (int r = 0; r < NS; ++r) {
-      const T q = p2[r] * coef;
-      l[r] = fma(rho, p1[r] - q, l[r]);
-      p2[r] = q;
+      const T u = p2[r] * coef;
+      l[r] = fma(rho, q[r] - u, l[r]);
+      p2[r] = u;
     }
   }
   T fv = T(0);
 #pragma unroll
-  for (int r = 0; r < NS; ++r) fv = fma(cs[r], p1[r], fv);
-  return sum_wave((double)fv);
+  for (int r = 0; r < NS; ++r) fv = fma(ca[r], q[r], fv);
+  return sum_wave((double)fv) * (rhod / kLog2e);
+}
+
+// Exact lower bound of the distance from the triangle inequality around the
+// centroid mean mu_c (support radius rad_c) and the instance mean mu_P:
+//   sum_j w_j max(0, |dist(mu_P, mu_c) - |y_j - mu_P|| - rad_c)^2,
+// for centroid c of this lane.  smu holds mu_P, srj / swj the instance's
+// |y_j - mu_P| and w_j.  A small relative slack keeps it below the true
+// bound under FP32 rounding.
+template <typename T>
+__device__ __forceinline__ T cheap_bound(const AssignArgs<T>& a, int c,
+                                         const T* smu, const T* srj,
+                                         const T* swj, int mk) {
+  T sq = T(0);
+  for (int t = 0; t < a.d; ++t) {
+    const T df = smu[t] - a.cmu[(int64_t)t * a.K + c];
+    sq = fma(df, df, sq);
+  }
+  const T dl = dsqrt(sq);
+  const T rad = a.crad[c];
+  T acc = T(0);
+  for (int j = 0; j < mk; ++j) {
+    const T rj = srj[j];
+    T gap = fabs(dl - rj) - rad - T(1e-5) * (dl + rj + rad);
+    gap = gap > T(0) ? gap : T(0);
+    acc = fma(swj[j] * gap, gap, acc);
+  }
+  return acc;
 }
 
 template <typename T, int MP, int NS>
 __device__ __forceinline__ void assign_tile(const AssignArgs<T>& a,
-                                            const Tile<T, MP>& tl, T* smu,
+                                            const Tile<T, MP>& tl, T* sw,
                                             int prev, double& bestv,
-                                            int& bestc, int& nevals) {
-  const T eps = (T)a.eps;
+                                            int& bestc, int& nevals,
+                                            int& ncost) {
   const int d = a.d;
-  T wk[NS], el[NS], cs[NS];
-  bool v[NS];
-  int jc[NS];
+  const int lane = threadIdx.x & (kWave - 1);
+  T wk[NS], cs[NS];
 #pragma unroll
-  for (int r = 0; r < NS; ++r) {
-    v[r] = tl.valid(r);
-    jc[r] = tl.colc(r);
-    wk[r] = a.W[tl.o + jc[r]];
-    wk[r] = v[r] ? wk[r] : T(0);
-    el[r] = v[r] ? eps : T(0);
-  }
+  for (int r = 0; r < NS; ++r)
+    wk[r] = tl.valid(r) ? a.W[tl.o + tl.colc(r)] : T(0);
+  auto consider = [&](int c) {
+    const double val = pair_value<T, MP, NS>(a, tl, c, cs, wk);
+    ++nevals;
+    if (bestc < 0 || val < bestv || (val == bestv && c < bestc)) {
+      bestv = val;
+      bestc = c;
+    }
+  };
   if (!a.prune) {
     for (int c = 0; c < a.K; ++c) {
-      pair_costs<T, MP, NS>(a, tl, c, v, jc, cs);
-      const double val = pair_value<T, MP, NS>(a, tl, c, cs, wk, el, v);
-      ++nevals;
-      if (bestc < 0 || val < bestv) {
-        bestv = val;
-        bestc = c;
-      }
+      pair_costs<T, MP, NS>(a, tl, c, cs);
+      ++ncost;
+      consider(c);
     }
     return;
   }
-  // Two exact lower bounds of the distance (section on pruning):
-  //   full:  sum_j w_j min_i C_ij                       (m x m_k x d work)
-  //   cheap: sum_j w_j max(0, |dist(mu_P, mu_c) - |y_j - mu_P|| - rad_c)^2
-  // from the triangle inequality around the centroid mean mu_c (support
-  // radius rad_c) and the instance mean mu_P; O(d + m_k) work.  A small
-  // relative slack keeps the cheap bound below the true one under FP32
-  // rounding.  Dimensions are split over the MP lanes of a column group.
+  // instance mean mu_P (dimensions split over the MP lanes of a column
+  // group), then |y_j - mu_P| and w_j per column into the wave's LDS
+  T* smu = sw;
+  T* srj = sw + d;
+  T* swj = srj + tl.mk;
   for (int t = tl.i; t < d; t += MP) {
     T sm = T(0);
 #pragma unroll
     for (int r = 0; r < NS; ++r)
-      sm = fma(wk[r], a.X[(tl.o + jc[r]) * a.xs + t], sm);
+      sm = fma(wk[r], a.X[(tl.o + tl.colc(r)) * a.xs + t], sm);
     sm = sum_row<MP>(sm);
     if (tl.g == 0) smu[t] = sm;
   }
   __builtin_amdgcn_wave_barrier();
-  T rj[NS];
 #pragma unroll
   for (int r = 0; r < NS; ++r) {
     T sq = T(0);
     for (int t = tl.i; t < d; t += MP) {
-      const T df = a.X[(tl.o + jc[r]) * a.xs + t] - smu[t];
+      const T df = a.X[(tl.o + tl.colc(r)) * a.xs + t] - smu[t];
       sq = fma(df, df, sq);
     }
-    rj[r] = dsqrt(sum_col<MP>(sq));
+    const T rj = dsqrt(sum_col<MP>(sq));
+    if (tl.i == 0 && tl.col(r) < tl.mk) {
+      srj[tl.col(r)] = rj;
+      swj[tl.col(r)] = wk[r];
+    }
   }
-  auto cheap_lb = [&](int c) -> double {
-    T sq = T(0);
-    for (int t = tl.i; t < d; t += MP) {
-      const T df = smu[t] - a.cmu[(int64_t)c * d + t];
-      sq = fma(df, df, sq);
-    }
-    const T dl = dsqrt(sum_col<MP>(sq));
-    const T rad = a.crad[c];
-    T acc = T(0);
-#pragma unroll
-    for (int r = 0; r < NS; ++r) {
-      T gap = fabs(dl - rj[r]) - rad - T(1e-5) * (dl + rj[r] + rad);
-      gap = gap > T(0) ? gap : T(0);
-      acc = fma(wk[r] * gap, gap, acc);
-    }
-    return sum_wave((double)(tl.i == 0 ? acc : T(0)));
-  };
-  // 1) first candidate: the previous label, else the smallest cheap bound
+  __builtin_amdgcn_wave_barrier();
+  const T big = T(3.0e38);
+  // 1) first candidate: the previous label, else the smallest bound
   int c0 = prev;
   if (c0 < 0 || c0 >= a.K) {
-    double lb0 = 0.0;
-    c0 = 0;
-    for (int c = 0; c < a.K; ++c) {
-      const double lb = cheap_lb(c);
-      if (c == 0 || lb < lb0) {
-        lb0 = lb;
-        c0 = c;
+    T lbm = big;
+    int cm = a.K;
+    for (int b0 = 0; b0 < a.K; b0 += kWave) {
+      const int c = b0 + lane;
+      const T lb = c < a.K ? cheap_bound(a, c, smu, srj, swj, tl.mk) : big;
+      if (lb < lbm) {
+        lbm = lb;
+        cm = c;
       }
     }
+    // wave argmin, ties to the lowest index
+    for (int o = 1; o < kWave; o <<= 1) {
+      const T ov = __shfl_xor(lbm, o, kWave);
+      const int oc = __shfl_xor(cm, o, kWave);
+      if (ov < lbm || (ov == lbm && oc < cm)) {
+        lbm = ov;
+        cm = oc;
+      }
+    }
+    c0 = uni(cm);
   }
-  pair_costs<T, MP, NS>(a, tl, c0, v, jc, cs);
-  bestv = pair_value<T, MP, NS>(a, tl, c0, cs, wk, el, v);
-  bestc = c0;
-  ++nevals;
+  pair_costs<T, MP, NS>(a, tl, c0, cs);
+  ++ncost;
+  consider(c0);
   // 2) every other centroid unless a bound clears the best value by a
   // margin far above FP32 rounding of the column sums, so a skipped
-  // centroid can never be the argmin (ties go to the lowest index)
-  for (int c = 0; c < a.K; ++c) {
-    if (c == c0) continue;
-    const double cut = bestv * (1.0 + 1e-4);
-    if (cheap_lb(c) > cut) continue;
-    pair_costs<T, MP, NS>(a, tl, c, v, jc, cs);
-    if (cost_lower_bound<T, MP, NS>(cs, v, wk, tl.i) > cut) continue;
-    const double val = pair_value<T, MP, NS>(a, tl, c, cs, wk, el, v);
-    ++nevals;
-    if (val < bestv || (val == bestv && c < bestc)) {
-      bestv = val;
-      bestc = c;
+  // centroid can never be the argmin (ties go to the lowest index).  The
+  // cheap bounds of 64 centroids at a time, one per lane; the survivors in
+  // index order, each checked again against the best value at its turn.
+  for (int b0 = 0; b0 < a.K; b0 += kWave) {
+    const int c = b0 + lane;
+    const T lb = c < a.K ? cheap_bound(a, c, smu, srj, swj, tl.mk) : big;
+    unsigned long long live =
+        __ballot(c < a.K && c != c0 && (double)lb <= bestv * (1.0 + 1e-4));
+    while (live) {
+      const int bit = __builtin_ctzll(live);
+      live &= live - 1;
+      const double cut = bestv * (1.0 + 1e-4);
+      if ((double)lane_value(lb, bit) > cut) continue;
+      const int cc = b0 + bit;
+      pair_costs<T, MP, NS>(a, tl, cc, cs);
+      ++ncost;
+      if (cost_lower_bound<T, MP, NS>(tl, cs, wk) > cut) continue;
+      consider(cc);
     }
   }
 }
 
 template <typename T, int MP, int R>
 __global__ void __launch_bounds__(256) k_assign(AssignArgs<T> a) {
-  extern __shared__ unsigned char s_raw[];  // per wave: d values (mu_P)
+  // per wave: d values (mu_P), then |y_j - mu_P| and w_j per column
+  extern __shared__ unsigned char s_raw[];
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = uni(threadIdx.x / kWave);
   const int64_t q = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave;
   if (q >= a.N) return;  // whole wavefront exits together
   const int64_t k = uni(a.list[q]);
-  T* smu = reinterpret_cast<T*>(s_raw) + (int64_t)wave * a.d;
+  T* sw = reinterpret_cast<T*>(s_raw) +
+          (int64_t)wave * (a.d + 2 * (kWave / MP) * R);
   Tile<T, MP> tl;
   tl.setup(a.off, nullptr, a.m, (int)k);
   const int prev = a.prev_valid ? uni(a.labels[k]) : -1;
   double bestv = 0.0;
-  int bestc = -1, nevals = 0;
+  int bestc = -1, nevals = 0, ncost = 0;
   with_slots<R>(tl.nsl, [&]<int NS>() {
-    assign_tile<T, MP, NS>(a, tl, smu, prev, bestv, bestc, nevals);
+    assign_tile<T, MP, NS>(a, tl, sw, prev, bestv, bestc, nevals, ncost);
   });
   if (lane == 0) {
     a.labels[k] = bestc;
     a.best[k] = bestv;
     if (a.evaluated) atomicAdd(a.evaluated, (unsigned long long)nevals);
+    if (a.costed) atomicAdd(a.costed, (unsigned long long)ncost);
   }
 }
 

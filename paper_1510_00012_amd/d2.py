@@ -119,7 +119,7 @@ def load_library(path: str = LIB_PATH):
         "d2_set_profiling": ([_p, _i32], ctypes.c_int),
         "d2_set_schedule": ([_p, _i32, _i32], ctypes.c_int),
         "d2_set_bucketing": ([_p, _i32], ctypes.c_int),
-        "d2_assign_pairs": ([_p, _p, _p], ctypes.c_int),
+        "d2_assign_pairs": ([_p, _p, _p, _p], ctypes.c_int),
         "d2_set_graph": ([_p, _i32], ctypes.c_int),
         "d2_autotune": ([_p, ctypes.POINTER(BadmmParams), _p, _p, _p, _p],
                         ctypes.c_int),
@@ -284,9 +284,16 @@ class D2Context:
     def assign_pairs(self):
         """(pairs iterated, total pairs) of the last assignment."""
         e, t = ctypes.c_int64(0), ctypes.c_int64(0)
-        self._chk(self.lib.d2_assign_pairs(self.h, ctypes.byref(e),
+        self._chk(self.lib.d2_assign_pairs(self.h, ctypes.byref(e), None,
                                            ctypes.byref(t)))
         return int(e.value), int(t.value)
+
+    def assign_pairs_costed(self):
+        """Pairs whose cost block the last assignment formed."""
+        c = ctypes.c_int64(0)
+        self._chk(self.lib.d2_assign_pairs(self.h, None, ctypes.byref(c),
+                                           None))
+        return int(c.value)
 
     def support_update(self):
         self._chk(self.lib.d2_support_update(self.h))

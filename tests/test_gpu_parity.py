@@ -308,6 +308,56 @@ def test_assignment_pruning_is_exact(d2, dtype):
     assert np.array_equal(best_a, best_b)
 
 
+@pytest.mark.parametrize("name,N,K,m", [("cfg4", 240, 100, 16),
+                                        ("cfg3", 160, 70, 32)])
+def test_assignment_pruning_many_centroids(d2, name, N, K, m):
+    """More centroids than lanes (the cheap bounds go 64 centroids at a
+    time, the last block ragged): pruned = exhaustive bitwise, from the
+    smallest-bound start and again from the previous labels; labels and
+    distances against the oracle as in test_assignment; pair counts
+    ordered (iterated <= costed <= total, costed = total without
+    pruning)."""
+    print(f"[assign prune many {name} K={K}]", flush=True)
+    wl = make_workload(name, N=N)
+    if np.sum(np.diff(wl["offsets"]) >= m) >= K:
+        mem = pick_init_members(wl["offsets"], K, m, 31)
+        Xc, Wc = oracle.init_centroids(wl, mem, m)
+    else:
+        # too few instances with m points: supports drawn from the pooled
+        # instance points, random weights
+        rng = np.random.Generator(np.random.PCG64(31))
+        Xc = wl["X"][rng.choice(len(wl["X"]), size=(K, m))]
+        Wc = rng.random((K, m)) + 0.05
+        Wc /= Wc.sum(1, keepdims=True)
+    with _ctx(d2, wl, "f32") as ctx:
+        ctx.centroids_set(Xc, Wc)
+        lab_a, best_a, _ = ctx.assign(iters=100, prune=False)
+        ev_a, tot = ctx.assign_pairs()
+        co_a = ctx.assign_pairs_costed()
+        # labels of the exhaustive call are the previous labels now
+        lab_c, best_c, nch = ctx.assign(iters=100, prune=True)
+        ev_c, _ = ctx.assign_pairs()
+        co_c = ctx.assign_pairs_costed()
+    with _ctx(d2, wl, "f32") as ctx:
+        ctx.centroids_set(Xc, Wc)
+        lab_b, best_b, _ = ctx.assign(iters=100, prune=True)
+        ev_b, _ = ctx.assign_pairs()
+        co_b = ctx.assign_pairs_costed()
+    assert ev_a == co_a == tot == N * K
+    assert ev_b <= co_b <= tot and ev_b < tot
+    assert ev_c <= co_c <= tot and ev_c < tot
+    assert nch == 0
+    for lab, best in ((lab_b, best_b), (lab_c, best_c)):
+        assert np.array_equal(lab, lab_a)
+        assert np.array_equal(best, best_a)
+    lab_o, best_o, dist_o = oracle.assign(wl, Xc, Wc, T=100, want_dist=True)
+    srt = np.sort(dist_o, axis=1)
+    margin = (srt[:, 1] - srt[:, 0]) / srt[:, 0]
+    assert _rel(best_a, best_o) < 1e-5
+    ok = (lab_a == lab_o) | (margin < 1e-5)
+    assert ok.all(), np.nonzero(~ok)
+
+
 def test_graph_replay_matches_eager(d2):
     """The captured launch sequence replayed several times (labels, warm
     start and centroids changing in between, eager assignment work between
