@@ -492,3 +492,33 @@ def test_matrix_core_paths_ragged(d2, d, m, mk_hi):
         assert np.abs(Xg - Xo).max() < 1e-5
         me = marginal_errors(ctx, wl, plans, range(0, 900, 30))
         assert me < 1e-6
+
+
+@pytest.mark.parametrize("d,m,mk_hi", [(5, 16, 30), (37, 20, 40),
+                                       (13, 9, 60)])
+def test_assignment_bound_odd_shapes(d2, d, m, mk_hi):
+    """Pruned assignment with odd d (stride padding), m below its tile
+    padding, ragged m_k up to 60 and more centroids than lanes, on points
+    far from the origin: pruning stays exact (labels and distances bitwise
+    those of the exhaustive search) and labels / distances match the oracle
+    as in test_assignment."""
+    from synth.generators import gaussian_mixture_workload
+    print(f"[assign bound d={d} m={m} mk_hi={mk_hi}]", flush=True)
+    wl = gaussian_mixture_workload(91 + d, 300, d, 4, mk_hi, 24, 6, 0.1, 1.0)
+    K = 70
+    mem = pick_init_members(wl["offsets"], K, m, 13)
+    Xc, Wc = oracle.init_centroids(wl, mem, m)
+    with _ctx(d2, wl, "f32") as ctx:
+        ctx.centroids_set(Xc, Wc)
+        lab_a, best_a, _ = ctx.assign(iters=50, prune=False)
+        lab_b, best_b, _ = ctx.assign(iters=50, prune=True)
+        ev_b, tot = ctx.assign_pairs()
+    assert ev_b < tot
+    assert np.array_equal(lab_a, lab_b)
+    assert np.array_equal(best_a, best_b)
+    lab_o, best_o, dist_o = oracle.assign(wl, Xc, Wc, T=50, want_dist=True)
+    srt = np.sort(dist_o, axis=1)
+    margin = (srt[:, 1] - srt[:, 0]) / srt[:, 0]
+    assert _rel(best_a, best_o) < 1e-5
+    ok = (lab_a == lab_o) | (margin < 1e-5)
+    assert ok.all(), np.nonzero(~ok)
