@@ -192,7 +192,7 @@ def main():
         log(f"[bench] recorded schedule {sched} for {key}")
 
     def step(first):
-        ctx.assign(iters=T_assign)
+        ctx.assign(iters=T_assign, outputs=False)
         if first and not sched:
             # schedule autotuned on the first labels (no plan cache yet)
             sched.update(ctx.autotune(iters=min(T, 20), tau=tau))

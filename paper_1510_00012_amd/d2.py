@@ -263,9 +263,13 @@ class D2Context:
         return lab
 
     # ------------------------------------------------------------ steps
-    def assign(self, iters=100, rho0=2.0, eps=1e-16, prune=True):
-        lab = np.empty(self.N, dtype=np.int32)
-        dist = np.empty(self.N)
+    def assign(self, iters=100, rho0=2.0, eps=1e-16, prune=True,
+               outputs=True):
+        """(labels, minimal distances, labels changed); with outputs=False
+        the labels stay in the context and only the change count returns
+        (labels and distances None)."""
+        lab = np.empty(self.N, dtype=np.int32) if outputs else None
+        dist = np.empty(self.N) if outputs else None
         nch = ctypes.c_int64(0)
         p = ot_params(iters, rho0, eps, prune)
         self._chk(self.lib.d2_assign(self.h, ctypes.byref(p), _ptr(lab),
