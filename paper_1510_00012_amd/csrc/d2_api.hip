@@ -30,7 +30,9 @@ int pad_rows(int m) { return 1 << std::max(3, ilog2(m)); }
 
 // kernel tables, filled by the per-type translation units
 void d2k_fill_f32(d2k::KernTable<float>* t);
+void d2k_fill_f32p(d2k::KernTable<float>* t);
 void d2k_fill_f64(d2k::KernTable<double>* t);
+void d2k_fill_f64p(d2k::KernTable<double>* t);
 void d2k_fill_fin(d2k::FinFn* f);
 
 namespace {
@@ -40,6 +42,7 @@ template <> const d2k::KernTable<float>& kern<float>() {
   static const d2k::KernTable<float> t = [] {
     d2k::KernTable<float> x;
     d2k_fill_f32(&x);
+    d2k_fill_f32p(&x);
     return x;
   }();
   return t;
@@ -48,6 +51,7 @@ template <> const d2k::KernTable<double>& kern<double>() {
   static const d2k::KernTable<double> t = [] {
     d2k::KernTable<double> x;
     d2k_fill_f64(&x);
+    d2k_fill_f64p(&x);
     return x;
   }();
   return t;
@@ -671,9 +675,10 @@ d2_status launch_ba(d2_ctx* c, const d2k::Args<T>& a, int& nl) {
                   c->MP == 32 && kt.bcx[0] != nullptr;
   for (int b = 0; b < c->nbk; ++b) {
     const int rb = ilog2(c->bk_R[b]);
-    auto fn = xo   ? kt.bax[ilog2(c->MP) - 3][rb]
-              : cx ? kt.bcx[rb]
-                   : kt.ba[c->onfly ? 1 : 0][ilog2(c->MP) - 3][rb];
+    auto fn = xo        ? kt.bax[ilog2(c->MP) - 3][rb]
+              : cx      ? kt.bcx[rb]
+              : a.xout  ? kt.ba[c->onfly ? 1 : 0][ilog2(c->MP) - 3][rb]
+                        : kt.bap[c->onfly ? 1 : 0][ilog2(c->MP) - 3][rb];
     if (!fn) return c->fail(D2_EINVAL, "no kernel for this tile shape");
     d2k::Args<T> ab = a;
     ab.blist = c->d_blist;

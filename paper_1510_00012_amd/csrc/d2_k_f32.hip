@@ -1,7 +1,9 @@
 // FP32 kernel instantiations and the per-cluster finalisation kernels.
 #include "d2_kinst.hpp"
 
-void d2k_fill_f32(d2k::KernTable<float>* t) { d2k::fill_table<float>(*t); }
+void d2k_fill_f32(d2k::KernTable<float>* t) {
+  d2k::fill_table<float, false>(*t);
+}
 
 void d2k_fill_fin(d2k::FinFn* f) {
   f[0] = &d2k::k_fin<8>;

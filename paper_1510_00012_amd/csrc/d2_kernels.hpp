@@ -677,7 +677,7 @@ __device__ __forceinline__ void bstore(double v, Rsrc r, uint32_t o) {
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int kMfmaMaxD = 64;
-constexpr int kVarNone = 0, kVarSupport = 1, kVarCost = 2;
+constexpr int kVarNone = 0, kVarSupport = 1, kVarCost = 2, kVarPlain = 3;
 
 // Per-wavefront FP32 accumulators of the support sums (MFMA layout) and of
 // the row indicators, added to the wavefront's FP64 LDS record once after
@@ -858,16 +858,17 @@ __device__ __forceinline__ void ba_tile(const Args<T>& a, const Tile<T, MP>& tl,
   if constexpr (VAR == kVarSupport) {
     // support-update launch of a large-d FP32 context (matrix cores)
     support_mfma<MP, NS>(a, tl, b, rr, rX, *sa);
-  } else {
+  } else if constexpr (VAR != kVarPlain) {
     if (a.xout) add_support_terms<T, MP, NS>(a, tl, b, rr, accx);
   }
 }
 
 // VAR: kVarSupport / kVarCost are kernels only for the launches that form
 // the support-update sums / recompute the cost (each once per tau
-// iterations) of FP32 contexts with large d, on the matrix cores; separate
-// kernels so that their registers do not lower the occupancy of the other
-// iterations.
+// iterations) of FP32 contexts with large d, on the matrix cores; kVarPlain
+// kernels leave out the support terms altogether and serve the launches
+// that form none (tau - 1 of every tau).  Separate kernels so that the
+// registers of the rarer launches do not lower the occupancy of the others.
 template <typename T, int MP, int R, bool ONFLY, int VAR = kVarNone>
 __global__ void __launch_bounds__(256) k_iter_ba(Args<T> a) {
   extern __shared__ double s_dyn[];  // [nwaves][MP][d+1] support terms
@@ -1528,6 +1529,7 @@ template <typename T> struct KernTable {
   using AX = void (*)(Args<T>, int);
   using AS = void (*)(AssignArgs<T>);
   BA ba[2][4][6] = {};  // [onfly][mp][r]
+  BA bap[2][4][6] = {}; // the same without support terms
   BA bax[4][6] = {};    // support-update launches, FP32, d > 4, MP 16 / 32
   BA bcx[6] = {};       // cost-recomputation launches, FP32, d <= 64, MP 32
   AX aux[4][6] = {};
