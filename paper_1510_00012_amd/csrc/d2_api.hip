@@ -649,6 +649,29 @@ d2_status launch_aux(d2_ctx* c, const d2k::Args<T>& a0, int mode, int& nl) {
   return D2_OK;
 }
 
+// Launch q of a group of independent launches goes to stream_of(c, q):
+// launch 0 to the context stream, the others to side streams that wait for
+// the work issued before the group (fork) and that the context stream waits
+// for after it (join).  Under graph capture the group becomes parallel
+// branches.
+hipStream_t stream_of(const d2_ctx* c, int q) {
+  return q == 0 ? c->stream : c->side[(q - 1) % d2_ctx::kSide];
+}
+d2_status fork_side(d2_ctx* c, int n) {
+  if (n <= 1) return D2_OK;
+  HIPCHK(c, hipEventRecord(c->fork_ev, c->stream));
+  for (int q = 1; q < n && q <= d2_ctx::kSide; ++q)
+    HIPCHK(c, hipStreamWaitEvent(c->side[q - 1], c->fork_ev, 0));
+  return D2_OK;
+}
+d2_status join_side(d2_ctx* c, int n) {
+  for (int q = 1; q < n && q <= d2_ctx::kSide; ++q) {
+    HIPCHK(c, hipEventRecord(c->join_ev[q - 1], c->side[q - 1]));
+    HIPCHK(c, hipStreamWaitEvent(c->stream, c->join_ev[q - 1], 0));
+  }
+  return D2_OK;
+}
+
 // One B-ADMM iteration: a launch per slot bucket, each kernel specialised
 // for its bucket's register slots (profiled as one "iter_ba" unit).
 template <typename T>
@@ -673,6 +696,11 @@ d2_status launch_ba(d2_ctx* c, const d2k::Args<T>& a, int& nl) {
                   c->d <= 64 && kt.bax[ilog2(c->MP) - 3][0] != nullptr;
   const bool cx = a.recost && xstage && !a.xout && c->d <= 64 &&
                   c->MP == 32 && kt.bcx[0] != nullptr;
+  // the buckets' launches write disjoint chunk records: side by side
+  {
+    d2_status s = fork_side(c, c->nbk);
+    if (s) return s;
+  }
   for (int b = 0; b < c->nbk; ++b) {
     const int rb = ilog2(c->bk_R[b]);
     auto fn = xo        ? kt.bax[ilog2(c->MP) - 3][rb]
@@ -686,9 +714,13 @@ d2_status launch_ba(d2_ctx* c, const d2k::Args<T>& a, int& nl) {
     ab.bidx = b;
     ab.boff = c->bk_off[b];
     hipLaunchKernelGGL(fn, dim3(c->bk_cap[b]), dim3(64 * waves), shm,
-                       c->stream, ab);
+                       stream_of(c, b), ab);
     HIPCHK(c, hipGetLastError());
     ++nl;
+  }
+  {
+    d2_status s = join_side(c, c->nbk);
+    if (s) return s;
   }
   prof_end(c, kKIterBA, pe);
   return D2_OK;
@@ -992,7 +1024,15 @@ d2_status run_assign(d2_ctx* c, const d2_ot_params* p, float* ms_out) {
                            c->stream));
   HIPCHK(c, hipEventRecord(c->ev0, c->stream));
   hipEvent_t pe = prof_begin(c);
-  // one launch per slot class, each kernel sized for its class
+  // one launch per slot class, each kernel sized for its class; the
+  // classes hold disjoint instances and run side by side
+  int nact = 0;
+  for (int q = 0; q < 6; ++q) nact += c->acnt[q] ? 1 : 0;
+  {
+    d2_status s = fork_side(c, nact);
+    if (s) return s;
+  }
+  int qi = 0;
   for (int q = 0; q < 6; ++q) {
     if (!c->acnt[q]) continue;
     auto fq = kt.asg[ilog2(c->MP) - 3][q];
@@ -1004,8 +1044,12 @@ d2_status run_assign(d2_ctx* c, const d2_ot_params* p, float* ms_out) {
     // per wave: the instance mean, then |y_j - mu_P| and w_j per column
     const size_t lds = sizeof(T) * wpb * (c->d + 2 * (64 / c->MP) * (1 << q));
     hipLaunchKernelGGL(fq, dim3((unsigned)blocks), dim3(64 * wpb), lds,
-                       c->stream, aq);
+                       stream_of(c, qi++), aq);
     HIPCHK(c, hipGetLastError());
+  }
+  {
+    d2_status s = join_side(c, nact);
+    if (s) return s;
   }
   prof_end(c, kKAssign, pe);
   HIPCHK(c, hipEventRecord(c->ev1, c->stream));
@@ -1061,10 +1105,20 @@ d2_status d2_create(d2_ctx** out, int device, d2_dtype dtype,
     c->own_stream = true;
   }
   if (hipEventCreate(&c->ev0) != hipSuccess ||
-      hipEventCreate(&c->ev1) != hipSuccess) {
-    delete c;
+      hipEventCreate(&c->ev1) != hipSuccess ||
+      hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming) !=
+          hipSuccess) {
+    d2_destroy(c);
     return D2_EDEVICE;
   }
+  for (int i = 0; i < d2_ctx::kSide; ++i)
+    if (hipStreamCreateWithFlags(&c->side[i], hipStreamNonBlocking) !=
+            hipSuccess ||
+        hipEventCreateWithFlags(&c->join_ev[i], hipEventDisableTiming) !=
+            hipSuccess) {
+      d2_destroy(c);
+      return D2_EDEVICE;
+    }
   *out = c;
   return D2_OK;
 }
@@ -1084,6 +1138,14 @@ void d2_destroy(d2_ctx* c) {
   if (c->h_stage) (void)hipHostFree(c->h_stage);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
+  for (int i = 0; i < d2_ctx::kSide; ++i) {
+    if (c->side[i]) {
+      (void)hipStreamSynchronize(c->side[i]);
+      (void)hipStreamDestroy(c->side[i]);
+    }
+    if (c->join_ev[i]) (void)hipEventDestroy(c->join_ev[i]);
+  }
+  if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }

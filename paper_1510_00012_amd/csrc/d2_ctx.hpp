@@ -97,6 +97,12 @@ struct d2_ctx {
   double* d_rtrace = nullptr;  // residual trace, same shape as d_trace
   int trace_cap = 0, trace_rows = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  // side streams (default priority) for launches that may run side by side
+  // -- the slot buckets of one iteration, the slot classes of the
+  // assignment -- forked from `stream` and joined back to it by events
+  static constexpr int kSide = 5;
+  hipStream_t side[kSide] = {};
+  hipEvent_t fork_ev = nullptr, join_ev[kSide] = {};
   // captured launch sequence of d2_barycenter
   bool use_graph = true;
   hipGraph_t graph = nullptr;
