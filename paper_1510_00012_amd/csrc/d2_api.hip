@@ -705,8 +705,9 @@ d2_status launch_ba(d2_ctx* c, const d2k::Args<T>& a, int& nl) {
     const int rb = ilog2(c->bk_R[b]);
     auto fn = xo        ? kt.bax[ilog2(c->MP) - 3][rb]
               : cx      ? kt.bcx[rb]
-              : a.xout  ? kt.ba[c->onfly ? 1 : 0][ilog2(c->MP) - 3][rb]
-                        : kt.bap[c->onfly ? 1 : 0][ilog2(c->MP) - 3][rb];
+              : (a.xout || a.recost)
+                  ? kt.ba[c->onfly ? 1 : 0][ilog2(c->MP) - 3][rb]
+                  : kt.bap[c->onfly ? 1 : 0][ilog2(c->MP) - 3][rb];
     if (!fn) return c->fail(D2_EINVAL, "no kernel for this tile shape");
     d2k::Args<T> ab = a;
     ab.blist = c->d_blist;

@@ -466,28 +466,36 @@ __device__ __forceinline__ void phase_b(const T (&el)[NS], T (&p)[NS],
 }
 
 // Phase A: in p = Pi2, l = Lambda, cost cs, instance weights wk; out
-// p = Pi1 (column KL projection) and b = Pi1~.  Returns the row sum r_i of
-// Pi1~ in rr and adds <C, Pi1> to f.
-template <typename T, int MP, int NS>
+// p = Pi1 (column KL projection) and, with KEEPB, b = Pi1~.  Returns the row
+// sum r_i of Pi1~ in rr and adds <C, Pi1> to f.  The column sums are formed
+// for a chunk of slots at a time (same adds in the same order per column).
+template <typename T, int MP, int NS, bool KEEPB>
 __device__ __forceinline__ void phase_a(const T (&el)[NS], T (&p)[NS],
                                         const T (&l)[NS], const T (&cs)[NS],
                                         const T (&wk)[NS], T a2, T (&b)[NS],
                                         T& rr, T& f) {
-  T av[NS], s[NS];
-#pragma unroll
-  for (int r = 0; r < NS; ++r) {
-    av[r] = fma(p[r], dexp2(-(cs[r] + l[r]) * a2), el[r]);
-    s[r] = av[r];
-  }
-  sum_col_n<MP, NS>(s);
+  constexpr int CH = NS <= 8 ? NS : (NS % 8 == 0 ? 8 : 4);
   rr = T(0);
 #pragma unroll
-  for (int r = 0; r < NS; ++r) {
-    T p1 = av[r] * (wk[r] * rcp_sum(s[r]));
-    f = fma(cs[r], p1, f);
-    b[r] = fma(p1, dexp2(l[r] * a2), el[r]);
-    rr += b[r];
-    p[r] = p1;
+  for (int r0 = 0; r0 < NS; r0 += CH) {
+    T av[CH], s[CH];
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      const int r = r0 + u;
+      av[u] = fma(p[r], dexp2(-(cs[r] + l[r]) * a2), el[r]);
+      s[u] = av[u];
+    }
+    sum_col_n<MP, CH>(s);
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      const int r = r0 + u;
+      T p1 = av[u] * (wk[r] * rcp_sum(s[u]));
+      f = fma(cs[r], p1, f);
+      const T bt = fma(p1, dexp2(l[r] * a2), el[r]);
+      if constexpr (KEEPB) b[r] = bt;
+      rr += bt;
+      p[r] = p1;
+    }
   }
   rr = sum_row<MP>(rr);
 }
@@ -824,6 +832,8 @@ __device__ __forceinline__ void ba_tile(const Args<T>& a, const Tile<T, MP>& tl,
     wk[r] = bload<T>(rW, j * es);
     if constexpr (ONFLY) {
       cs[r] = cost4<T>(xr, bload<V4>(rX, j * (uint32_t)sizeof(V4)));
+    } else if constexpr (VAR == kVarPlain) {
+      cs[r] = bload<T>(rC, eo[r]);  // plain launches never recompute
     } else {
       if (!a.recost)
         cs[r] = bload<T>(rC, eo[r]);
@@ -834,14 +844,14 @@ __device__ __forceinline__ void ba_tile(const Args<T>& a, const Tile<T, MP>& tl,
   if constexpr (VAR == kVarCost) {
     // cost recomputation launch of a d <= 64 FP32 context (matrix cores)
     cost_mfma<NS>(a, tl, xl, xnorm, rX, cs);
-  } else if constexpr (!ONFLY) {
+  } else if constexpr (!ONFLY && VAR != kVarPlain) {
     if (a.recost && xl) cost_tile<T, MP, NS>(a, tl, xl, cs);
   }
   T res = T(0);
   phase_b<T, MP, NS>(el, p, l, wi, rho, a2, res);
   accr += (double)res;
   T rr, f = T(0);
-  phase_a<T, MP, NS>(el, p, l, cs, wk, a2, b, rr, f);
+  phase_a<T, MP, NS, VAR != kVarPlain>(el, p, l, cs, wk, a2, b, rr, f);
   accw += consensus_term<T, MP>(rr, tl.rowok, a.rule);
   accf += (double)f;
 #pragma unroll
@@ -849,7 +859,7 @@ __device__ __forceinline__ void ba_tile(const Args<T>& a, const Tile<T, MP>& tl,
     bstore(p[r], rP, eo[r]);
     bstore(l[r], rL, eo[r]);
   }
-  if constexpr (!ONFLY) {
+  if constexpr (!ONFLY && VAR != kVarPlain) {
     if (a.recost) {
 #pragma unroll
       for (int r = 0; r < NS; ++r) bstore(cs[r], rC, eo[r]);
@@ -866,8 +876,8 @@ __device__ __forceinline__ void ba_tile(const Args<T>& a, const Tile<T, MP>& tl,
 // VAR: kVarSupport / kVarCost are kernels only for the launches that form
 // the support-update sums / recompute the cost (each once per tau
 // iterations) of FP32 contexts with large d, on the matrix cores; kVarPlain
-// kernels leave out the support terms altogether and serve the launches
-// that form none (tau - 1 of every tau).  Separate kernels so that the
+// kernels leave out the support terms and the cost recomputation
+// altogether and serve the launches that do neither (most of them).  Separate kernels so that the
 // registers of the rarer launches do not lower the occupancy of the others.
 template <typename T, int MP, int R, bool ONFLY, int VAR = kVarNone>
 __global__ void __launch_bounds__(256) k_iter_ba(Args<T> a) {
@@ -913,7 +923,7 @@ __global__ void __launch_bounds__(256) k_iter_ba(Args<T> a) {
   const double* xrow = a.xc + ((int64_t)c * MP + (rowok ? i : 0)) * a.d;
   T* xl = nullptr;
   T xnorm = T(0);
-  if constexpr (!ONFLY) {
+  if constexpr (!ONFLY && VAR != kVarPlain) {
     if (a.recost && a.xstage) {
       xl = reinterpret_cast<T*>(s_dyn + (a.xout ? nwaves * nrec : 0));
       stage_support<T, MP>(a, c, xl);
@@ -998,7 +1008,7 @@ __device__ __forceinline__ void aux_tile(const Args<T>& a, const Tile<T, MP>& tl
       wk[r] = v[r] ? wk[r] : T(0);
     }
     T rr, f = T(0);
-    phase_a<T, MP, NS>(el, p, l, cs, wk, a2, b, rr, f);
+    phase_a<T, MP, NS, true>(el, p, l, cs, wk, a2, b, rr, f);
     accw += consensus_term<T, MP>(rr, tl.rowok, a.rule);
     accf += (double)f;
     if (a.xout) add_support_terms<T, MP, NS>(a, tl, b, rr, accx);
