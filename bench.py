@@ -133,7 +133,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=9)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="cfg2")
+    ap.add_argument("--workload", default="gmm_d3_n65536_k16")
     ap.add_argument("--iters", type=int, default=None)
     ap.add_argument("--profile-rounds", type=int, default=3,
                     help="host-issued rounds timed per kernel with HIP events")

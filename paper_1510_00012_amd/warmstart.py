@@ -35,7 +35,7 @@ from paper_1510_00012_amd import d2 as D2
 from synth.generators import deepsets_init_params, warmstart_clusters
 
 FAMILIES = {
-    # cfg2-like colour distributions and cfg3-like word-vector bags
+    # gmm_d3_n65536_k16-like colour distributions and topic_d64_n200000_k64-like word-vector bags
     "gmm3": dict(m=16, n_train=4000, n_eval=500, nc_lo=64, nc_hi=2048,
                  steps=3000, batch=32, lr=1e-3),
     "topic64": dict(m=32, n_train=1000, n_eval=200, nc_lo=64, nc_hi=512,

@@ -145,26 +145,30 @@ def topic_sphere_workload(seed, N, d=64, n_topic=512, n_class=64, noise=0.3,
 # smaller instance of the same distribution (tests use this).
 WORKLOADS = {
     # pixel-colour-like, one cluster (Sec. 4 pilot shapes): d=3, m_k=8
-    "cfg1": dict(kind="gmm", N=256, d=3, mk_lo=8, mk_hi=8, n_comp=4, n_class=1,
-                 sigma=0.1, alpha=1.0, K=1, m=8, T=200, rounds=0),
+    "gmm_d3_n256": dict(kind="gmm", N=256, d=3, mk_lo=8, mk_hi=8, n_comp=4,
+                        n_class=1, sigma=0.1, alpha=1.0, K=1, m=8, T=200,
+                        rounds=0, seed=1000),
     # full clustering loop, colour-like: d=3, m_k in [4,16]
-    "cfg2": dict(kind="gmm", N=65536, d=3, mk_lo=4, mk_hi=16, n_comp=32,
-                 n_class=16, sigma=0.05, alpha=0.5, K=16, m=16, T=100,
-                 rounds=10),
+    "gmm_d3_n65536_k16": dict(kind="gmm", N=65536, d=3, mk_lo=4, mk_hi=16,
+                              n_comp=32, n_class=16, sigma=0.05, alpha=0.5,
+                              K=16, m=16, T=100, rounds=10, seed=2000),
     # word-vector bags: d=64, heavy-tailed m_k in [8,64]
-    "cfg3": dict(kind="topic", N=200000, d=64, K=64, m=32, T=100, rounds=1),
+    "topic_d64_n200000_k64": dict(kind="topic", N=200000, d=64, K=64, m=32,
+                                  T=100, rounds=1, seed=3000),
     # Table 2 synthetic scale: d=16, m_k in [4,32]
-    "cfg4": dict(kind="gmm", N=2000000, d=16, mk_lo=4, mk_hi=32, n_comp=1024,
-                 n_class=256, sigma=0.1, alpha=1.0, K=256, m=16, T=50,
-                 rounds=5),
+    "gmm_d16_n2000000_k256": dict(kind="gmm", N=2000000, d=16, mk_lo=4,
+                                  mk_hi=32, n_comp=1024, n_class=256,
+                                  sigma=0.1, alpha=1.0, K=256, m=16, T=50,
+                                  rounds=5, seed=4000),
 }
 
 
 def make_workload(name, seed=None, N=None, replicate=0):
-    """Build a named workload; seed defaults to 1000*cfg_index + replicate."""
+    """Build a named workload; seed defaults to the workload's own seed +
+    replicate."""
     p = dict(WORKLOADS[name])
     if seed is None:
-        seed = 1000 * int(name[-1]) + int(replicate)
+        seed = p["seed"] + int(replicate)
     if N is None:
         N = p["N"]
     if p["kind"] == "gmm":
@@ -211,10 +215,11 @@ def warmstart_clusters(family, n_clusters, seed, nc_lo=64, nc_hi=2048,
     of every cluster has the maximal support size, so that a member with at
     least m points exists for the plain initial centroid.
 
-    family "gmm3" (the colour-like cfg2 family): d = 3, m_k ~ U{4..16};
+    family "gmm3" (the colour-like family of gmm_d3_n65536_k16): d = 3, m_k ~ U{4..16};
       own class = 2 Gaussian components with means ~ U[0,1]^3, sigma 0.05;
       contamination = 2 further components; weights Dirichlet(0.5).
-    family "topic64" (the word-vector-like cfg3 family): d = 64,
+    family "topic64" (the word-vector-like family of
+    topic_d64_n200000_k64): d = 64,
       m_k = 7 + Zipf(1.2) <= 64; own class = 8 unit topic vectors,
       contamination = 8 more; points normalise(t + (0.3/8) N(0, I)),
       rounded to bf16; weights Zipf(1.2) counts <= 1000.

@@ -60,14 +60,14 @@ def test_assignment_exponential_count():
 def test_traffic_summary_is_tied_to_the_kernel_source():
     h = bench.kernel_source_hash()
     assert h == profiling.kernel_source_hash()
-    path = os.path.join(ROOT, "profiles", "traffic_k_iter_ba_cfg2.json")
+    path = os.path.join(ROOT, "profiles", "traffic_k_iter_ba_gmm_d3_n65536_k16.json")
     rec = json.load(open(path))
-    got = bench.load_traffic("k_iter_ba", "cfg2", h)
+    got = bench.load_traffic("k_iter_ba", "gmm_d3_n65536_k16", h)
     if rec["kernel_source_hash"] == h:
         assert got == rec["hbm_bytes_per_launch"]
     else:
         assert got is None
-    assert bench.load_traffic("k_iter_ba", "cfg2", "0" * 16) is None
+    assert bench.load_traffic("k_iter_ba", "gmm_d3_n65536_k16", "0" * 16) is None
     assert bench.load_traffic("k_iter_ba", "no_such_workload", h) is None
 
 

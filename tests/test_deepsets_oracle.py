@@ -14,7 +14,7 @@ M, D, H = 3, 2, 8
 
 
 def _clusters(seed, m=M, d=D, n_cl=2, with_targets=True):
-    wl = make_workload("cfg1", seed=seed, N=12)
+    wl = make_workload("gmm_d3_n256", seed=seed, N=12)
     rng = np.random.Generator(np.random.PCG64(seed + 5))
     out = []
     for c in range(n_cl):

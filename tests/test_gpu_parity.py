@@ -40,7 +40,7 @@ def test_single_cluster_barycenter(d2, dtype, tol):
     """One cluster, N=256, m=8, d=3, m_k=8 (pixel-colour shape), 200
     iterations with support updates every 10."""
     print(f"[single_cluster {dtype}]", flush=True)
-    wl = make_workload("cfg1")
+    wl = make_workload("gmm_d3_n256")
     mem = pick_init_members(wl["offsets"], 1, 8, wl["seed"])
     Xc, Wc = oracle.init_centroids(wl, mem, 8)
     lab = np.zeros(256, dtype=np.int32)
@@ -71,7 +71,7 @@ def test_multi_cluster_barycenter_ragged(d2, dtype):
     """K=4 clusters of a 6000-instance colour-like set (m_k in [4,16],
     m=16): many chunks per cluster, one empty cluster (label 4 unused)."""
     print(f"[multi_cluster {dtype}]", flush=True)
-    wl = make_workload("cfg2", N=6000)
+    wl = make_workload("gmm_d3_n65536_k16", N=6000)
     K = 5
     mem = pick_init_members(wl["offsets"], K, 16, 11)
     Xc, Wc = oracle.init_centroids(wl, mem, 16)
@@ -139,7 +139,7 @@ def test_edge_shapes(d2):
             assert me < 1e-6
 
 
-@pytest.mark.parametrize("name,m", [("cfg3", 32), ("cfg4", 16)])
+@pytest.mark.parametrize("name,m", [("topic_d64_n200000_k64", 32), ("gmm_d16_n2000000_k256", 16)])
 def test_large_d_cached_cost_path(d2, name, m):
     """d=64 (word-vector-bag shape, bf16-exact unit vectors), m=32, m_k in
     [8,64], and d=16 (m=16, m_k in [4,32]): the cost is cached per support
@@ -171,7 +171,7 @@ def test_warm_start_and_support_update(d2):
     label did not change; then the standalone support update (Eq. updatex)
     from the cached Pi2."""
     print("[warm_start]", flush=True)
-    wl = make_workload("cfg2", N=3000)
+    wl = make_workload("gmm_d3_n65536_k16", N=3000)
     mem = pick_init_members(wl["offsets"], 3, 16, 2)
     Xc, Wc = oracle.init_centroids(wl, mem, 16)
     lab1, _, _ = oracle.assign(wl, Xc, Wc, T=40)
@@ -205,7 +205,7 @@ def test_assignment(d2, dtype):
     relative margin between best and second-best is below 1e-5; distances
     within 1e-5 (f32) / 1e-10 (f64) relative."""
     print(f"[assign {dtype}]", flush=True)
-    wl = make_workload("cfg2", N=2000)
+    wl = make_workload("gmm_d3_n65536_k16", N=2000)
     mem = pick_init_members(wl["offsets"], 6, 16, 9)
     Xc, Wc = oracle.init_centroids(wl, mem, 16)
     lab_o, best_o, dist_o = oracle.assign(wl, Xc, Wc, T=100, want_dist=True)
@@ -224,7 +224,7 @@ def test_assignment(d2, dtype):
 def test_centroid_init_matches_oracle(d2):
     """Eq. (merge) initialisation computed by the library's host code."""
     print("[init]", flush=True)
-    wl = make_workload("cfg2", N=500)
+    wl = make_workload("gmm_d3_n65536_k16", N=500)
     mem = pick_init_members(wl["offsets"], 4, 8, 3)
     Xo, Wo = oracle.init_centroids(wl, mem, 8)
     with _ctx(d2, wl, "f64") as ctx:
@@ -240,7 +240,7 @@ def test_clustering_rounds_teacher_forced(d2):
     assignment labels agree off near-ties, the warm-started barycenter
     traces agree to 1e-5 (FP32)."""
     print("[cluster_rounds]", flush=True)
-    wl = make_workload("cfg2", N=4000)
+    wl = make_workload("gmm_d3_n65536_k16", N=4000)
     K = 4
     mem = pick_init_members(wl["offsets"], K, 16, 5)
     Xc, Wc = oracle.init_centroids(wl, mem, 16)
@@ -271,7 +271,7 @@ def test_cluster_call_runs_and_is_deterministic(d2):
     """d2_cluster end to end twice from the same start: bitwise identical
     centroids and labels (fixed-order reductions, no float atomics)."""
     print("[cluster_determinism]", flush=True)
-    wl = make_workload("cfg2", N=5000)
+    wl = make_workload("gmm_d3_n65536_k16", N=5000)
     mem = pick_init_members(wl["offsets"], 8, 16, 1)
     outs = []
     for _ in range(2):
@@ -293,7 +293,7 @@ def test_assignment_pruning_is_exact(d2, dtype):
     and minimal distances of the exhaustive search, while iterating fewer
     (instance, centroid) pairs."""
     print(f"[assign_prune {dtype}]", flush=True)
-    wl = make_workload("cfg2", N=4000)
+    wl = make_workload("gmm_d3_n65536_k16", N=4000)
     mem = pick_init_members(wl["offsets"], 16, 16, 23)
     Xc, Wc = oracle.init_centroids(wl, mem, 16)
     with _ctx(d2, wl, dtype) as ctx:
@@ -308,8 +308,8 @@ def test_assignment_pruning_is_exact(d2, dtype):
     assert np.array_equal(best_a, best_b)
 
 
-@pytest.mark.parametrize("name,N,K,m", [("cfg4", 240, 100, 16),
-                                        ("cfg3", 160, 70, 32)])
+@pytest.mark.parametrize("name,N,K,m", [("gmm_d16_n2000000_k256", 240, 100, 16),
+                                        ("topic_d64_n200000_k64", 160, 70, 32)])
 def test_assignment_pruning_many_centroids(d2, name, N, K, m):
     """More centroids than lanes (the cheap bounds go 64 centroids at a
     time, the last block ragged): pruned = exhaustive bitwise, from the
@@ -363,7 +363,7 @@ def test_graph_replay_matches_eager(d2):
     start and centroids changing in between, eager assignment work between
     replays) gives bitwise the results of host-issued launches."""
     print("[graph_replay]", flush=True)
-    wl = make_workload("cfg2", N=5000)
+    wl = make_workload("gmm_d3_n65536_k16", N=5000)
     mem = pick_init_members(wl["offsets"], 6, 16, 8)
     with _ctx(d2, wl, "f32") as g, _ctx(d2, wl, "f32") as e:
         e.set_graph(False)
@@ -390,7 +390,7 @@ def test_autotune_then_parity(d2):
     """The autotuner restores the centroids, picks a valid schedule, and the
     tuned barycenter still matches the oracle."""
     print("[autotune]", flush=True)
-    wl = make_workload("cfg2", N=6000)
+    wl = make_workload("gmm_d3_n65536_k16", N=6000)
     mem = pick_init_members(wl["offsets"], 4, 16, 12)
     Xc, Wc = oracle.init_centroids(wl, mem, 16)
     lab, _, _ = oracle.assign(wl, Xc, Wc, T=40)
@@ -413,8 +413,8 @@ def test_autotune_then_parity(d2):
                 assert _rel(g_tr[:, c], tr[c]) < 1e-5
 
 
-@pytest.mark.parametrize("name,N,K,m", [("cfg3", 1200, 5, 32),
-                                        ("cfg4", 1500, 4, 16)])
+@pytest.mark.parametrize("name,N,K,m", [("topic_d64_n200000_k64", 1200, 5, 32),
+                                        ("gmm_d16_n2000000_k256", 1500, 4, 16)])
 def test_assignment_split_by_slot_class(d2, name, N, K, m):
     """Larger tiles (d = 64 / 16, m_k up to 64 / 32): the assignment runs
     one launch per slot class; labels and distances as in
@@ -440,7 +440,7 @@ def test_slot_buckets_match_oracle(d2):
     centroids and objective trace, against the oracle, on the d = 64
     shape whose m_k spans four slot classes."""
     print("[slot buckets]", flush=True)
-    wl = make_workload("cfg3", N=1500)
+    wl = make_workload("topic_d64_n200000_k64", N=1500)
     mem = pick_init_members(wl["offsets"], 3, 32, 4)
     Xc, Wc = oracle.init_centroids(wl, mem, 32)
     lab, _, _ = oracle.assign(wl, Xc, Wc, T=30)

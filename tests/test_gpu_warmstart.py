@@ -185,7 +185,7 @@ def test_ws_training_reduces_loss(d2):
 @pytest.mark.parametrize("dtype,tol", [("f64", 1e-9), ("f32", 1e-5)])
 def test_objective_feasible_matches_oracle(d2, dtype, tol):
     print(f"[objective_feasible {dtype}]", flush=True)
-    wl = make_workload("cfg2", N=900)
+    wl = make_workload("gmm_d3_n65536_k16", N=900)
     K = 3
     mem = pick_init_members(wl["offsets"], K, 16, 7)
     Xc, Wc = oracle.init_centroids(wl, mem, 16)

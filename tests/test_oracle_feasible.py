@@ -34,7 +34,7 @@ def test_round_feasible_marginals_and_identity():
 
 
 def test_rounded_cost_bounds_lp_and_matches_lp_plan():
-    wl = make_workload("cfg1", N=6)
+    wl = make_workload("gmm_d3_n256", N=6)
     off, X, W = wl["offsets"], wl["X"], wl["W"]
     rng = np.random.Generator(np.random.PCG64(5))
     x = rng.random((4, 3))
@@ -51,7 +51,7 @@ def test_rounded_cost_bounds_lp_and_matches_lp_plan():
 
 
 def test_feasible_objective_converges_to_lp():
-    wl = make_workload("cfg1", N=12)
+    wl = make_workload("gmm_d3_n256", N=12)
     members = np.arange(12)
     x0, w0 = oracle.init_centroids(wl, [0], 8)
     out = oracle.barycenter(wl, members, x0[0], w0[0], T=3000, tau=10)

@@ -321,7 +321,7 @@ def test_identical_members_fixed_point(oracle_mod):
 def test_barycenter_invariants_every_iteration(oracle_mod):
     """Column sums of every Pi1 = w^(k); row sums of every Pi2 = w; w in the
     simplex; sum Lambda^(k) = 0; ftrace matches <C, Pi1> from cdist."""
-    wl = make_workload("cfg1", N=24)
+    wl = make_workload("gmm_d3_n256", N=24)
     off = wl["offsets"]
     mem = pick_init_members(off, 1, 8, 0)
     Xc, Wc = oracle_mod.init_centroids(wl, mem, 8)
@@ -343,7 +343,7 @@ def test_barycenter_invariants_every_iteration(oracle_mod):
 
 def test_rho_is_rho0_times_mean_cost(oracle_mod):
     """Eq. (rho), read as rho0 * mean_{k,i,j} c(x_i, x^(k)_j)."""
-    wl = make_workload("cfg1", N=10)
+    wl = make_workload("gmm_d3_n256", N=10)
     off = wl["offsets"]
     x = wl["X"][:8]
     out = oracle_mod.barycenter(wl, np.arange(10), x, np.full(8, 1 / 8), T=1)
@@ -354,7 +354,7 @@ def test_rho_is_rho0_times_mean_cost(oracle_mod):
 
 def test_barycenter_thread_count_invariant(oracle_mod):
     """Fixed reduction order: results do not depend on the thread count."""
-    wl = make_workload("cfg2", N=300)
+    wl = make_workload("gmm_d3_n65536_k16", N=300)
     mem = pick_init_members(wl["offsets"], 1, 16, 0)
     Xc, Wc = oracle_mod.init_centroids(wl, mem, 16)
     nt = oracle_mod.num_threads()
@@ -423,7 +423,7 @@ def test_assign_is_argmin_of_pair_values(oracle_mod):
     """Assignment step: label = argmin over centroids of the B-ADMM transport
     value (ties to the lowest index); on well-separated data it agrees with
     the exact-W^2 argmin (LP)."""
-    wl = make_workload("cfg2", N=40)
+    wl = make_workload("gmm_d3_n65536_k16", N=40)
     off = wl["offsets"]
     mem = pick_init_members(off, 4, 16, 3)
     Xc, Wc = oracle_mod.init_centroids(wl, mem, 16)
@@ -450,7 +450,7 @@ def test_cluster_loop_with_one_point_is_lloyd_on_means(oracle_mod):
     var(P), so labels follow the nearest instance mean and each centroid
     becomes the mean of its members' means -- Lloyd's K-means on the
     instance means (own numpy Lloyd from the same start)."""
-    wl = make_workload("cfg2", N=200)
+    wl = make_workload("gmm_d3_n65536_k16", N=200)
     off, X, W = wl["offsets"], wl["X"], wl["W"]
     N = len(off) - 1
     means = np.array([W[off[k]:off[k + 1]] @ X[off[k]:off[k + 1]]

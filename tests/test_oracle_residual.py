@@ -12,7 +12,7 @@ from synth.generators import make_workload
 
 
 def test_residual_matches_returned_plans():
-    wl = make_workload("cfg2", N=300)
+    wl = make_workload("gmm_d3_n65536_k16", N=300)
     off = wl["offsets"]
     mem = np.arange(0, 300, 3)
     x0, w0 = oracle.init_centroids(wl, [mem[0]] if np.diff(off)[mem[0]] >= 16
@@ -29,7 +29,7 @@ def test_residual_matches_returned_plans():
 
 
 def test_residual_vanishes_with_fixed_support():
-    wl = make_workload("cfg1", N=40)
+    wl = make_workload("gmm_d3_n256", N=40)
     x0, w0 = oracle.init_centroids(wl, [0], 8)
     o = oracle.barycenter(wl, np.arange(40), x0[0], w0[0], T=3000, tau=5000)
     r = o["rtrace"]
