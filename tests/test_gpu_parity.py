@@ -386,6 +386,37 @@ def test_graph_replay_matches_eager(d2):
             assert np.array_equal(tg, te)
 
 
+def test_graph_replay_with_buckets_matches_eager(d2):
+    """Slot buckets (every class its own launch) and assignment slot classes
+    run side by side on forked streams; the captured graph with those
+    parallel branches, replayed over several rounds, gives bitwise the
+    results of host-issued launches."""
+    print("[graph_replay buckets]", flush=True)
+    wl = make_workload("topic_d64_n200000_k64", N=1500)
+    mem = pick_init_members(wl["offsets"], 3, 32, 6)
+    with _ctx(d2, wl, "f32") as g, _ctx(d2, wl, "f32") as e:
+        e.set_graph(False)
+        for ctx in (g, e):
+            ctx.set_bucketing(0)
+            ctx.centroids_init(mem, 32)
+        for r in range(3):
+            lab_g, best_g, _ = g.assign(iters=40)
+            lab_e, best_e, _ = e.assign(iters=40)
+            assert np.array_equal(lab_g, lab_e) and np.array_equal(best_g,
+                                                                   best_e)
+            init = d2.D2_INIT_PRODUCT if r == 0 else d2.D2_INIT_CACHED
+            sg = g.barycenter(iters=20, init=init)
+            se = e.barycenter(iters=20, init=init)
+            assert sg["graph"] == 1 and se["graph"] == 0
+            assert sg["launches"] == se["launches"]
+            Xg, Wg = g.centroids_get()
+            Xe, We = e.centroids_get()
+            assert np.array_equal(Xg, Xe) and np.array_equal(Wg, We), r
+            tg, _ = g.objective(20)
+            te, _ = e.objective(20)
+            assert np.array_equal(tg, te)
+
+
 def test_autotune_then_parity(d2):
     """The autotuner restores the centroids, picks a valid schedule, and the
     tuned barycenter still matches the oracle."""
