@@ -966,11 +966,22 @@ __global__ void __launch_bounds__(256) k_iter_ba(Args<T> a) {
 template <typename T, int MP, int NS>
 __device__ __forceinline__ void aux_tile(const Args<T>& a, const Tile<T, MP>& tl,
                                          int k, int mode, const double* xrow,
-                                         const T* xl, T wi, T rho, T a2, T eps,
-                                         double& accw, double& accf,
-                                         double& accr, double* accx) {
+                                         const T (&xr)[4], const T* xl, T wi,
+                                         T rho, T a2, T eps, double& accw,
+                                         double& accf, double& accr,
+                                         double* accx) {
+  using V4 = typename Vec4<T>::type;
   const int d = a.d;
   const int lane = threadIdx.x & (kWave - 1);
+  // cost of slot r: for d <= 4 (stride 4, zero padded) one 4-wide load of
+  // the support point against the centroid row in registers, the same
+  // arithmetic in the same order as the direct difference over t < d
+  auto cost_of = [&](int r) -> T {
+    const int jc = tl.colc(r);
+    if (a.xs == 4)
+      return cost4<T>(xr, reinterpret_cast<const V4*>(a.X + (tl.o + jc) * 4)[0]);
+    return cost_generic<T>(xrow, a.X + (tl.o + jc) * a.xs, d);
+  };
   T p[NS], l[NS], cs[NS], wk[NS], el[NS], b[NS];
   bool v[NS];
 #pragma unroll
@@ -984,8 +995,7 @@ __device__ __forceinline__ void aux_tile(const Args<T>& a, const Tile<T, MP>& tl
     if (xl) cost_tile<T, MP, NS>(a, tl, xl, cs);
 #pragma unroll
     for (int r = 0; r < NS; ++r) {
-      T cv = xl ? cs[r]
-                : cost_generic<T>(xrow, a.X + (tl.o + tl.colc(r)) * a.xs, d);
+      T cv = xl ? cs[r] : cost_of(r);
       if (v[r]) {
         if (a.Cc) a.Cc[tl.eidx(r, a.m)] = cv;
         s += cv;
@@ -1001,8 +1011,7 @@ __device__ __forceinline__ void aux_tile(const Args<T>& a, const Tile<T, MP>& tl
       const int64_t e = tl.eidx(r, a.m);
       const int jc = tl.colc(r);
       wk[r] = a.W[tl.o + jc];
-      cs[r] = a.Cc ? a.Cc[e]
-                   : cost_generic<T>(xrow, a.X + (tl.o + jc) * a.xs, d);
+      cs[r] = a.Cc ? a.Cc[e] : cost_of(r);
       p[r] = cached ? a.P2[e] : wi * wk[r];
       p[r] = v[r] ? p[r] : T(0);
       wk[r] = v[r] ? wk[r] : T(0);
@@ -1086,6 +1095,12 @@ __global__ void __launch_bounds__(256) k_aux(Args<T> a, int mode) {
   const T a2 = (T)(kLog2e / rhod);
   const T wi = (rowok && (mode == kBF || mode == kA0)) ? (T)s_w[i] : T(0);
   const double* xrow = a.xc + ((int64_t)c * MP + (rowok ? i : 0)) * d;
+  T xr[4] = {T(0), T(0), T(0), T(0)};
+  if (a.xs == 4) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+      if (t < d && rowok) xr[t] = (T)xrow[t];
+  }
   const int nrec = MP * (d + 1);
   double* accx = s_dyn + (int64_t)wave * nrec;
   if (xrecs)
@@ -1101,8 +1116,8 @@ __global__ void __launch_bounds__(256) k_aux(Args<T> a, int mode) {
     const int k = uni(a.work[pos]);
     tl.setup(a.off, a.pofs, a.m, k);
     with_slots<R>(tl.nsl, [&]<int NS>() {
-      aux_tile<T, MP, NS>(a, tl, k, mode, xrow, xl, wi, rho, a2, eps, accw,
-                          accf, accr, accx);
+      aux_tile<T, MP, NS>(a, tl, k, mode, xrow, xr, xl, wi, rho, a2, eps,
+                          accw, accf, accr, accx);
     });
   }
   if (mode == kRho) {
