@@ -143,7 +143,8 @@ void free_instances(d2_ctx* c) {
   dfree(c->d_W);
   dfree(c->d_labels);
   dfree(c->d_best);
-  dfree(c->d_evals);
+  dfree(c->d_pairs);
+  c->last_pairs = 0;
   dfree(c->d_alist);
   c->alist_MP = 0;
   c->cls_MP = 0;
@@ -960,8 +961,7 @@ d2_status run_assign(d2_ctx* c, const d2_ot_params* p, float* ms_out) {
   a.wc = c->d_wc;
   a.labels = c->d_labels;
   a.best = c->d_best;
-  a.evaluated = c->d_evals;
-  a.costed = c->d_evals + 1;
+  a.counts = c->d_pairs;
   a.prune = p->prune ? 1 : 0;
   a.prev_valid = c->have_labels ? 1 : 0;
   {
@@ -1021,8 +1021,6 @@ d2_status run_assign(d2_ctx* c, const d2_ot_params* p, float* ms_out) {
     c->alist_MP = c->MP;
   }
   const int wpb = 4;
-  HIPCHK(c, hipMemsetAsync(c->d_evals, 0, 2 * sizeof(unsigned long long),
-                           c->stream));
   HIPCHK(c, hipEventRecord(c->ev0, c->stream));
   hipEvent_t pe = prof_begin(c);
   // one launch per slot class, each kernel sized for its class; the
@@ -1059,10 +1057,6 @@ d2_status run_assign(d2_ctx* c, const d2_ot_params* p, float* ms_out) {
   float ms = 0.f;
   HIPCHK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
   if (ms_out) *ms_out = ms;
-  unsigned long long ev[2] = {0, 0};
-  HIPCHK(c, hipMemcpy(ev, c->d_evals, sizeof(ev), hipMemcpyDeviceToHost));
-  c->last_evals = (int64_t)ev[0];
-  c->last_costed = (int64_t)ev[1];
   c->last_pairs = c->N * (int64_t)c->K;
   return D2_OK;
 }
@@ -1205,7 +1199,7 @@ d2_status d2_load_instances(d2_ctx* c, int64_t N, int32_t d,
   if ((s = dalloc(c, &c->d_W, c->esz() * n))) return s;
   if ((s = dalloc(c, (void**)&c->d_labels, sizeof(int32_t) * N))) return s;
   if ((s = dalloc(c, (void**)&c->d_best, sizeof(double) * N))) return s;
-  if ((s = dalloc(c, (void**)&c->d_evals, 2 * sizeof(unsigned long long))))
+  if ((s = dalloc(c, (void**)&c->d_pairs, 2 * sizeof(int32_t) * N)))
     return s;
   HIPCHK(c, hipMemcpy(c->d_off, offsets, sizeof(int64_t) * (N + 1),
                       hipMemcpyHostToDevice));
@@ -1379,8 +1373,21 @@ d2_status d2_assign(d2_ctx* c, const d2_ot_params* p, int32_t* labels_out,
 d2_status d2_assign_pairs(const d2_ctx* c, int64_t* evaluated,
                           int64_t* costed, int64_t* total) {
   if (!c) return D2_EINVAL;
-  if (evaluated) *evaluated = c->last_evals;
-  if (costed) *costed = c->last_costed;
+  // sums of the per-instance counts of the last assignment
+  int64_t ev = 0, co = 0;
+  if (c->last_pairs > 0) {
+    std::vector<int32_t> cnt(2 * (size_t)c->N);
+    if (hipSetDevice(c->device) != hipSuccess ||
+        hipMemcpy(cnt.data(), c->d_pairs, sizeof(int32_t) * cnt.size(),
+                  hipMemcpyDeviceToHost) != hipSuccess)
+      return D2_EDEVICE;
+    for (size_t q = 0; q < cnt.size(); q += 2) {
+      ev += cnt[q];
+      co += cnt[q + 1];
+    }
+  }
+  if (evaluated) *evaluated = ev;
+  if (costed) *costed = co;
   if (total) *total = c->last_pairs;
   return D2_OK;
 }

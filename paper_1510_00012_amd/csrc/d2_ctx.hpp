@@ -40,11 +40,12 @@ struct d2_ctx {
   uint64_t label_gen = 0;  // bumped whenever h_labels changes
   int32_t* d_labels = nullptr;
   double* d_best = nullptr;
-  unsigned long long* d_evals = nullptr;
+  int32_t* d_pairs = nullptr;  // N x 2: per instance of the last assignment,
+                               // transports run and cost blocks formed
   void* d_cmu = nullptr;   // d x K centroid means (device dtype)
   void* d_crad = nullptr;  // K centroid support radii
   void* d_xct = nullptr;   // K x MP x xs centroid supports (device dtype)
-  int64_t last_evals = 0, last_costed = 0, last_pairs = 0;
+  int64_t last_pairs = 0;  // pairs of the last assignment (0: none yet)
   // assignment: instance ids grouped by slot class (one launch per class,
   // each kernel specialised for its class), built for the current pad(m)
   int32_t* d_alist = nullptr;

@@ -1198,8 +1198,8 @@ template <typename T> struct AssignArgs {
   const double* wc;  // K x MP
   int32_t* labels;      // out; with prev_valid also the previous labels
   double* best;
-  unsigned long long* evaluated;  // pairs run through the iterations
-  unsigned long long* costed;     // pairs whose cost block was formed
+  int32_t* counts;      // N x 2 per instance: pairs run through the
+                        // iterations, pairs whose cost block was formed
   const T* cmu;         // d x K weighted mean of each centroid's support
   const T* crad;        // K  radius of the support around that mean
   const T* xct;         // K x MP x xs centroid supports in the device dtype
@@ -1528,8 +1528,9 @@ __global__ void __launch_bounds__(256) k_assign(AssignArgs<T> a) {
   if (lane == 0) {
     a.labels[k] = bestc;
     a.best[k] = bestv;
-    if (a.evaluated) atomicAdd(a.evaluated, (unsigned long long)nevals);
-    if (a.costed) atomicAdd(a.costed, (unsigned long long)ncost);
+    // per-instance counts (plain stores: a counter shared by all
+    // wavefronts serialises its atomic updates)
+    reinterpret_cast<int2*>(a.counts)[k] = make_int2(nevals, ncost);
   }
 }
 
