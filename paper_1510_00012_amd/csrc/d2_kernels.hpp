@@ -578,6 +578,54 @@ __device__ __forceinline__ void add_support_terms(const Args<T>& a,
   if (lane < MP && rr > T(0)) acc[lane * (d + 1) + d] += 1.0;
 }
 
+// The same support record for d <= 4 (stride 4) accumulated in registers:
+// each lane adds its own partial sum_j b_ij y_j,t / r_i (its columns only)
+// and the indicator r_i > 0 in FP64 across the wavefront's tiles; the sums
+// over the lanes of a row are formed once, by flush_support4.
+struct XAcc4 {
+  double u[4] = {0.0, 0.0, 0.0, 0.0};
+  double n = 0.0;
+};
+template <typename T, int MP, int NS>
+__device__ __forceinline__ void add_support_terms4(const Args<T>& a,
+                                                   const Tile<T, MP>& tl,
+                                                   const T (&b)[NS], T rr,
+                                                   XAcc4& xa) {
+  using V4 = typename Vec4<T>::type;
+  const T ir = rcp_sum(rr);
+  T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0);
+#pragma unroll
+  for (int r = 0; r < NS; ++r) {
+    const V4 y = reinterpret_cast<const V4*>(a.X + (tl.o + tl.colc(r)) * 4)[0];
+    s0 = fma(b[r], y.x, s0);
+    s1 = fma(b[r], y.y, s1);
+    s2 = fma(b[r], y.z, s2);
+    s3 = fma(b[r], y.w, s3);
+  }
+  xa.u[0] += (double)(s0 * ir);
+  xa.u[1] += (double)(s1 * ir);
+  xa.u[2] += (double)(s2 * ir);
+  xa.u[3] += (double)(s3 * ir);
+  if (tl.g == 0 && rr > T(0)) xa.n += 1.0;
+}
+// Row sums of the register accumulators into the wavefront's record
+// acc[MP][d+1] (lanes < MP hold row lane).
+template <int MP>
+__device__ __forceinline__ void flush_support4(const XAcc4& xa, int d,
+                                               double* acc) {
+  const int lane = threadIdx.x & (kWave - 1);
+  double u[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) u[t] = sum_row<MP>(xa.u[t]);
+  if (lane < MP) {
+    double* ap = acc + lane * (d + 1);
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+      if (t < d) ap[t] += u[t];
+    ap[d] += xa.n;
+  }
+}
+
 // The cluster's support rows in LDS as T, row stride xs + 4 (zero padded
 // past d), for the cost work of a launch (one cluster per workgroup).
 template <typename T, int MP>
@@ -808,7 +856,8 @@ __device__ __forceinline__ void ba_tile(const Args<T>& a, const Tile<T, MP>& tl,
                                         const T* xl, T xnorm, T wi, T rho,
                                         T a2, T eps, double& accw,
                                         double& accf, double& accr,
-                                        double* accx, SupAcc<MP>* sa) {
+                                        double* accx, SupAcc<MP>* sa,
+                                        XAcc4& xa4) {
   using V4 = typename Vec4<T>::type;
   constexpr uint32_t es = sizeof(T);
   // one resource per array over this tile (uniform), 32-bit lane offsets;
@@ -869,7 +918,12 @@ __device__ __forceinline__ void ba_tile(const Args<T>& a, const Tile<T, MP>& tl,
     // support-update launch of a large-d FP32 context (matrix cores)
     support_mfma<MP, NS>(a, tl, b, rr, rX, *sa);
   } else if constexpr (VAR != kVarPlain) {
-    if (a.xout) add_support_terms<T, MP, NS>(a, tl, b, rr, accx);
+    if (a.xout) {
+      if constexpr (ONFLY)
+        add_support_terms4<T, MP, NS>(a, tl, b, rr, xa4);
+      else
+        add_support_terms<T, MP, NS>(a, tl, b, rr, accx);
+    }
   }
 }
 
@@ -937,6 +991,7 @@ __global__ void __launch_bounds__(256) k_iter_ba(Args<T> a) {
     }
   }
   double accw = 0.0, accf = 0.0, accr = 0.0;
+  XAcc4 xa4;  // support terms of d <= 4 launches, in registers
   SupAcc<(MP == 16 || MP == 32) ? MP : 32> sacc;
   SupAcc<MP>* sap = nullptr;
   if constexpr (VAR == kVarSupport) {
@@ -952,10 +1007,12 @@ __global__ void __launch_bounds__(256) k_iter_ba(Args<T> a) {
     }
     with_slots<R>(tl.nsl, [&]<int NS>() {
       ba_tile<T, MP, NS, ONFLY, VAR>(a, tl, xr, xrow, xl, xnorm, wi, rho, a2,
-                                     eps, accw, accf, accr, accx, sap);
+                                     eps, accw, accf, accr, accx, sap, xa4);
     });
   }
   if constexpr (VAR == kVarSupport) sacc.flush(a.d, accx);
+  if constexpr (ONFLY && VAR != kVarPlain)
+    if (a.xout) flush_support4<MP>(xa4, a.d, accx);
   write_w_record<MP>(accw, accf, accr, a.part, a.ps, ch);
   if (a.xout) write_x_record(s_dyn, nrec, a.xout, ch);
 }
