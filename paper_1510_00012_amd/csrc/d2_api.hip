@@ -625,7 +625,11 @@ d2_status launch_fin(d2_ctx* c, const d2k::FinArgs& f, int mode, int& nl) {
 template <typename T>
 d2_status launch_aux(d2_ctx* c, const d2k::Args<T>& a0, int mode, int& nl) {
   const auto& kt = kern<T>();
-  auto fn = kt.aux[ilog2(c->MP) - 3][ilog2(c->R)];
+  const int ma = ilog2(c->MP) - 3, mr = ilog2(c->R);
+  auto fn = mode == d2k::kRho ? kt.auxm[0][ma][mr]
+            : mode == d2k::kA0 ? kt.auxm[1][ma][mr]
+            : mode == d2k::kBF ? kt.auxm[2][ma][mr]
+                               : kt.aux[ma][mr];
   if (!fn) return c->fail(D2_EINVAL, "no kernel for this tile shape");
   d2k::Args<T> a = a0;
   int waves = c->waves;

@@ -1020,14 +1020,15 @@ __global__ void __launch_bounds__(256) k_iter_ba(Args<T> a) {
 // ---------------------------------------------------------------------------
 // Auxiliary kernel: cost sums / first phase A / last phase B / support only
 // ---------------------------------------------------------------------------
-template <typename T, int MP, int NS>
+template <typename T, int MP, int NS, int MODE>
 __device__ __forceinline__ void aux_tile(const Args<T>& a, const Tile<T, MP>& tl,
-                                         int k, int mode, const double* xrow,
+                                         int k, int mode_arg, const double* xrow,
                                          const T (&xr)[4], const T* xl, T wi,
                                          T rho, T a2, T eps, double& accw,
                                          double& accf, double& accr,
                                          double* accx) {
   using V4 = typename Vec4<T>::type;
+  const int mode = MODE >= 0 ? MODE : mode_arg;
   const int d = a.d;
   const int lane = threadIdx.x & (kWave - 1);
   // cost of slot r: for d <= 4 (stride 4, zero padded) one 4-wide load of
@@ -1122,8 +1123,11 @@ __device__ __forceinline__ void aux_tile(const Args<T>& a, const Tile<T, MP>& tl
   (void)lane;
 }
 
-template <typename T, int MP, int R>
-__global__ void __launch_bounds__(256) k_aux(Args<T> a, int mode) {
+// MODE >= 0: a kernel fixed to that mode (the other modes' paths and their
+// registers compiled out); MODE < 0: the mode from the argument
+template <typename T, int MP, int R, int MODE = -1>
+__global__ void __launch_bounds__(256) k_aux(Args<T> a, int mode_arg) {
+  const int mode = MODE >= 0 ? MODE : mode_arg;
   extern __shared__ double s_dyn[];  // [nwaves][MP][d+1] support terms
   __shared__ double s_w[MP];
   __shared__ double s_x[MP * 4];
@@ -1173,7 +1177,7 @@ __global__ void __launch_bounds__(256) k_aux(Args<T> a, int mode) {
     const int k = uni(a.work[pos]);
     tl.setup(a.off, a.pofs, a.m, k);
     with_slots<R>(tl.nsl, [&]<int NS>() {
-      aux_tile<T, MP, NS>(a, tl, k, mode, xrow, xr, xl, wi, rho, a2, eps,
+      aux_tile<T, MP, NS, MODE>(a, tl, k, mode, xrow, xr, xl, wi, rho, a2, eps,
                           accw, accf, accr, accx);
     });
   }
@@ -1603,6 +1607,7 @@ template <typename T> struct KernTable {
   BA bax[4][6] = {};    // support-update launches, FP32, d > 4, MP 16 / 32
   BA bcx[6] = {};       // cost-recomputation launches, FP32, d <= 64, MP 32
   AX aux[4][6] = {};
+  AX auxm[3][4][6] = {};  // fixed to kRho, kA0, kBF
   AS asg[4][6] = {};
 };
 using FinFn = void (*)(FinArgs, int);

@@ -14,6 +14,9 @@ void add_kernels(KernTable<T>& t) {
     // launches that form no support terms
     t.bap[0][a][b] = &k_iter_ba<T, MP, R, false, kVarPlain>;
     t.bap[1][a][b] = &k_iter_ba<T, MP, R, true, kVarPlain>;
+    t.auxm[0][a][b] = &k_aux<T, MP, R, kRho>;
+    t.auxm[1][a][b] = &k_aux<T, MP, R, kA0>;
+    t.auxm[2][a][b] = &k_aux<T, MP, R, kBF>;
   } else {
     t.ba[0][a][b] = &k_iter_ba<T, MP, R, false>;
     t.ba[1][a][b] = &k_iter_ba<T, MP, R, true>;
@@ -27,7 +30,8 @@ void add_kernels(KernTable<T>& t) {
 }
 
 // Tiles up to 2048 entries: R * (64 / MP) columns of MP rows, m_k <= 64.
-// PLAIN: the kernels without support terms (a translation unit of their own)
+// PLAIN: the kernels without support terms and the auxiliary kernels fixed
+// to one mode (a translation unit of their own)
 template <typename T, bool PLAIN> void fill_table(KernTable<T>& t) {
   add_kernels<T, 8, 1, PLAIN>(t);  add_kernels<T, 8, 2, PLAIN>(t);
   add_kernels<T, 8, 4, PLAIN>(t);  add_kernels<T, 8, 8, PLAIN>(t);
