@@ -2,18 +2,21 @@
 """Benchmark of the B-ADMM / D2-clustering hot path on one MI355X.
 
 One step = one round of D2-clustering over the whole synthetic workload:
-the assignment step (B-ADMM transport against every centroid) followed by
-the batched B-ADMM barycenter update of all K clusters (T iterations,
-support update every tau, cached-plan warm start).  Default workload: K=16
-clusters, N=65,536 colour-like ragged instances (m_k uniform in [4,16]),
-d=3, centroid support m=16, T=100, 10 rounds (1 warm-up + 9 timed).
+the assignment step (B-ADMM transport against every centroid, exact
+pruning) followed by the batched B-ADMM barycenter update of all K clusters
+(T iterations, support update every tau, cached-plan warm start).  Default
+workload: the largest single-GPU configuration, K=256 clusters, N=2,000,000
+ragged instances (m_k uniform in [4,32]) in d=16 from a 1024-component
+Gaussian mixture, centroid support m=16, T=50; 5 rounds (1 warm-up + 4
+timed).  Plans Pi1, Pi2, Lambda and the cost cache stay resident in HBM.
 
 value  = N * T * steps / (wall time of the timed steps): B-ADMM
          instance-iterations per second of whole rounds (assignment time
          included), inputs resident in HBM.
 Also reported: the barycenter-only rate, per-kernel HIP-event times, the
 roofline of the dominant kernel (and of the plan-update kernel), and the FP64
-CPU oracle timed on a bounded sample of the same workload.
+CPU oracle timed on bounded slices of the same workload (extrapolated to the
+whole round, at all host cores and at one thread).
 """
 from __future__ import annotations
 
@@ -90,50 +93,101 @@ def load_traffic(kernel, workload, src_hash):
     return rec.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(wl, Xc, Wc, T, tau, T_assign, target_s=15.0):
-    """The FP64 oracle on a bounded sample of the workload: one round
-    (assignment of the sample, then B-ADMM per cluster of the sample)."""
+def _subset(wl, idx):
+    """Instances idx of a workload as a workload of their own."""
+    off, X, W = wl["offsets"], wl["X"], wl["W"]
+    idx = np.asarray(idx, dtype=np.int64)
+    sizes = off[idx + 1] - off[idx]
+    o = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    rows = np.concatenate([np.arange(off[k], off[k + 1]) for k in idx])
+    return {"offsets": o, "X": np.ascontiguousarray(X[rows]),
+            "W": np.ascontiguousarray(W[rows])}
+
+
+def cpu_baseline(wl, Xc, Wc, labels, T, tau, T_assign, target_s=20.0):
+    """The FP64 oracle on bounded slices of one round of the workload,
+    extrapolated to the whole round.
+
+    Barycenter: whole clusters (the GPU's labels, taken in index order) run
+    through the oracle's B-ADMM (T iterations, tau) until about 35 % of the
+    time budget is used; the time is scaled by (plan entries of the
+    workload) / (plan entries of the slice) -- the method's work is linear
+    in the plan entries (Sec. 5 complexity).  Assignment: an evenly spaced
+    instance sample run through the oracle's exhaustive assignment (T_assign
+    iterations per instance-centroid pair), scaled by (support points of the
+    workload) / (support points of the sample).  Both legs are timed with
+    all host threads and again with one thread (each about a quarter of the
+    budget at one thread)."""
     import oracle
     oracle.build(force=False)
-    off, X, W = wl["offsets"], wl["X"], wl["W"]
+    off = wl["offsets"]
     N = len(off) - 1
+    K, m = Wc.shape
+    sizes = np.diff(off)
+    n_tot = int(off[-1])
+    members = [np.nonzero(labels == c)[0] for c in range(K)]
+    order = [c for c in range(K) if len(members[c])]
 
-    def sub(idx):
-        sizes = off[idx + 1] - off[idx]
-        o = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
-        rows = np.concatenate([np.arange(off[k], off[k + 1]) for k in idx])
-        return {"offsets": o, "X": X[rows], "W": W[rows]}
+    def bary_time(budget):
+        t = 0.0
+        cols = 0
+        used = []
+        for c in order:
+            sub = _subset(wl, members[c])
+            t0 = time.perf_counter()
+            oracle.barycenter(sub, np.arange(len(members[c])), Xc[c], Wc[c],
+                              T=T, tau=tau)
+            t += time.perf_counter() - t0
+            cols += int(sizes[members[c]].sum())
+            used.append(c)
+            if t >= budget:
+                break
+        return t * n_tot / cols, len(used), cols
 
-    def run(S):
-        idx = np.linspace(0, N - 1, S).astype(np.int64)
-        sw = sub(idx)
-        t0 = time.perf_counter()
-        lab, _, _ = oracle.assign(sw, Xc, Wc, T=T_assign)
-        t1 = time.perf_counter()
-        for c in range(len(Wc)):
-            mem = np.nonzero(lab == c)[0]
-            if len(mem):
-                oracle.barycenter(sw, mem, Xc[c], Wc[c], T=T, tau=tau)
-        t2 = time.perf_counter()
-        return t1 - t0, t2 - t1
+    def assign_time(budget, S):
+        # the oracle's assignment hands out instances 64 at a time per
+        # thread, so an all-thread sample starts at 64 instances per thread
+        while True:
+            idx = np.linspace(0, N - 1, S).astype(np.int64)
+            sub = _subset(wl, idx)
+            t0 = time.perf_counter()
+            oracle.assign(sub, Xc, Wc, T=T_assign)
+            t = time.perf_counter() - t0
+            if t >= budget or S >= N:
+                return t * n_tot / int(sub["offsets"][-1]), S
+            S = int(min(N, S * max(2.0, min(8.0, budget / max(t, 1e-3)))))
 
-    pa, pb = run(512)
-    per = (pa + pb) / 512
-    S = int(min(N, max(512, target_s / max(per, 1e-9))))
-    ta, tb = run(S)
-    return {"value": S * T / (ta + tb), "unit": "instance-iterations/s",
-            "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"{S} of {N} instances (evenly spaced), one round: "
-                      f"assignment ({T_assign} it/pair, {ta:.1f}s) + "
-                      f"barycenter per cluster ({T} it, {tb:.1f}s)"}
+    threads = oracle.num_threads()
+    tb, nb, cb = bary_time(0.35 * target_s)
+    ta, sa = assign_time(0.15 * target_s, min(N, 64 * threads))
+    oracle.set_num_threads(1)
+    try:
+        tb1, nb1, cb1 = bary_time(0.25 * target_s)
+        ta1, sa1 = assign_time(0.1 * target_s, 8)
+    finally:
+        oracle.set_num_threads(threads)
+    return {"value": N * T / (ta + tb), "unit": "instance-iterations/s",
+            "cores": threads, "kind": "oracle",
+            "sample": f"extrapolated from slices of one round: barycenter of "
+                      f"{nb} whole clusters ({cb} of {n_tot} support points, "
+                      f"{T} it, scaled by plan entries -> {tb:.1f}s), "
+                      f"exhaustive assignment of {sa} evenly spaced instances "
+                      f"against all {K} centroids ({T_assign} it/pair, scaled "
+                      f"by support points -> {ta:.1f}s)",
+            "barycenter_s_extrapolated": tb, "assign_s_extrapolated": ta,
+            "single_thread": {
+                "value": N * T / (ta1 + tb1), "cores": 1,
+                "sample": f"barycenter of {nb1} clusters ({cb1} support "
+                          f"points -> {tb1:.1f}s), assignment of {sa1} "
+                          f"instances (-> {ta1:.1f}s), extrapolated as above"}}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=9)
+    ap.add_argument("--steps", type=int, default=4)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="gmm_d3_n65536_k16")
+    ap.add_argument("--workload", default="gmm_d16_n2000000_k256")
     ap.add_argument("--iters", type=int, default=None)
     ap.add_argument("--profile-rounds", type=int, default=3,
                     help="host-issued rounds timed per kernel with HIP events")
@@ -144,7 +198,7 @@ def main():
                     help="tune the launch schedule now instead of using the "
                          "recorded one")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the multi-GPU path (sharding "
@@ -177,6 +231,10 @@ def main():
         torch.cuda.synchronize()
         del src, dst
         log(f"[bench] calibration copy of {args.copy_mib} MiB done")
+    # achievable-bandwidth reference: the library's plain copy kernel
+    copy_gbs, copy_ms = d2.copy_probe(0, 4096, 10)
+    log(f"[bench] device-copy probe: {copy_gbs:.0f} GB/s (4 GiB copy, "
+        f"{copy_ms:.3f} ms)")
     stream = torch.cuda.Stream()
     ctx = d2.D2Context(0, "f32", stream=stream.cuda_stream)
     ctx.load_instances(wl["offsets"], wl["X"], wl["W"])
@@ -251,6 +309,8 @@ def main():
         ach = b / avg_s / 1e9
         return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                "copy_probe_gbs": copy_gbs,
+                "frac_of_copy_probe": ach / copy_gbs,
                 "traffic": load_traffic("k_iter_ba", args.workload, src_hash),
                 "kernel": "k_iter_ba", "avg_launch_ms": 1000 * avg_s,
                 "bytes_per_launch": b}
@@ -300,9 +360,12 @@ def main():
     }
     if not args.no_cpu_baseline:
         Xc, Wc = ctx.centroids_get()
-        log("[bench] timing the FP64 CPU oracle on a sample")
-        rec["cpu_baseline"] = cpu_baseline(wl, Xc, Wc, T, tau, T_assign,
+        labels = ctx.labels_get()
+        log("[bench] timing the FP64 CPU oracle on slices of the workload")
+        rec["cpu_baseline"] = cpu_baseline(wl, Xc, Wc, labels, T, tau,
+                                           T_assign,
                                            target_s=args.cpu_seconds)
+        log(f"[bench] cpu baseline: {rec['cpu_baseline']['sample']}")
     ctx.close()
     print(json.dumps(rec), flush=True)
 

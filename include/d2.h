@@ -112,7 +112,12 @@ d2_status d2_load_instances(d2_ctx* ctx, int64_t N, int32_t d,
                             const double* W);
 
 /* Set the K centroids: Xc is K x m x d, Wc is K x m (rows in the simplex,
- * |sum - 1| <= 1e-6, renormalised).  Requires loaded instances. */
+ * |sum - 1| <= 1e-6, renormalised).  Requires loaded instances.  With K and
+ * m unchanged the plan cache of the last d2_barycenter is kept, so that a
+ * caller may continue a clustering run from centroids it adjusted; a caller
+ * setting unrelated centroids passes D2_INIT_PRODUCT to the next
+ * d2_barycenter.  d2_centroids_init and an accepted d2_ws_propose drop the
+ * cache. */
 d2_status d2_centroids_set(d2_ctx* ctx, int32_t K, int32_t m,
                            const double* Xc, const double* Wc);
 /* Copy the centroids out (Xc: K x m x d, Wc: K x m). */
@@ -250,6 +255,16 @@ d2_status d2_set_bucketing(d2_ctx* ctx, int32_t min_pct);
 d2_status d2_autotune(d2_ctx* ctx, const d2_badmm_params* p,
                       int32_t* chunk_out, int32_t* waves_out,
                       int32_t* bucket_out, double* ms_best);
+
+/* Achievable-bandwidth probe (not part of the paper: the reference point
+ * beside the published HBM peak for the plan-update roofline).  Copies a
+ * buffer of `bytes` (>= 1 MiB; rounded down to 16 bytes) to a second one on
+ * `device` with a plain vectorised kernel, reps + 1 times; the fastest of
+ * the last reps launches gives *gbs = 2 * bytes / time (read + write, in
+ * GB/s) and *ms its duration (may be NULL).  Allocates and frees its two
+ * buffers; D2_ENOMEM if they do not fit. */
+d2_status d2_copy_probe(int device, int64_t bytes, int32_t reps, double* gbs,
+                        double* ms);
 
 /* Sizes: N, n, d, K, m of the context (any pointer may be NULL). */
 d2_status d2_sizes(const d2_ctx* ctx, int64_t* N, int64_t* n, int32_t* d,

@@ -1065,6 +1065,24 @@ d2_status run_assign(d2_ctx* c, const d2_ot_params* p, float* ms_out) {
   return D2_OK;
 }
 
+// Device-copy probe: each thread moves 4 x 16 bytes per step (all four
+// loads issued before the stores), grid-stride over the buffer.
+__global__ void __launch_bounds__(256)
+    k_copy_probe(const float4* __restrict__ src, float4* __restrict__ dst,
+                 int64_t n4) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i + 3 * stride < n4; i += 4 * stride) {
+    const float4 a = src[i], b = src[i + stride], c = src[i + 2 * stride],
+                 d = src[i + 3 * stride];
+    dst[i] = a;
+    dst[i + stride] = b;
+    dst[i + 2 * stride] = c;
+    dst[i + 3 * stride] = d;
+  }
+  for (; i < n4; i += stride) dst[i] = src[i];
+}
+
 bool finite_all(const double* p, size_t n) {
   for (size_t q = 0; q < n; ++q)
     if (!std::isfinite(p[q])) return false;
@@ -1318,7 +1336,10 @@ d2_status d2_centroids_init(d2_ctx* c, int32_t K, int32_t m,
     merge_support(mk, d, y.data(), wy.data(), m, &Xc[(size_t)q * m * d],
                   &Wc[(size_t)q * m]);
   }
-  return d2_centroids_set(c, K, m, Xc.data(), Wc.data());
+  if ((s = d2_centroids_set(c, K, m, Xc.data(), Wc.data()))) return s;
+  // fresh centroids: cached plans of earlier ones are not a warm start
+  c->have_cache = false;
+  return D2_OK;
 }
 
 d2_status d2_labels_set(d2_ctx* c, const int32_t* labels) {
@@ -1638,6 +1659,50 @@ d2_status d2_autotune(d2_ctx* c, const d2_badmm_params* p,
   if (bucket_out) *bucket_out = bb;
   if (ms_out) *ms_out = best;
   return D2_OK;
+}
+
+d2_status d2_copy_probe(int device, int64_t bytes, int32_t reps,
+                        double* gbs, double* ms) {
+  if (bytes < (1 << 20) || reps < 1 || !gbs) return D2_EINVAL;
+  if (hipSetDevice(device) != hipSuccess) return D2_EDEVICE;
+  const int64_t n4 = bytes / 16;
+  void *a = nullptr, *b = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  d2_status st = D2_OK;
+  float best = 0.f;
+  if (hipMalloc(&a, n4 * 16) != hipSuccess ||
+      hipMalloc(&b, n4 * 16) != hipSuccess) {
+    st = D2_ENOMEM;
+  } else if (hipMemset(a, 0, n4 * 16) != hipSuccess ||
+             hipEventCreate(&e0) != hipSuccess ||
+             hipEventCreate(&e1) != hipSuccess) {
+    st = D2_EDEVICE;
+  } else {
+    // 256 CUs x 8 workgroups of 256 threads
+    for (int r = 0; r <= reps && st == D2_OK; ++r) {
+      (void)hipEventRecord(e0, nullptr);
+      hipLaunchKernelGGL(k_copy_probe, dim3(2048), dim3(256), 0, nullptr,
+                         (const float4*)a, (float4*)b, n4);
+      (void)hipEventRecord(e1, nullptr);
+      if (hipEventSynchronize(e1) != hipSuccess) {
+        st = D2_EDEVICE;
+        break;
+      }
+      float t = 0.f;
+      (void)hipEventElapsedTime(&t, e0, e1);
+      if (r > 0 && (best == 0.f || t < best)) best = t;  // first: warm-up
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (a) (void)hipFree(a);
+  if (b) (void)hipFree(b);
+  (void)hipGetLastError();
+  if (st == D2_OK) {
+    *gbs = 2.0 * (double)(n4 * 16) / (best * 1e-3) / 1e9;
+    if (ms) *ms = best;
+  }
+  return st;
 }
 
 d2_status d2_sizes(const d2_ctx* c, int64_t* N, int64_t* n, int32_t* d,

@@ -1387,11 +1387,16 @@ d2_status d2_ws_propose(d2_ws* w, d2_ctx* c, int32_t gate, int32_t* accepted,
   WSCHK(w, hipMemcpyAsync(bqv.data(), w->bq, sizeof(double) * K,
                           hipMemcpyDeviceToHost, st));
   WSCHK(w, hipStreamSynchronize(st));
+  bool any = false;
   for (int q = 0; q < K; ++q) {
     if (accepted) accepted[q] = av[q];
     if (bound_prop) bound_prop[q] = av[q] < 0 ? NAN : bpv[q];
     if (bound_plain) bound_plain[q] = av[q] < 0 ? NAN : bqv[q];
+    any = any || av[q] == 1;
   }
+  // the cached plans belong to the replaced centroids: a following
+  // D2_INIT_CACHED call starts from the product coupling
+  if (any) c->have_cache = false;
   return D2_OK;
 }
 

@@ -29,7 +29,8 @@ EXPORTS = [
     "d2_support_update", "d2_cluster", "d2_objective", "d2_plans_get",
     "d2_sizes", "d2_set_profiling", "d2_kernel_stats", "d2_set_schedule",
     "d2_assign_pairs", "d2_set_graph", "d2_autotune",
-    "d2_set_bucketing", "d2_objective_feasible", "d2_residual", "d2_ws_param_count", "d2_ws_create",
+    "d2_set_bucketing", "d2_objective_feasible", "d2_residual",
+    "d2_copy_probe", "d2_ws_param_count", "d2_ws_create",
     "d2_ws_destroy", "d2_ws_last_error", "d2_ws_params_set",
     "d2_ws_params_get", "d2_ws_targets_from", "d2_ws_grad",
     "d2_ws_train_step", "d2_ws_propose",
@@ -126,6 +127,7 @@ def load_library(path: str = LIB_PATH):
         "d2_kernel_stats": ([_p, ctypes.POINTER(KernelStat), _i32, _p, _i32],
                             ctypes.c_int),
         "d2_objective_feasible": ([_p, _p, _p], ctypes.c_int),
+        "d2_copy_probe": ([ctypes.c_int, _i64, _i32, _p, _p], ctypes.c_int),
         "d2_ws_param_count": ([_i32, _i32, _i32], _i64),
         "d2_ws_create": ([ctypes.POINTER(_p), _i32, _i32, _i32, _i32, _p],
                          ctypes.c_int),
@@ -385,6 +387,18 @@ class D2Context:
         bufs = [np.empty(self.m * mk) for _ in range(3)]
         self._chk(self.lib.d2_plans_get(self.h, int(k), *[_ptr(b) for b in bufs]))
         return tuple(b.reshape(mk, self.m).T.copy() for b in bufs)
+
+
+def copy_probe(device=0, mib=2048, reps=10):
+    """(GB/s, ms) of the library's plain device-copy kernel over a buffer of
+    `mib` MiB (read + write bytes per second of the fastest repetition)."""
+    lib = load_library()
+    g, t = ctypes.c_double(0), ctypes.c_double(0)
+    st = lib.d2_copy_probe(int(device), int(mib) << 20, int(reps),
+                           ctypes.byref(g), ctypes.byref(t))
+    if st != D2_OK:
+        raise D2Error(st, "d2_copy_probe failed")
+    return g.value, t.value
 
 
 def ws_param_count(m, d, hidden):

@@ -1,10 +1,16 @@
 """GPU (HIP, through the C ABI) vs the FP64 oracle.
 
 Bars (stated in the tests):
-  FP64 device arithmetic: objective trace, centroids rel <= 1e-10.
-  FP32 device arithmetic: objective trace rel <= 1e-5; row/column sums of
-  Pi1 and Pi2 within 1e-6 of the oracle's; centroid weights/supports within
+  FP64 device arithmetic: objective trace, centroids rel <= 1e-10; every
+  entry of Pi1 and Pi2 within 1e-12 of the oracle's, Lambda / rho within
+  1e-10.
+  FP32 device arithmetic: objective trace rel <= 1e-5; every entry of Pi1
+  and Pi2 (hence their row/column sums) within 1e-6 of the oracle's;
+  Lambda / rho within PLAN_TOL["f32"][2]; centroid weights/supports within
   1e-5 (absolute, values are O(1)).
+Lambda is compared divided by its cluster's rho: Eq. (badmm2) adds
+rho (Pi1 - Pi2) per iteration, so Lambda / rho is the running sum of plan
+differences, a quantity on the plans' scale.
 Sizes span several workgroup chunks per cluster and ragged support sizes.
 """
 import numpy as np
@@ -12,9 +18,32 @@ import pytest
 
 import oracle
 from synth.generators import make_workload, pick_init_members
-from tests._helpers import marginal_errors, oracle_barycenters
+from tests._helpers import oracle_barycenters, plan_errors
 
 pytestmark = pytest.mark.gpu
+
+# (Pi1 entries, Pi2 entries, Lambda / rho entries, marginals), absolute.
+# FP32: an entry is at most its column's weight, so the 1e-6 bar on the
+# marginals bounds the entries too; Lambda / rho sums the per-iteration
+# differences Pi1 - Pi2 (T of them), whose FP32 rounding errors, a few ulp of
+# values below 1 each, are bounded by 2e-7 * T in the worst case and largely
+# cancel: 2e-5 covers T = 100 with margin.
+PLAN_TOL = {"f64": (1e-12, 1e-12, 1e-10, 1e-12),
+            "f32": (1e-6, 1e-6, 2e-5, 1e-6)}
+
+
+def check_plans(ctx, wl, plans, ks, rhos, labels, dtype, local=None,
+                tag=""):
+    """Every entry of Pi1, Pi2 and Lambda / rho of instances ks against the
+    oracle's plans (PLAN_TOL)."""
+    errs = plan_errors(ctx, wl, plans, ks, lambda k: rhos[labels[k]],
+                       local=local)
+    print(f"  plan errors {tag} {dtype}: Pi1 {errs[0]:.3g} Pi2 {errs[1]:.3g}"
+          f" Lambda/rho {errs[2]:.3g} marginals {errs[3]:.3g}", flush=True)
+    for e, t, name in zip(errs, PLAN_TOL[dtype],
+                          ("Pi1", "Pi2", "Lambda/rho", "marginals")):
+        assert e <= t, (tag, name, e, t)
+    return errs
 
 
 @pytest.fixture(scope="module")
@@ -61,8 +90,8 @@ def test_single_cluster_barycenter(d2, dtype, tol):
         assert _rel(g_tr[:, 0], tr[0]) < tol, np.max(np.abs(g_tr[:, 0] / tr[0] - 1))
         assert np.abs(Wg - Wo).max() < tol
         assert np.abs(Xg - Xo).max() < tol
-        me = marginal_errors(ctx, wl, plans, range(0, 256, 7))
-        assert me < (1e-12 if dtype == "f64" else 1e-6), me
+        check_plans(ctx, wl, plans, range(256), rhos, lab, dtype,
+                    tag="single")
         assert st["launches"] >= 200
 
 
@@ -101,9 +130,53 @@ def test_multi_cluster_barycenter_ragged(d2, dtype):
         assert np.array_equal(Xg[4], Xc[4])
         np.testing.assert_allclose(Wg[4], Wc[4] / Wc[4].sum(), rtol=0,
                                    atol=1e-16)
-        ks = np.linspace(0, 5999, 40).astype(int)
-        me = marginal_errors(ctx, wl, plans, ks)
-        assert me < (1e-12 if dtype == "f64" else 1e-6), me
+        ks = np.linspace(0, 5999, 300).astype(int)
+        check_plans(ctx, wl, plans, ks, rhos, lab, dtype, tag="multi")
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("name,m,rule,fixed", [
+    ("gmm_d3_n65536_k16", 16, 2, False),
+    ("gmm_d3_n65536_k16", 16, 1, True),
+    ("gmm_d3_n65536_k16", 16, 2, True),
+    ("gmm_d16_n2000000_k256", 16, 2, False),
+    ("gmm_d16_n2000000_k256", 16, 1, True),
+    ("topic_d64_n200000_k64", 32, 2, False)])
+def test_rule2_and_fixed_support(d2, dtype, name, m, rule, fixed):
+    """The R2 weight rule (Eq. (badmmw2): w proportional to the squared mean
+    of sqrt(w~^(k))) and the fixed-support barycenter (no Eq. (updatex)
+    step: the oracle runs with a support-update period beyond T) on the
+    on-the-fly (d = 3) and cached-cost (d = 16, 64) paths: objective trace,
+    centroids and every plan entry against the oracle."""
+    print(f"[rule={rule} fixed={fixed} {name} {dtype}]", flush=True)
+    N = 3000
+    wl = make_workload(name, N=N)
+    K = 3
+    mem = pick_init_members(wl["offsets"], K, m, 19)
+    Xc, Wc = oracle.init_centroids(wl, mem, m)
+    lab, _, _ = oracle.assign(wl, Xc, Wc, T=30)
+    T = 40
+    Xo, Wo, tr, rhos, plans = oracle_barycenters(
+        wl, lab, Xc, Wc, T=T, tau=(10 ** 9 if fixed else 10), rule=rule)
+    tol = 1e-10 if dtype == "f64" else 1e-5
+    with _ctx(d2, wl, dtype) as ctx:
+        ctx.centroids_set(Xc, Wc)
+        ctx.labels_set(lab)
+        ctx.barycenter(iters=T, tau=10, rule=rule, fixed_support=fixed,
+                       init=d2.D2_INIT_PRODUCT)
+        g_tr, _ = ctx.objective(T)
+        Xg, Wg = ctx.centroids_get()
+        for c in range(K):
+            if tr[c] is not None:
+                assert _rel(g_tr[:, c], tr[c]) < tol, (c, _rel(g_tr[:, c],
+                                                           tr[c]))
+        assert np.abs(Wg - Wo).max() < tol
+        if fixed:
+            assert np.array_equal(Xg, Xc)
+        else:
+            assert np.abs(Xg - Xo).max() < tol
+        check_plans(ctx, wl, plans, range(0, N, 3), rhos, lab, dtype,
+                    tag=f"rule={rule} fixed={fixed} {name}")
 
 
 def test_edge_shapes(d2):
@@ -123,8 +196,8 @@ def test_edge_shapes(d2):
         Xc = rng.random((2, m, d))
         Wc = rng.dirichlet(np.ones(m), size=2)
         lab = (np.arange(len(sizes)) % 2).astype(np.int32)
-        Xo, Wo, tr, _, plans = oracle_barycenters(wl, lab, Xc, Wc, T=25,
-                                                  tau=5)
+        Xo, Wo, tr, rhos, plans = oracle_barycenters(wl, lab, Xc, Wc, T=25,
+                                                     tau=5)
         with _ctx(d2, wl, "f32") as ctx:
             ctx.centroids_set(Xc, Wc)
             ctx.labels_set(lab)
@@ -135,8 +208,8 @@ def test_edge_shapes(d2):
                 assert _rel(g_tr[:, c], tr[c]) < 1e-5
             assert np.abs(Wg - Wo).max() < 1e-5
             assert np.abs(Xg - Xo).max() < 1e-5
-            me = marginal_errors(ctx, wl, plans, [0, 1, 2, 3, 4, 100])
-            assert me < 1e-6
+            check_plans(ctx, wl, plans, range(len(sizes)), rhos, lab,
+                        "f32", tag=f"edge d={d} m={m}")
 
 
 @pytest.mark.parametrize("name,m", [("topic_d64_n200000_k64", 32), ("gmm_d16_n2000000_k256", 16)])
@@ -150,7 +223,8 @@ def test_large_d_cached_cost_path(d2, name, m):
     mem = pick_init_members(wl["offsets"], 3, m, 4)
     Xc, Wc = oracle.init_centroids(wl, mem, m)
     lab, _, _ = oracle.assign(wl, Xc, Wc, T=30)
-    Xo, Wo, tr, _, plans = oracle_barycenters(wl, lab, Xc, Wc, T=30, tau=10)
+    Xo, Wo, tr, rhos, plans = oracle_barycenters(wl, lab, Xc, Wc, T=30,
+                                                 tau=10)
     with _ctx(d2, wl, "f32") as ctx:
         ctx.centroids_set(Xc, Wc)
         ctx.labels_set(lab)
@@ -162,8 +236,8 @@ def test_large_d_cached_cost_path(d2, name, m):
                 assert _rel(g_tr[:, c], tr[c]) < 1e-5
         assert np.abs(Wg - Wo).max() < 1e-5
         assert np.abs(Xg - Xo).max() < 1e-5
-        me = marginal_errors(ctx, wl, plans, range(0, 1500, 50))
-        assert me < 1e-6
+        check_plans(ctx, wl, plans, range(0, 1500, 3), rhos, lab, "f32",
+                    tag=name)
 
 
 def test_warm_start_and_support_update(d2):
@@ -179,8 +253,9 @@ def test_warm_start_and_support_update(d2):
     lab2, _, _ = oracle.assign(wl, X1, W1, T=40)
     warm = (lab2 == lab1)
     assert 0 < warm.sum() < len(warm) or warm.all()
-    X2, W2, tr2, _, plans = oracle_barycenters(wl, lab2, X1, W1, plans=plans,
-                                               warm=warm, T=30)
+    X2, W2, tr2, rhos2, plans = oracle_barycenters(wl, lab2, X1, W1,
+                                                   plans=plans, warm=warm,
+                                                   T=30)
     with _ctx(d2, wl, "f64") as ctx:
         ctx.centroids_set(Xc, Wc)
         ctx.labels_set(lab1)
@@ -192,6 +267,10 @@ def test_warm_start_and_support_update(d2):
         g_tr, _ = ctx.objective(30)
         for c in range(3):
             assert _rel(g_tr[:, c], tr2[c]) < 1e-9
+        # the warm-started plans entry by entry (both sides started the
+        # unchanged-label members from their own cached Pi2)
+        check_plans(ctx, wl, plans, range(0, 3000, 3), rhos2, lab2, "f64",
+                    tag="warm")
         ctx.support_update()
         Xs, _ = ctx.centroids_get()
     # oracle support update from its final Pi2 equals the barycenter's own
@@ -475,7 +554,8 @@ def test_slot_buckets_match_oracle(d2):
     mem = pick_init_members(wl["offsets"], 3, 32, 4)
     Xc, Wc = oracle.init_centroids(wl, mem, 32)
     lab, _, _ = oracle.assign(wl, Xc, Wc, T=30)
-    Xo, Wo, tr, _, plans = oracle_barycenters(wl, lab, Xc, Wc, T=30, tau=10)
+    Xo, Wo, tr, rhos, plans = oracle_barycenters(wl, lab, Xc, Wc, T=30,
+                                                 tau=10)
     res = {}
     with _ctx(d2, wl, "f32") as ctx:
         for pct in (0, 10, 100):
@@ -490,8 +570,8 @@ def test_slot_buckets_match_oracle(d2):
                     assert _rel(g_tr[:, c], tr[c]) < 1e-5, (pct, c)
             assert np.abs(Wg - Wo).max() < 1e-5, pct
             assert np.abs(Xg - Xo).max() < 1e-5, pct
-            me = marginal_errors(ctx, wl, plans, range(0, 1500, 50))
-            assert me < 1e-6, pct
+            check_plans(ctx, wl, plans, range(0, 1500, 7), rhos, lab, "f32",
+                        tag=f"buckets {pct}")
             res[pct] = (st["launches"], Xg)
     # more buckets, more launches per iteration
     assert res[0][0] > res[100][0]
@@ -509,7 +589,8 @@ def test_matrix_core_paths_ragged(d2, d, m, mk_hi):
     mem = pick_init_members(wl["offsets"], 3, m, 5)
     Xc, Wc = oracle.init_centroids(wl, mem, m)
     lab, _, _ = oracle.assign(wl, Xc, Wc, T=30)
-    Xo, Wo, tr, _, plans = oracle_barycenters(wl, lab, Xc, Wc, T=30, tau=10)
+    Xo, Wo, tr, rhos, plans = oracle_barycenters(wl, lab, Xc, Wc, T=30,
+                                                 tau=10)
     with _ctx(d2, wl, "f32") as ctx:
         ctx.centroids_set(Xc, Wc)
         ctx.labels_set(lab)
@@ -521,8 +602,8 @@ def test_matrix_core_paths_ragged(d2, d, m, mk_hi):
                 assert _rel(g_tr[:, c], tr[c]) < 1e-5, c
         assert np.abs(Wg - Wo).max() < 1e-5
         assert np.abs(Xg - Xo).max() < 1e-5
-        me = marginal_errors(ctx, wl, plans, range(0, 900, 30))
-        assert me < 1e-6
+        check_plans(ctx, wl, plans, range(0, 900, 2), rhos, lab, "f32",
+                    tag=f"mfma d={d} m={m}")
 
 
 @pytest.mark.parametrize("d,m,mk_hi", [(5, 16, 30), (37, 20, 40),
