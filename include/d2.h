@@ -49,8 +49,11 @@ typedef enum { D2_F32 = 0, D2_F64 = 1 } d2_dtype;
 
 typedef enum {
   D2_INIT_PRODUCT = 0, /* Pi2^0 = w_i w^(k)_j for every member (Sec. 5)     */
-  D2_INIT_CACHED = 1   /* cached Pi2 where the label did not change, else
+  D2_INIT_CACHED = 1,  /* cached Pi2 where the label did not change, else
                           the product (Sec. 5 warm start)                   */
+  D2_INIT_LEARNED = 2  /* starting centroid proposed by the network attached
+                          with d2_set_warm_start (gated against the current
+                          centroid), Pi2^0 = product; not in the paper      */
 } d2_init;
 
 /* Parameters of one B-ADMM centroid update (Sec. 3.2, Algorithm "Centroid
@@ -111,6 +114,21 @@ d2_status d2_load_instances(d2_ctx* ctx, int64_t N, int32_t d,
                             const int64_t* offsets, const double* X,
                             const double* W);
 
+/* Borrow N ragged instances that already sit in device memory (for
+ * example PyTorch tensors), without copying.  offsets (host, N+1) as in
+ * d2_load_instances.  dX is n x xs in the context's dtype (float for D2_F32,
+ * double for D2_F64), xs = d rounded up to a multiple of 4, row-major, with
+ * the padding columns t >= d equal to 0; dW is n weights in the same dtype.
+ * Both must stay valid and unchanged until the context is destroyed or
+ * loads other instances; the library never writes or frees them.  A device
+ * check runs first (finite coordinates, zero padding, finite weights >= 0
+ * summing to 1 within 1e-6 per instance, in double); on failure D2_EINVAL
+ * names the first offending instance and the context is unchanged.  The
+ * weights are used as given (no renormalisation). */
+d2_status d2_load_instances_device(d2_ctx* ctx, int64_t N, int32_t d,
+                                   const int64_t* offsets, const void* dX,
+                                   const void* dW);
+
 /* Set the K centroids: Xc is K x m x d, Wc is K x m (rows in the simplex,
  * |sum - 1| <= 1e-6, renormalised).  Requires loaded instances.  With K and
  * m unchanged the plan cache of the last d2_barycenter is kept, so that a
@@ -141,6 +159,19 @@ d2_status d2_labels_get(d2_ctx* ctx, int32_t* labels);
  * n_changed may be NULL. */
 d2_status d2_assign(d2_ctx* ctx, const d2_ot_params* p, int32_t* labels_out,
                     double* dist_out, int64_t* n_changed);
+
+/* Cross-round bounds of the pruned assignment (on = 1, the default).  The
+ * pruning's lower bound LB(k, c) = sum_j w^(k)_j min_i C_ij depends on the
+ * centroid only through its support points, so each pruned d2_assign
+ * stores a lower bound on sqrt(LB) for every (instance, centroid) pair
+ * (N x K floats on the device) and the next one lowers it by the largest
+ * distance any support point of the centroid moved in between (the
+ * triangle inequality, as in the paper's Sec. 5 use of Elkan's method):
+ * pairs whose decayed bound already clears the best distance skip their
+ * cost block.  Labels and minimal distances stay those of the exhaustive
+ * search.  on = 0 frees the bounds; if they cannot be allocated the
+ * assignment prunes within the round only. */
+d2_status d2_set_assign_bounds(d2_ctx* ctx, int32_t on);
 
 /* Pair counts of the last d2_assign: pairs run through the transport
  * iterations, pairs whose m x m_k cost block was formed (those passing the
@@ -256,6 +287,23 @@ d2_status d2_autotune(d2_ctx* ctx, const d2_badmm_params* p,
                       int32_t* chunk_out, int32_t* waves_out,
                       int32_t* bucket_out, double* ms_best);
 
+/* Round-boundary checkpoint of a clustering run (Sec. 5 keeps each
+ * member's Pi2 across rounds for the warm start; this saves exactly what
+ * the next round reads): the centroids, the labels, the cache labels and
+ * the cached Pi2 plans, and the launch schedule (results depend on it
+ * through summation order), with a fingerprint of the loaded instances and
+ * a checksum.  Written to path + ".tmp" and renamed, so a crash never
+ * leaves a half-written checkpoint under `path`.  The assignment's
+ * cross-round bounds are not saved (they only skip work).  D2_ESTATE
+ * without instances and centroids. */
+d2_status d2_checkpoint_save(d2_ctx* ctx, const char* path);
+/* Restore a checkpoint into a context holding the same instances (same N,
+ * n, d, dtype and fingerprint).  The file is read and checked in full
+ * before anything changes: a missing, truncated, corrupt or foreign file
+ * gives D2_EINVAL and leaves the context as it was.  Continuing the run
+ * afterwards gives bitwise the results of the uninterrupted run. */
+d2_status d2_checkpoint_load(d2_ctx* ctx, const char* path);
+
 /* Achievable-bandwidth probe (not part of the paper: the reference point
  * beside the published HBM peak for the plan-update roofline).  Copies a
  * buffer of `bytes` (>= 1 MiB; rounded down to 16 bytes) to a second one on
@@ -345,6 +393,20 @@ d2_status d2_ws_grad(d2_ws* ws, d2_ctx* ctx, const int32_t* clusters,
  * gradient; loss (may be NULL) gets the batch loss before the step. */
 d2_status d2_ws_train_step(d2_ws* ws, d2_ctx* ctx, const int32_t* clusters,
                            int32_t nb, const d2_ws_opt* opt, double* loss);
+
+/* Save / load the network: parameters, Adam moments and step count (so
+ * that training resumes exactly), with its shape (m, d, hidden) and a
+ * checksum.  Load requires a handle of the same shape; on any error
+ * (missing, truncated, foreign or corrupt file) D2_EINVAL and the handle is
+ * unchanged.  Save writes path + ".tmp" and renames it. */
+d2_status d2_ws_save(d2_ws* ws, const char* path);
+d2_status d2_ws_load(d2_ws* ws, const char* path);
+
+/* Attach a network for D2_INIT_LEARNED calls of d2_barycenter (NULL
+ * detaches).  gate != 0 keeps the current centroid of a cluster unless the
+ * proposal passes d2_ws_propose's gate.  The caller keeps the handle alive
+ * while it is attached. */
+d2_status d2_set_warm_start(d2_ctx* ctx, d2_ws* ws, int32_t gate);
 
 /* Propose a centroid for every non-empty cluster of the context's current
  * labels.  The product-coupling bound sum_k sum_ij w_i w_j^(k) C_ij of the

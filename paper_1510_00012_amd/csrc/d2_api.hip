@@ -30,8 +30,10 @@ int pad_rows(int m) { return 1 << std::max(3, ilog2(m)); }
 
 // kernel tables, filled by the per-type translation units
 void d2k_fill_f32(d2k::KernTable<float>* t);
+void d2k_fill_f32w(d2k::KernTable<float>* t);
 void d2k_fill_f32p(d2k::KernTable<float>* t);
 void d2k_fill_f64(d2k::KernTable<double>* t);
+void d2k_fill_f64w(d2k::KernTable<double>* t);
 void d2k_fill_f64p(d2k::KernTable<double>* t);
 void d2k_fill_fin(d2k::FinFn* f);
 
@@ -42,6 +44,7 @@ template <> const d2k::KernTable<float>& kern<float>() {
   static const d2k::KernTable<float> t = [] {
     d2k::KernTable<float> x;
     d2k_fill_f32(&x);
+    d2k_fill_f32w(&x);
     d2k_fill_f32p(&x);
     return x;
   }();
@@ -51,6 +54,7 @@ template <> const d2k::KernTable<double>& kern<double>() {
   static const d2k::KernTable<double> t = [] {
     d2k::KernTable<double> x;
     d2k_fill_f64(&x);
+    d2k_fill_f64w(&x);
     d2k_fill_f64p(&x);
     return x;
   }();
@@ -69,6 +73,12 @@ const d2k::FinFn* fin_table() {
 }  // namespace
 
 namespace {
+
+bool finite_all(const double* p, size_t n) {
+  for (size_t q = 0; q < n; ++q)
+    if (!std::isfinite(p[q])) return false;
+  return true;
+}
 
 template <typename P> void dfree(P*& p) {
   if (p) (void)hipFree((void*)p);
@@ -124,21 +134,36 @@ void free_lists(d2_ctx* c) {
   drop_graph(c);
 }
 
+void free_bounds(d2_ctx* c) {
+  dfree(c->d_lbs);
+  dfree(c->d_xref);
+  dfree(c->d_dlt);
+  c->lbs_valid = false;
+}
+
 void free_centroids(d2_ctx* c) {
   drop_graph(c);
+  free_bounds(c);
   dfree(c->d_cmu);
   dfree(c->d_crad);
   dfree(c->d_xct);
   dfree(c->d_xc);
   dfree(c->d_wc);
+  dfree(c->d_xsave);
+  dfree(c->d_wsave);
   dfree(c->d_rho);
   dfree(c->d_cnt);
   c->K = c->m = c->MP = 0;
 }
 
 void free_instances(d2_ctx* c) {
+  free_bounds(c);
   dfree(c->d_off);
   dfree(c->d_pofs);
+  if (c->borrowed) {
+    c->d_X = c->d_W = nullptr;
+    c->borrowed = false;
+  }
   dfree(c->d_X);
   dfree(c->d_W);
   dfree(c->d_labels);
@@ -229,6 +254,11 @@ d2_status ensure_centroid_bufs(d2_ctx* c, int K, int m) {
   if ((s = dalloc(c, (void**)&c->d_xc, sizeof(double) * K * c->MP * c->d)))
     return s;
   if ((s = dalloc(c, (void**)&c->d_wc, sizeof(double) * K * c->MP))) return s;
+  if ((s = dalloc(c, (void**)&c->d_xsave,
+                  sizeof(double) * K * c->MP * c->d)))
+    return s;
+  if ((s = dalloc(c, (void**)&c->d_wsave, sizeof(double) * K * c->MP)))
+    return s;
   if ((s = dalloc(c, (void**)&c->d_rho, sizeof(double) * K))) return s;
   if ((s = dalloc(c, (void**)&c->d_cnt, sizeof(int) * K))) return s;
   HIPCHK(c, hipMemset(c->d_cnt, 0, sizeof(int) * K));
@@ -819,6 +849,12 @@ d2_status run_barycenter(d2_ctx* c, const d2_badmm_params* p,
                            c->stream));
   HIPCHK(c, hipMemsetAsync(c->d_rtrace, 0, sizeof(double) * T_ * K,
                            c->stream));
+  const size_t xbytes = sizeof(double) * (size_t)K * MP * c->d;
+  const size_t wbytes = sizeof(double) * (size_t)K * MP;
+  HIPCHK(c, hipMemcpyAsync(c->d_xsave, c->d_xc, xbytes,
+                           hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->d_wsave, c->d_wc, wbytes,
+                           hipMemcpyDeviceToDevice, c->stream));
   int nl = 0;
   bool graphed = false;
   d2_status s;
@@ -860,21 +896,26 @@ d2_status run_barycenter(d2_ctx* c, const d2_badmm_params* p,
   prof_collect(c);
   float ms = 0.f;
   HIPCHK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
-  c->trace_rows = T_;
-  c->h_cache_labels = c->h_labels;
-  c->have_cache = true;
-  // non-finite guard on the new centroids
+  // non-finite guard on the new centroids: on failure the centroids of the
+  // call's start are restored and the (non-finite) plans are not a cache
   std::vector<double> hx((size_t)K * MP * c->d), hw((size_t)K * MP);
   HIPCHK(c, hipMemcpy(hx.data(), c->d_xc, hx.size() * 8,
                       hipMemcpyDeviceToHost));
   HIPCHK(c, hipMemcpy(hw.data(), c->d_wc, hw.size() * 8,
                       hipMemcpyDeviceToHost));
-  for (double v : hx)
-    if (!std::isfinite(v))
-      return c->fail(D2_ENUMERIC, "non-finite centroid support");
-  for (double v : hw)
-    if (!std::isfinite(v))
-      return c->fail(D2_ENUMERIC, "non-finite centroid weights");
+  if (!finite_all(hx.data(), hx.size()) || !finite_all(hw.data(), hw.size())) {
+    HIPCHK(c, hipMemcpy(c->d_xc, c->d_xsave, xbytes,
+                        hipMemcpyDeviceToDevice));
+    HIPCHK(c, hipMemcpy(c->d_wc, c->d_wsave, wbytes,
+                        hipMemcpyDeviceToDevice));
+    c->have_cache = false;
+    c->trace_rows = 0;
+    return c->fail(D2_ENUMERIC, "non-finite centroid support or weights "
+                                "(centroids restored)");
+  }
+  c->trace_rows = T_;
+  c->h_cache_labels = c->h_labels;
+  c->have_cache = true;
   if (st) {
     st->iters = T_;
     int ne = 0;
@@ -903,7 +944,8 @@ int slots_for(const d2_ctx* c) {
 template <typename T>
 __global__ void __launch_bounds__(64)
     k_cstats(const double* xc, const double* wc, int m, int MP, int d,
-             int xs, int K, T* cmu, T* crad, T* xct) {
+             int xs, int K, T* cmu, T* crad, T* xct, const double* xref,
+             float* dlt) {
   extern __shared__ double s_mu[];  // d
   const int q = blockIdx.x, l = threadIdx.x;
   const double* xq = xc + (size_t)q * MP * d;
@@ -933,6 +975,21 @@ __global__ void __launch_bounds__(64)
   }
   for (int o = 32; o > 0; o >>= 1) r = fmax(r, __shfl_xor(r, o));
   if (l == 0) crad[q] = (T)(r * (1.0 + 1e-6) + 1e-30);
+  if (xref) {
+    // drift: the largest distance a support point moved since xref
+    const double* xo = xref + (size_t)q * MP * d;
+    double g = 0.0;
+    for (int i = l; i < m; i += 64) {
+      double s = 0.0;
+      for (int t = 0; t < d; ++t) {
+        const double df = xq[(size_t)i * d + t] - xo[(size_t)i * d + t];
+        s += df * df;
+      }
+      g = fmax(g, sqrt(s));
+    }
+    for (int o = 32; o > 0; o >>= 1) g = fmax(g, __shfl_xor(g, o));
+    if (l == 0) dlt[q] = (float)(g * (1.0 + 1e-6) + 1e-30);
+  }
 }
 
 template <typename T>
@@ -947,9 +1004,31 @@ d2_status centroid_stats(d2_ctx* c) {
   }
   hipLaunchKernelGGL(k_cstats<T>, dim3(K), dim3(64), sizeof(double) * d,
                      c->stream, c->d_xc, c->d_wc, c->m, MP, d, c->xs, K,
-                     (T*)c->d_cmu, (T*)c->d_crad, (T*)c->d_xct);
+                     (T*)c->d_cmu, (T*)c->d_crad, (T*)c->d_xct,
+                     c->lbs_valid ? (const double*)c->d_xref : nullptr,
+                     c->d_dlt);
   HIPCHK(c, hipGetLastError());
   return D2_OK;
+}
+
+// Buffers of the cross-round assignment bounds (N x K floats); without
+// them (switched off, or no memory) the assignment prunes within the round
+// only.
+bool ensure_bounds(d2_ctx* c) {
+  if (!c->use_lbs) return false;
+  if (c->d_lbs) return true;
+  const size_t nb = sizeof(float) * (size_t)c->N * c->K;
+  if (hipMalloc((void**)&c->d_lbs, nb) != hipSuccess ||
+      hipMalloc((void**)&c->d_xref,
+                sizeof(double) * (size_t)c->K * c->MP * c->d) != hipSuccess ||
+      hipMalloc((void**)&c->d_dlt, sizeof(float) * c->K) != hipSuccess) {
+    (void)hipGetLastError();
+    free_bounds(c);
+    c->use_lbs = false;
+    return false;
+  }
+  c->lbs_valid = false;
+  return true;
 }
 
 template <typename T>
@@ -968,10 +1047,14 @@ d2_status run_assign(d2_ctx* c, const d2_ot_params* p, float* ms_out) {
   a.counts = c->d_pairs;
   a.prune = p->prune ? 1 : 0;
   a.prev_valid = c->have_labels ? 1 : 0;
+  const bool bounds = a.prune && ensure_bounds(c);
   {
     d2_status s = centroid_stats<T>(c);
     if (s) return s;
   }
+  a.lbs = bounds ? c->d_lbs : nullptr;
+  a.dlt = c->d_dlt;
+  a.lbs_in = bounds && c->lbs_valid ? 1 : 0;
   a.cmu = (const T*)c->d_cmu;
   a.crad = (const T*)c->d_crad;
   a.xct = (const T*)c->d_xct;
@@ -1055,6 +1138,13 @@ d2_status run_assign(d2_ctx* c, const d2_ot_params* p, float* ms_out) {
     if (s) return s;
   }
   prof_end(c, kKAssign, pe);
+  if (bounds) {
+    // the stored bounds now refer to the current centroid supports
+    HIPCHK(c, hipMemcpyAsync(c->d_xref, c->d_xc,
+                             sizeof(double) * (size_t)c->K * c->MP * c->d,
+                             hipMemcpyDeviceToDevice, c->stream));
+    c->lbs_valid = true;
+  }
   HIPCHK(c, hipEventRecord(c->ev1, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   prof_collect(c);
@@ -1083,11 +1173,6 @@ __global__ void __launch_bounds__(256)
   for (; i < n4; i += stride) dst[i] = src[i];
 }
 
-bool finite_all(const double* p, size_t n) {
-  for (size_t q = 0; q < n; ++q)
-    if (!std::isfinite(p[q])) return false;
-  return true;
-}
 
 }  // namespace
 
@@ -1171,14 +1256,18 @@ const char* d2_last_error(const d2_ctx* c) {
   return c ? c->err.c_str() : "null context";
 }
 
-d2_status d2_load_instances(d2_ctx* c, int64_t N, int32_t d,
-                            const int64_t* offsets, const double* X,
-                            const double* W) {
-  if (!c) return D2_EINVAL;
-  if (N < 1 || d < 1 || !offsets || !X || !W)
+}  // extern "C"
+
+namespace {
+
+// Validate the instance offsets (Sec. 2 layout): offsets[0] = 0, 1 <= m_k
+// <= 64, n < 2^31.  Returns the largest m_k through mkmax.
+d2_status check_offsets(d2_ctx* c, int64_t N, int32_t d,
+                        const int64_t* offsets, int& mkmax) {
+  if (N < 1 || d < 1 || !offsets)
     return c->fail(D2_EINVAL, "need N >= 1, d >= 1 and non-null arrays");
   if (offsets[0] != 0) return c->fail(D2_EINVAL, "offsets[0] must be 0");
-  int mkmax = 0;
+  mkmax = 0;
   for (int64_t k = 0; k < N; ++k) {
     int64_t mk = offsets[k + 1] - offsets[k];
     if (mk < 1 || mk > 64)
@@ -1186,11 +1275,141 @@ d2_status d2_load_instances(d2_ctx* c, int64_t N, int32_t d,
                                     ": support size must be in [1, 64]");
     mkmax = std::max<int>(mkmax, (int)mk);
   }
+  if (offsets[N] > INT32_MAX)
+    return c->fail(D2_EINVAL, "n exceeds 2^31 - 1");
+  return D2_OK;
+}
+
+// Drop the previous instances, centroids and plans and take over the new
+// offsets; allocates the per-instance device arrays except X and W.
+d2_status adopt_offsets(d2_ctx* c, int64_t N, int32_t d,
+                        const int64_t* offsets, int mkmax) {
+  free_instances(c);
+  free_centroids(c);
+  c->N = N;
+  c->n = offsets[N];
+  c->d = d;
+  c->xs = (d + 3) / 4 * 4;  // zero-padded stride, a multiple of 4
+  c->mk_max = mkmax;
+  c->h_off.assign(offsets, offsets + N + 1);
+  c->inst_hash = 0;
+  d2_status s;
+  if ((s = dalloc(c, (void**)&c->d_off, sizeof(int64_t) * (N + 1)))) return s;
+  if ((s = dalloc(c, (void**)&c->d_labels, sizeof(int32_t) * N))) return s;
+  if ((s = dalloc(c, (void**)&c->d_best, sizeof(double) * N))) return s;
+  if ((s = dalloc(c, (void**)&c->d_pairs, 2 * sizeof(int32_t) * N)))
+    return s;
+  HIPCHK(c, hipMemcpy(c->d_off, offsets, sizeof(int64_t) * (N + 1),
+                      hipMemcpyHostToDevice));
+  c->h_labels.assign(N, 0);
+  ++c->label_gen;
+  return D2_OK;
+}
+
+// Validation of borrowed device instances, one thread per instance: finite
+// coordinates, zero padding columns, finite non-negative weights summing
+// to 1 within 1e-6 (in double).  bad gets min over failing instances of
+// (k << 2 | reason): reason 1 coordinates, 2 weights, 3 weight sum.
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_check_instances(const int64_t* off, const T* X, const T* W, int64_t N,
+                      int d, int xs, unsigned long long* bad) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= N) return;
+  int reason = 0;
+  double s = 0.0;
+  for (int64_t j = off[k]; j < off[k + 1] && !reason; ++j) {
+    for (int t = 0; t < xs; ++t) {
+      const T v = X[j * xs + t];
+      if (t < d ? !isfinite((double)v) : v != T(0)) reason = 1;
+    }
+    const T w = W[j];
+    if (!(w >= T(0)) || !isfinite((double)w)) reason = 2;
+    s += (double)w;
+  }
+  if (!reason && !(fabs(s - 1.0) <= 1e-6)) reason = 3;
+  if (reason)
+    atomicMin(bad, ((unsigned long long)k << 2) | (unsigned long long)reason);
+}
+
+// Order-independent 64-bit fingerprint of 32-bit words: the wrapping sum of
+// a mix of (index, word) for every word, so that any change of a word or of
+// its position changes it (with high probability) and the result does not
+// depend on the summation order.
+__device__ __forceinline__ unsigned long long mix64(unsigned long long z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+__global__ void __launch_bounds__(256)
+    k_fingerprint(const uint32_t* w, int64_t nw, unsigned long long salt,
+                  unsigned long long* out) {
+  unsigned long long acc = 0;
+  const int64_t st = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < nw;
+       q += st)
+    acc += mix64(salt ^ mix64((unsigned long long)q * 0x100000001B3ull ^
+                              (unsigned long long)w[q]));
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+  if ((threadIdx.x & 63) == 0) atomicAdd(out, acc);
+}
+
+// Fingerprint of the loaded instances (offsets, and the device copies of
+// X and W in the device dtype), computed on first use.
+d2_status instance_hash(d2_ctx* c, uint64_t* out) {
+  if (c->inst_hash) {
+    *out = c->inst_hash;
+    return D2_OK;
+  }
+  unsigned long long* d = nullptr;
+  d2_status s = dalloc(c, (void**)&d, sizeof(unsigned long long) * 3);
+  if (s) return s;
+  const void* src[3] = {c->d_off, c->d_X, c->d_W};
+  const int64_t words[3] = {2 * (c->N + 1),
+                            (int64_t)(c->esz() / 4) * c->n * c->xs,
+                            (int64_t)(c->esz() / 4) * c->n};
+  d2_status st = D2_OK;
+  if (hipMemsetAsync(d, 0, sizeof(unsigned long long) * 3, c->stream) !=
+      hipSuccess)
+    st = c->fail(D2_EDEVICE, "hipMemsetAsync");
+  for (int q = 0; q < 3 && !st; ++q) {
+    hipLaunchKernelGGL(k_fingerprint, dim3(1024), dim3(256), 0, c->stream,
+                       (const uint32_t*)src[q], words[q],
+                       (unsigned long long)(q + 1), d + q);
+    if (hipGetLastError() != hipSuccess)
+      st = c->fail(D2_EDEVICE, "k_fingerprint launch");
+  }
+  unsigned long long h[3] = {0, 0, 0};
+  if (!st && hipMemcpyAsync(h, d, sizeof(h), hipMemcpyDeviceToHost,
+                            c->stream) != hipSuccess)
+    st = c->fail(D2_EDEVICE, "hipMemcpyAsync");
+  if (!st && hipStreamSynchronize(c->stream) != hipSuccess)
+    st = c->fail(D2_EDEVICE, "hipStreamSynchronize");
+  dfree(d);
+  if (st) return st;
+  c->inst_hash = (h[0] * 31 + h[1]) * 31 + h[2] + (uint64_t)c->dt;
+  if (!c->inst_hash) c->inst_hash = 1;
+  *out = c->inst_hash;
+  return D2_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+d2_status d2_load_instances(d2_ctx* c, int64_t N, int32_t d,
+                            const int64_t* offsets, const double* X,
+                            const double* W) {
+  if (!c) return D2_EINVAL;
+  int mkmax = 0;
+  d2_status s = check_offsets(c, N, d, offsets, mkmax);
+  if (s) return s;
+  if (!X || !W) return c->fail(D2_EINVAL, "null X or W");
   const int64_t n = offsets[N];
-  if (n > INT32_MAX) return c->fail(D2_EINVAL, "n exceeds 2^31 - 1");
   std::vector<double> Wn(W, W + n);
   for (int64_t k = 0; k < N; ++k) {
-    double s = 0.0;
+    double sum = 0.0;
     for (int64_t j = offsets[k]; j < offsets[k + 1]; ++j) {
       if (!(W[j] >= 0.0) || !std::isfinite(W[j]))
         return c->fail(D2_EINVAL, "instance " + std::to_string(k) +
@@ -1199,32 +1418,17 @@ d2_status d2_load_instances(d2_ctx* c, int64_t N, int32_t d,
         if (!std::isfinite(X[j * d + t]))
           return c->fail(D2_EINVAL, "instance " + std::to_string(k) +
                                         ": non-finite support point");
-      s += W[j];
+      sum += W[j];
     }
-    if (!(std::fabs(s - 1.0) <= 1e-6))
+    if (!(std::fabs(sum - 1.0) <= 1e-6))
       return c->fail(D2_EINVAL, "instance " + std::to_string(k) +
                                     ": weights do not sum to 1");
-    for (int64_t j = offsets[k]; j < offsets[k + 1]; ++j) Wn[j] = W[j] / s;
+    for (int64_t j = offsets[k]; j < offsets[k + 1]; ++j) Wn[j] = W[j] / sum;
   }
   HIPCHK(c, hipSetDevice(c->device));
-  free_instances(c);
-  free_centroids(c);
-  c->N = N;
-  c->n = n;
-  c->d = d;
-  c->xs = (d + 3) / 4 * 4;  // zero-padded stride, a multiple of 4
-  c->mk_max = mkmax;
-  c->h_off.assign(offsets, offsets + N + 1);
-  d2_status s;
-  if ((s = dalloc(c, (void**)&c->d_off, sizeof(int64_t) * (N + 1)))) return s;
+  if ((s = adopt_offsets(c, N, d, offsets, mkmax))) return s;
   if ((s = dalloc(c, &c->d_X, c->esz() * n * c->xs))) return s;
   if ((s = dalloc(c, &c->d_W, c->esz() * n))) return s;
-  if ((s = dalloc(c, (void**)&c->d_labels, sizeof(int32_t) * N))) return s;
-  if ((s = dalloc(c, (void**)&c->d_best, sizeof(double) * N))) return s;
-  if ((s = dalloc(c, (void**)&c->d_pairs, 2 * sizeof(int32_t) * N)))
-    return s;
-  HIPCHK(c, hipMemcpy(c->d_off, offsets, sizeof(int64_t) * (N + 1),
-                      hipMemcpyHostToDevice));
   // supports with row stride xs (zero padding for d <= 4)
   std::vector<double> Xp((size_t)n * c->xs, 0.0);
   for (int64_t j = 0; j < n; ++j)
@@ -1236,8 +1440,63 @@ d2_status d2_load_instances(d2_ctx* c, int64_t N, int32_t d,
     if ((s = upload_conv<float>(c, c->d_X, Xp.data(), Xp.size()))) return s;
     if ((s = upload_conv<float>(c, c->d_W, Wn.data(), n))) return s;
   }
-  c->h_labels.assign(N, 0);
-  ++c->label_gen;
+  return D2_OK;
+}
+
+d2_status d2_load_instances_device(d2_ctx* c, int64_t N, int32_t d,
+                                   const int64_t* offsets, const void* dX,
+                                   const void* dW) {
+  if (!c) return D2_EINVAL;
+  int mkmax = 0;
+  d2_status s = check_offsets(c, N, d, offsets, mkmax);
+  if (s) return s;
+  if (!dX || !dW) return c->fail(D2_EINVAL, "null X or W");
+  HIPCHK(c, hipSetDevice(c->device));
+  // the device data are checked before anything of the context changes
+  const int xs = (d + 3) / 4 * 4;
+  int64_t* doff = nullptr;
+  unsigned long long* dbad = nullptr;
+  if ((s = dalloc(c, (void**)&doff, sizeof(int64_t) * (N + 1)))) return s;
+  if ((s = dalloc(c, (void**)&dbad, sizeof(unsigned long long)))) {
+    dfree(doff);
+    return s;
+  }
+  unsigned long long bad = ~0ull;
+  hipError_t e = hipMemcpy(doff, offsets, sizeof(int64_t) * (N + 1),
+                           hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(dbad, &bad, sizeof(bad), hipMemcpyHostToDevice);
+  if (e == hipSuccess) {
+    const unsigned blocks = (unsigned)((N + 255) / 256);
+    if (c->dt == D2_F64)
+      hipLaunchKernelGGL(k_check_instances<double>, dim3(blocks), dim3(256),
+                         0, c->stream, doff, (const double*)dX,
+                         (const double*)dW, N, d, xs, dbad);
+    else
+      hipLaunchKernelGGL(k_check_instances<float>, dim3(blocks), dim3(256), 0,
+                         c->stream, doff, (const float*)dX, (const float*)dW,
+                         N, d, xs, dbad);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpy(&bad, dbad, sizeof(bad), hipMemcpyDeviceToHost);
+  dfree(doff);
+  dfree(dbad);
+  if (e != hipSuccess)
+    return c->fail(D2_EDEVICE, std::string("instance check: ") +
+                                   hipGetErrorString(e));
+  if (bad != ~0ull) {
+    static const char* why[4] = {"", "non-finite coordinate or non-zero "
+                                     "padding", "weights must be finite and "
+                                     ">= 0", "weights do not sum to 1"};
+    return c->fail(D2_EINVAL, "instance " + std::to_string(bad >> 2) + ": " +
+                                  why[bad & 3]);
+  }
+  if ((s = adopt_offsets(c, N, d, offsets, mkmax))) return s;
+  c->d_X = const_cast<void*>(dX);
+  c->d_W = const_cast<void*>(dW);
+  c->borrowed = true;
   return D2_OK;
 }
 
@@ -1424,11 +1683,24 @@ d2_status d2_barycenter(d2_ctx* c, const d2_badmm_params* p,
   if (!c->have_labels) return c->fail(D2_ESTATE, "need labels");
   if (!p || p->iters < 1 || p->tau < 1 || !(p->rho0 > 0) || !(p->eps >= 0) ||
       (p->rule != 1 && p->rule != 2) || p->xplan != 0 ||
-      (p->init != D2_INIT_PRODUCT && p->init != D2_INIT_CACHED))
+      (p->init != D2_INIT_PRODUCT && p->init != D2_INIT_CACHED &&
+       p->init != D2_INIT_LEARNED))
     return c->fail(D2_EINVAL, "bad B-ADMM parameters");
+  if (p->init == D2_INIT_LEARNED && !c->ws)
+    return c->fail(D2_ESTATE, "D2_INIT_LEARNED needs d2_set_warm_start");
   HIPCHK(c, hipSetDevice(c->device));
-  d2_status s = ensure_plans(c);
-  if (s) return s;
+  d2_status s;
+  if (p->init == D2_INIT_LEARNED) {
+    // the network proposes each cluster's starting centroid from its
+    // members (gated against the current centroid); plans start from the
+    // product coupling
+    if ((s = d2_ws_propose(c->ws, c, c->ws_gate, nullptr, nullptr,
+                           nullptr))) {
+      const char* e = d2_ws_last_error(c->ws);
+      return c->fail(s, std::string("warm-start proposal: ") + (e ? e : ""));
+    }
+  }
+  if ((s = ensure_plans(c))) return s;
   if ((s = build_lists(c, p->init == D2_INIT_CACHED))) return s;
   return c->dt == D2_F64 ? run_barycenter<double>(c, p, st)
                          : run_barycenter<float>(c, p, st);
@@ -1568,6 +1840,24 @@ d2_status d2_kernel_stats(d2_ctx* c, d2_kernel_stat* out, int32_t cap,
   return D2_OK;
 }
 
+d2_status d2_set_warm_start(d2_ctx* c, d2_ws* ws, int32_t gate) {
+  if (!c) return D2_EINVAL;
+  c->ws = ws;
+  c->ws_gate = gate ? 1 : 0;
+  return D2_OK;
+}
+
+d2_status d2_set_assign_bounds(d2_ctx* c, int32_t on) {
+  if (!c) return D2_EINVAL;
+  if (!on) {
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    free_bounds(c);
+  }
+  c->use_lbs = on != 0;
+  return D2_OK;
+}
+
 d2_status d2_set_graph(d2_ctx* c, int32_t on) {
   if (!c) return D2_EINVAL;
   c->use_graph = on != 0;
@@ -1703,6 +1993,208 @@ d2_status d2_copy_probe(int device, int64_t bytes, int32_t reps,
     if (ms) *ms = best;
   }
   return st;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Checkpoint file: a fixed header, then the sections it announces, then a
+// checksum of everything before it.
+struct CkptHeader {
+  char magic[8];
+  int32_t version, dtype, d, K, m, MP;
+  int32_t chunk, waves, bucket, have_labels, have_cache;
+  int64_t N, n, plan_elems;
+  uint64_t inst_hash;
+};
+constexpr char kCkptMagic[8] = {'D', '2', 'C', 'K', 'P', 'T', 0, 1};
+
+struct Hasher {  // FNV-1a over the bytes written / read
+  uint64_t h = 1469598103934665603ull;
+  void add(const void* p, size_t n) {
+    const unsigned char* b = (const unsigned char*)p;
+    for (size_t q = 0; q < n; ++q) h = (h ^ b[q]) * 1099511628211ull;
+  }
+};
+
+bool write_all(FILE* f, Hasher& hs, const void* p, size_t n) {
+  hs.add(p, n);
+  return n == 0 || fwrite(p, 1, n, f) == n;
+}
+bool read_all(FILE* f, Hasher& hs, void* p, size_t n) {
+  if (n && fread(p, 1, n, f) != n) return false;
+  hs.add(p, n);
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+d2_status d2_checkpoint_save(d2_ctx* c, const char* path) {
+  if (!c) return D2_EINVAL;
+  if (!path) return c->fail(D2_EINVAL, "null path");
+  if (!c->N || !c->K) return c->fail(D2_ESTATE, "need instances, centroids");
+  HIPCHK(c, hipSetDevice(c->device));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  CkptHeader h;
+  std::memset(&h, 0, sizeof(h));
+  std::memcpy(h.magic, kCkptMagic, 8);
+  h.version = 1;
+  h.dtype = (int32_t)c->dt;
+  h.d = c->d;
+  h.K = c->K;
+  h.m = c->m;
+  h.MP = c->MP;
+  h.chunk = c->chunk_inst;
+  h.waves = c->waves;
+  h.bucket = c->bucket_min_pct;
+  h.have_labels = c->have_labels ? 1 : 0;
+  h.have_cache = (c->have_cache && c->d_P2) ? 1 : 0;
+  h.N = c->N;
+  h.n = c->n;
+  h.plan_elems = h.have_cache ? c->h_pofs[c->N] : 0;
+  d2_status s = instance_hash(c, &h.inst_hash);
+  if (s) return s;
+  std::vector<double> hx((size_t)c->K * c->MP * c->d), hw((size_t)c->K * c->MP);
+  HIPCHK(c, hipMemcpy(hx.data(), c->d_xc, hx.size() * 8,
+                      hipMemcpyDeviceToHost));
+  HIPCHK(c, hipMemcpy(hw.data(), c->d_wc, hw.size() * 8,
+                      hipMemcpyDeviceToHost));
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE* f = fopen(tmp.c_str(), "wb");
+  if (!f) return c->fail(D2_EINVAL, "cannot open " + tmp + " for writing");
+  Hasher hs;
+  bool ok = write_all(f, hs, &h, sizeof(h)) &&
+            write_all(f, hs, hx.data(), hx.size() * 8) &&
+            write_all(f, hs, hw.data(), hw.size() * 8);
+  if (ok && h.have_labels)
+    ok = write_all(f, hs, c->h_labels.data(), sizeof(int32_t) * c->N);
+  if (ok && h.have_cache) {
+    ok = write_all(f, hs, c->h_cache_labels.data(), sizeof(int32_t) * c->N);
+    // the cached Pi2 in 64 MB pieces
+    std::vector<unsigned char> buf((size_t)64 << 20);
+    const size_t total = (size_t)h.plan_elems * c->esz();
+    for (size_t o = 0; ok && o < total; o += buf.size()) {
+      const size_t nb = std::min(buf.size(), total - o);
+      if (hipMemcpy(buf.data(), (const unsigned char*)c->d_P2 + o, nb,
+                    hipMemcpyDeviceToHost) != hipSuccess) {
+        fclose(f);
+        std::remove(tmp.c_str());
+        return c->fail(D2_EDEVICE, "reading the plan cache");
+      }
+      ok = write_all(f, hs, buf.data(), nb);
+    }
+  }
+  const uint64_t sum = hs.h;
+  ok = ok && fwrite(&sum, 1, 8, f) == 8;
+  ok = (fclose(f) == 0) && ok;
+  if (!ok || std::rename(tmp.c_str(), path) != 0) {
+    std::remove(tmp.c_str());
+    return c->fail(D2_EINVAL, std::string("writing ") + path + " failed");
+  }
+  return D2_OK;
+}
+
+d2_status d2_checkpoint_load(d2_ctx* c, const char* path) {
+  if (!c) return D2_EINVAL;
+  if (!path) return c->fail(D2_EINVAL, "null path");
+  if (!c->N) return c->fail(D2_ESTATE, "load the same instances first");
+  HIPCHK(c, hipSetDevice(c->device));
+  FILE* f = fopen(path, "rb");
+  if (!f) return c->fail(D2_EINVAL, std::string("cannot open ") + path);
+  // read and check everything before the context changes
+  Hasher hs;
+  CkptHeader h;
+  auto bad = [&](const std::string& why) {
+    fclose(f);
+    return c->fail(D2_EINVAL, std::string(path) + ": " + why);
+  };
+  if (!read_all(f, hs, &h, sizeof(h))) return bad("truncated header");
+  if (std::memcmp(h.magic, kCkptMagic, 8) != 0 || h.version != 1)
+    return bad("not a checkpoint of this library");
+  if (h.dtype != (int32_t)c->dt) return bad("device dtype differs");
+  if (h.N != c->N || h.n != c->n || h.d != c->d)
+    return bad("instance sizes differ from the loaded instances");
+  if (h.K < 1 || h.m < 1 || h.m > 64 || h.MP != pad_rows(h.m) ||
+      h.chunk < 1 || h.chunk > 4096 ||
+      (h.waves != 1 && h.waves != 2 && h.waves != 4) || h.bucket < 0 ||
+      h.bucket > 100)
+    return bad("corrupt header");
+  uint64_t ih = 0;
+  d2_status s = instance_hash(c, &ih);
+  if (s) {
+    fclose(f);
+    return s;
+  }
+  if (ih != h.inst_hash) return bad("the loaded instances differ");
+  std::vector<double> hx((size_t)h.K * h.MP * h.d), hw((size_t)h.K * h.MP);
+  std::vector<int32_t> lab, clab;
+  if (!read_all(f, hs, hx.data(), hx.size() * 8) ||
+      !read_all(f, hs, hw.data(), hw.size() * 8))
+    return bad("truncated centroids");
+  if (!finite_all(hx.data(), hx.size()) || !finite_all(hw.data(), hw.size()))
+    return bad("non-finite centroids");
+  if (h.have_labels) {
+    lab.resize(c->N);
+    if (!read_all(f, hs, lab.data(), sizeof(int32_t) * c->N))
+      return bad("truncated labels");
+  }
+  std::vector<unsigned char> plans;
+  if (h.have_cache) {
+    clab.resize(c->N);
+    if (!read_all(f, hs, clab.data(), sizeof(int32_t) * c->N))
+      return bad("truncated cache labels");
+    int64_t pe = 0;
+    for (int64_t k = 0; k < c->N; ++k)
+      pe += ((int64_t)h.m * (c->h_off[k + 1] - c->h_off[k]) + 31) / 32 * 32;
+    if (pe != h.plan_elems) return bad("plan cache size differs");
+    plans.resize((size_t)h.plan_elems * c->esz());
+    if (!read_all(f, hs, plans.data(), plans.size()))
+      return bad("truncated plan cache");
+  }
+  for (int32_t v : lab)
+    if (v < 0 || v >= h.K) return bad("label out of range");
+  for (int32_t v : clab)
+    if (v < 0 || v >= h.K) return bad("label out of range");
+  uint64_t sum = 0;
+  const uint64_t want = hs.h;
+  if (fread(&sum, 1, 8, f) != 8 || sum != want) return bad("checksum mismatch");
+  fclose(f);
+  if ((s = check_limits(c, h.m))) return s;
+  // apply
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if ((s = ensure_centroid_bufs(c, h.K, h.m))) return s;
+  HIPCHK(c, hipMemcpy(c->d_xc, hx.data(), hx.size() * 8,
+                      hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->d_wc, hw.data(), hw.size() * 8,
+                      hipMemcpyHostToDevice));
+  c->R = slots_for(c);
+  free_bounds(c);
+  if ((s = d2_set_schedule(c, h.chunk, h.waves))) return s;
+  if ((s = d2_set_bucketing(c, h.bucket))) return s;
+  c->lists_valid = false;
+  drop_graph(c);
+  c->have_labels = h.have_labels != 0;
+  if (c->have_labels) {
+    c->h_labels = lab;
+    HIPCHK(c, hipMemcpy(c->d_labels, lab.data(), sizeof(int32_t) * c->N,
+                        hipMemcpyHostToDevice));
+  } else {
+    c->h_labels.assign(c->N, 0);
+  }
+  ++c->label_gen;
+  c->have_cache = false;
+  if (h.have_cache) {
+    if ((s = ensure_plans(c))) return s;
+    HIPCHK(c, hipMemcpy(c->d_P2, plans.data(), plans.size(),
+                        hipMemcpyHostToDevice));
+    c->h_cache_labels = clab;
+    c->have_cache = true;
+  }
+  c->trace_rows = 0;
+  return D2_OK;
 }
 
 d2_status d2_sizes(const d2_ctx* c, int64_t* N, int64_t* n, int32_t* d,

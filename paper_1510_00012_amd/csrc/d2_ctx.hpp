@@ -28,10 +28,17 @@ struct d2_ctx {
   int64_t* d_pofs = nullptr;
   void* d_X = nullptr;
   void* d_W = nullptr;
+  bool borrowed = false;  // d_X, d_W belong to the caller (device load)
+  // learned warm start used by D2_INIT_LEARNED (owned by the caller)
+  d2_ws* ws = nullptr;
+  int ws_gate = 1;
+  uint64_t inst_hash = 0;  // fingerprint of the instances (0: not yet)
   // centroids (double on device, rows padded to MP)
   int K = 0, m = 0, MP = 0, R = 0;
   double* d_xc = nullptr;
   double* d_wc = nullptr;
+  double* d_xsave = nullptr;  // centroids at the start of a barycenter call
+  double* d_wsave = nullptr;  // (restored if it fails numerically)
   double* d_rho = nullptr;
   int* d_cnt = nullptr;
   // labels
@@ -46,6 +53,12 @@ struct d2_ctx {
   void* d_crad = nullptr;  // K centroid support radii
   void* d_xct = nullptr;   // K x MP x xs centroid supports (device dtype)
   int64_t last_pairs = 0;  // pairs of the last assignment (0: none yet)
+  // cross-round assignment bounds: N x K stored lower bounds, the centroid
+  // supports they refer to, and the per-centroid drift since then
+  bool use_lbs = true, lbs_valid = false;
+  float* d_lbs = nullptr;
+  double* d_xref = nullptr;
+  float* d_dlt = nullptr;
   // assignment: instance ids grouped by slot class (one launch per class,
   // each kernel specialised for its class), built for the current pad(m)
   int32_t* d_alist = nullptr;

@@ -1,8 +1,9 @@
-// FP32 kernel instantiations and the per-cluster finalisation kernels.
+// FP32 kernel instantiations (row paddings 8 and 16) and the per-cluster
+// finalisation kernels.
 #include "d2_kinst.hpp"
 
 void d2k_fill_f32(d2k::KernTable<float>* t) {
-  d2k::fill_table<float, false>(*t);
+  d2k::fill_table<float, false, 8, 16>(*t);
 }
 
 void d2k_fill_fin(d2k::FinFn* f) {

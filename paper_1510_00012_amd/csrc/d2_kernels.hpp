@@ -1265,6 +1265,14 @@ template <typename T> struct AssignArgs {
   const T* crad;        // K  radius of the support around that mean
   const T* xct;         // K x MP x xs centroid supports in the device dtype
   const int32_t* list;  // instance ids of this launch (one slot class)
+  // Cross-round bounds (pruning only): lbs[k * K + c] holds a lower bound
+  // on sqrt(LB(k, c)), LB the column-relaxed bound below, valid for the
+  // centroid supports of the last pruned assignment; dlt[c] bounds how far
+  // any support point of centroid c moved since then.  lbs_in: the stored
+  // values may be read (else they are written only).  lbs null: no bounds.
+  float* lbs;
+  const float* dlt;
+  int lbs_in;
   int64_t N;            // instances in this launch
   double rho0, eps;
   int m, d, xs, K, iters, prune, prev_valid;
@@ -1461,10 +1469,10 @@ __device__ __forceinline__ T cheap_bound(const AssignArgs<T>& a, int c,
 
 template <typename T, int MP, int NS>
 __device__ __forceinline__ void assign_tile(const AssignArgs<T>& a,
-                                            const Tile<T, MP>& tl, T* sw,
-                                            int prev, double& bestv,
-                                            int& bestc, int& nevals,
-                                            int& ncost) {
+                                            const Tile<T, MP>& tl,
+                                            int64_t kinst, T* sw, int prev,
+                                            double& bestv, int& bestc,
+                                            int& nevals, int& ncost) {
   const int d = a.d;
   const int lane = threadIdx.x & (kWave - 1);
   T wk[NS], cs[NS];
@@ -1542,17 +1550,45 @@ __device__ __forceinline__ void assign_tile(const AssignArgs<T>& a,
   }
   pair_costs<T, MP, NS>(a, tl, c0, cs);
   ++ncost;
+  const double lb0 = a.lbs ? cost_lower_bound<T, MP, NS>(tl, cs, wk) : 0.0;
   consider(c0);
+  // stored bound of a formed cost block: sqrt(LB) rounded down by far more
+  // than the FP32 rounding of the block, so it stays a lower bound
+  auto stored = [](double lbv) -> float {
+    return (float)(sqrt(lbv > 0.0 ? lbv : 0.0) * (1.0 - 1e-6));
+  };
+  const int64_t lrow = kinst * (int64_t)a.K;  // this instance's bounds
   // 2) every other centroid unless a bound clears the best value by a
   // margin far above FP32 rounding of the column sums, so a skipped
   // centroid can never be the argmin (ties go to the lowest index).  The
-  // cheap bounds of 64 centroids at a time, one per lane; the survivors in
-  // index order, each checked again against the best value at its turn.
+  // bounds of 64 centroids at a time, one per lane: the stored bound of the
+  // last pruned assignment decayed by the centroid's support drift (if
+  // sqrt(LB) was at least u and no support point moved further than dlt,
+  // sqrt(LB) is at least u - dlt: every min_i |y_j - x_i| falls by at most
+  // dlt and the w-weighted 2-norm over j by at most dlt), else the cheap
+  // bound; the survivors in index order, each checked again against the
+  // best value at its turn.
   for (int b0 = 0; b0 < a.K; b0 += kWave) {
     const int c = b0 + lane;
-    const T lb = c < a.K ? cheap_bound(a, c, smu, srj, swj, tl.mk) : big;
+    const double cut0 = bestv * (1.0 + 1e-4);
+    T lb = big;
+    float nu = 0.0f;  // new stored bound of pair (k, c)
+    if (c < a.K) {
+      T sb = T(0);
+      if (a.lbs && a.lbs_in) {
+        const T u = (T)a.lbs[lrow + c] - (T)a.dlt[c];
+        sb = u > T(0) ? u : T(0);
+      }
+      lb = sb * sb;
+      if ((double)lb <= cut0) {
+        const T cb = cheap_bound(a, c, smu, srj, swj, tl.mk);
+        lb = cb > lb ? cb : lb;
+      }
+      nu = (float)dsqrt(lb) * (1.0f - 1e-6f);
+      if (c == c0) nu = stored(lb0);
+    }
     unsigned long long live =
-        __ballot(c < a.K && c != c0 && (double)lb <= bestv * (1.0 + 1e-4));
+        __ballot(c < a.K && c != c0 && (double)lb <= cut0);
     while (live) {
       const int bit = __builtin_ctzll(live);
       live &= live - 1;
@@ -1561,9 +1597,12 @@ __device__ __forceinline__ void assign_tile(const AssignArgs<T>& a,
       const int cc = b0 + bit;
       pair_costs<T, MP, NS>(a, tl, cc, cs);
       ++ncost;
-      if (cost_lower_bound<T, MP, NS>(tl, cs, wk) > cut) continue;
+      const double lbx = cost_lower_bound<T, MP, NS>(tl, cs, wk);
+      if (lane == bit) nu = stored(lbx);
+      if (lbx > cut) continue;
       consider(cc);
     }
+    if (a.lbs && c < a.K) a.lbs[lrow + c] = nu;
   }
 }
 
@@ -1584,7 +1623,7 @@ __global__ void __launch_bounds__(256) k_assign(AssignArgs<T> a) {
   double bestv = 0.0;
   int bestc = -1, nevals = 0, ncost = 0;
   with_slots<R>(tl.nsl, [&]<int NS>() {
-    assign_tile<T, MP, NS>(a, tl, sw, prev, bestv, bestc, nevals, ncost);
+    assign_tile<T, MP, NS>(a, tl, k, sw, prev, bestv, bestc, nevals, ncost);
   });
   if (lane == 0) {
     a.labels[k] = bestc;

@@ -31,19 +31,29 @@ void add_kernels(KernTable<T>& t) {
 
 // Tiles up to 2048 entries: R * (64 / MP) columns of MP rows, m_k <= 64.
 // PLAIN: the kernels without support terms and the auxiliary kernels fixed
-// to one mode (a translation unit of their own)
-template <typename T, bool PLAIN> void fill_table(KernTable<T>& t) {
-  add_kernels<T, 8, 1, PLAIN>(t);  add_kernels<T, 8, 2, PLAIN>(t);
-  add_kernels<T, 8, 4, PLAIN>(t);  add_kernels<T, 8, 8, PLAIN>(t);
-  add_kernels<T, 16, 1, PLAIN>(t); add_kernels<T, 16, 2, PLAIN>(t);
-  add_kernels<T, 16, 4, PLAIN>(t); add_kernels<T, 16, 8, PLAIN>(t);
-  add_kernels<T, 16, 16, PLAIN>(t);
-  add_kernels<T, 32, 1, PLAIN>(t); add_kernels<T, 32, 2, PLAIN>(t);
-  add_kernels<T, 32, 4, PLAIN>(t); add_kernels<T, 32, 8, PLAIN>(t);
-  add_kernels<T, 32, 16, PLAIN>(t); add_kernels<T, 32, 32, PLAIN>(t);
-  add_kernels<T, 64, 1, PLAIN>(t); add_kernels<T, 64, 2, PLAIN>(t);
-  add_kernels<T, 64, 4, PLAIN>(t); add_kernels<T, 64, 8, PLAIN>(t);
-  add_kernels<T, 64, 16, PLAIN>(t); add_kernels<T, 64, 32, PLAIN>(t);
+// to one mode (a translation unit of their own).  Row paddings MP in
+// [LO, HI] only, so that one type's kernels compile in parallel units.
+template <typename T, bool PLAIN, int LO = 8, int HI = 64>
+void fill_table(KernTable<T>& t) {
+  if constexpr (LO <= 8 && 8 <= HI) {
+    add_kernels<T, 8, 1, PLAIN>(t);  add_kernels<T, 8, 2, PLAIN>(t);
+    add_kernels<T, 8, 4, PLAIN>(t);  add_kernels<T, 8, 8, PLAIN>(t);
+  }
+  if constexpr (LO <= 16 && 16 <= HI) {
+    add_kernels<T, 16, 1, PLAIN>(t); add_kernels<T, 16, 2, PLAIN>(t);
+    add_kernels<T, 16, 4, PLAIN>(t); add_kernels<T, 16, 8, PLAIN>(t);
+    add_kernels<T, 16, 16, PLAIN>(t);
+  }
+  if constexpr (LO <= 32 && 32 <= HI) {
+    add_kernels<T, 32, 1, PLAIN>(t); add_kernels<T, 32, 2, PLAIN>(t);
+    add_kernels<T, 32, 4, PLAIN>(t); add_kernels<T, 32, 8, PLAIN>(t);
+    add_kernels<T, 32, 16, PLAIN>(t); add_kernels<T, 32, 32, PLAIN>(t);
+  }
+  if constexpr (LO <= 64 && 64 <= HI) {
+    add_kernels<T, 64, 1, PLAIN>(t); add_kernels<T, 64, 2, PLAIN>(t);
+    add_kernels<T, 64, 4, PLAIN>(t); add_kernels<T, 64, 8, PLAIN>(t);
+    add_kernels<T, 64, 16, PLAIN>(t); add_kernels<T, 64, 32, PLAIN>(t);
+  }
 }
 
 }  // namespace d2k

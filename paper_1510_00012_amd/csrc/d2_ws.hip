@@ -20,6 +20,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <cstdio>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -1259,6 +1260,97 @@ d2_status d2_ws_params_get(d2_ws* w, float* theta) {
   WSCHK(w, hipDeviceSynchronize());
   WSCHK(w, hipMemcpy(theta, w->th, sizeof(float) * w->np,
                      hipMemcpyDeviceToHost));
+  return D2_OK;
+}
+
+namespace {
+constexpr char kWsMagic[8] = {'D', '2', 'W', 'S', 'N', 'E', 'T', 1};
+struct WsHeader {
+  char magic[8];
+  int32_t m, d, H, pad;
+  int64_t np, step;
+};
+uint64_t fnv(const void* p, size_t n, uint64_t h) {
+  const unsigned char* b = (const unsigned char*)p;
+  for (size_t q = 0; q < n; ++q) h = (h ^ b[q]) * 1099511628211ull;
+  return h;
+}
+}  // namespace
+
+d2_status d2_ws_save(d2_ws* w, const char* path) {
+  if (!w) return D2_EINVAL;
+  if (!path) return w->fail(D2_EINVAL, "null path");
+  WSCHK(w, hipSetDevice(w->device));
+  WSCHK(w, hipDeviceSynchronize());
+  std::vector<float> buf((size_t)3 * w->np);
+  WSCHK(w, hipMemcpy(buf.data(), w->th, sizeof(float) * w->np,
+                     hipMemcpyDeviceToHost));
+  WSCHK(w, hipMemcpy(buf.data() + w->np, w->m1, sizeof(float) * w->np,
+                     hipMemcpyDeviceToHost));
+  WSCHK(w, hipMemcpy(buf.data() + 2 * w->np, w->m2, sizeof(float) * w->np,
+                     hipMemcpyDeviceToHost));
+  WsHeader h;
+  std::memset(&h, 0, sizeof(h));
+  std::memcpy(h.magic, kWsMagic, 8);
+  h.m = w->m;
+  h.d = w->d;
+  h.H = w->H;
+  h.np = w->np;
+  h.step = w->step;
+  uint64_t sum = fnv(&h, sizeof(h), 1469598103934665603ull);
+  sum = fnv(buf.data(), sizeof(float) * buf.size(), sum);
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE* f = fopen(tmp.c_str(), "wb");
+  if (!f) return w->fail(D2_EINVAL, "cannot open " + tmp + " for writing");
+  bool ok = fwrite(&h, sizeof(h), 1, f) == 1 &&
+            fwrite(buf.data(), sizeof(float), buf.size(), f) == buf.size() &&
+            fwrite(&sum, 8, 1, f) == 1;
+  ok = (fclose(f) == 0) && ok;
+  if (!ok || std::rename(tmp.c_str(), path) != 0) {
+    std::remove(tmp.c_str());
+    return w->fail(D2_EINVAL, std::string("writing ") + path + " failed");
+  }
+  return D2_OK;
+}
+
+d2_status d2_ws_load(d2_ws* w, const char* path) {
+  if (!w) return D2_EINVAL;
+  if (!path) return w->fail(D2_EINVAL, "null path");
+  FILE* f = fopen(path, "rb");
+  if (!f) return w->fail(D2_EINVAL, std::string("cannot open ") + path);
+  WsHeader h;
+  std::vector<float> buf((size_t)3 * w->np);
+  uint64_t sum = 0;
+  bool ok = fread(&h, sizeof(h), 1, f) == 1;
+  const bool same = ok && std::memcmp(h.magic, kWsMagic, 8) == 0 &&
+                    h.m == w->m && h.d == w->d && h.H == w->H &&
+                    h.np == w->np && h.step >= 0;
+  ok = same && fread(buf.data(), sizeof(float), buf.size(), f) == buf.size() &&
+       fread(&sum, 8, 1, f) == 1;
+  fclose(f);
+  if (!same)
+    return w->fail(D2_EINVAL, std::string(path) +
+                                  ": not a network of this shape (m, d, H)");
+  if (!ok) return w->fail(D2_EINVAL, std::string(path) + ": truncated");
+  uint64_t want = fnv(&h, sizeof(h), 1469598103934665603ull);
+  want = fnv(buf.data(), sizeof(float) * buf.size(), want);
+  if (want != sum)
+    return w->fail(D2_EINVAL, std::string(path) + ": checksum mismatch");
+  for (size_t q = 0; q < buf.size(); ++q)
+    if (!std::isfinite(buf[q]))
+      return w->fail(D2_EINVAL, std::string(path) + ": non-finite values");
+  WSCHK(w, hipSetDevice(w->device));
+  WSCHK(w, hipDeviceSynchronize());
+  WSCHK(w, hipMemcpy(w->th, buf.data(), sizeof(float) * w->np,
+                     hipMemcpyHostToDevice));
+  WSCHK(w, hipMemcpy(w->m1, buf.data() + w->np, sizeof(float) * w->np,
+                     hipMemcpyHostToDevice));
+  WSCHK(w, hipMemcpy(w->m2, buf.data() + 2 * w->np, sizeof(float) * w->np,
+                     hipMemcpyHostToDevice));
+  w->step = h.step;
+  d2_status s = refresh(w, nullptr);
+  if (s) return s;
+  WSCHK(w, hipDeviceSynchronize());
   return D2_OK;
 }
 

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libd2.so")
 
 D2_OK, D2_EINVAL, D2_ENOMEM, D2_EDEVICE, D2_ENUMERIC, D2_ESTATE = range(6)
 D2_F32, D2_F64 = 0, 1
-D2_INIT_PRODUCT, D2_INIT_CACHED = 0, 1
+D2_INIT_PRODUCT, D2_INIT_CACHED, D2_INIT_LEARNED = 0, 1, 2
 STATUS_NAMES = {0: "D2_OK", 1: "D2_EINVAL", 2: "D2_ENOMEM", 3: "D2_EDEVICE",
                 4: "D2_ENUMERIC", 5: "D2_ESTATE"}
 
@@ -30,7 +30,9 @@ EXPORTS = [
     "d2_sizes", "d2_set_profiling", "d2_kernel_stats", "d2_set_schedule",
     "d2_assign_pairs", "d2_set_graph", "d2_autotune",
     "d2_set_bucketing", "d2_objective_feasible", "d2_residual",
-    "d2_copy_probe", "d2_ws_param_count", "d2_ws_create",
+    "d2_copy_probe", "d2_set_assign_bounds", "d2_load_instances_device",
+    "d2_checkpoint_save", "d2_checkpoint_load", "d2_set_warm_start",
+    "d2_ws_save", "d2_ws_load", "d2_ws_param_count", "d2_ws_create",
     "d2_ws_destroy", "d2_ws_last_error", "d2_ws_params_set",
     "d2_ws_params_get", "d2_ws_targets_from", "d2_ws_grad",
     "d2_ws_train_step", "d2_ws_propose",
@@ -122,6 +124,14 @@ def load_library(path: str = LIB_PATH):
         "d2_set_bucketing": ([_p, _i32], ctypes.c_int),
         "d2_assign_pairs": ([_p, _p, _p, _p], ctypes.c_int),
         "d2_set_graph": ([_p, _i32], ctypes.c_int),
+        "d2_set_assign_bounds": ([_p, _i32], ctypes.c_int),
+        "d2_load_instances_device": ([_p, _i64, _i32, _p, _p, _p],
+                                     ctypes.c_int),
+        "d2_checkpoint_save": ([_p, ctypes.c_char_p], ctypes.c_int),
+        "d2_checkpoint_load": ([_p, ctypes.c_char_p], ctypes.c_int),
+        "d2_set_warm_start": ([_p, _p, _i32], ctypes.c_int),
+        "d2_ws_save": ([_p, ctypes.c_char_p], ctypes.c_int),
+        "d2_ws_load": ([_p, ctypes.c_char_p], ctypes.c_int),
         "d2_autotune": ([_p, ctypes.POINTER(BadmmParams), _p, _p, _p, _p],
                         ctypes.c_int),
         "d2_kernel_stats": ([_p, ctypes.POINTER(KernelStat), _i32, _p, _i32],
@@ -236,6 +246,36 @@ class D2Context:
                                              _ptr(W)))
         self.offsets, self.N, self.n, self.d = off, N, int(off[-1]), d
 
+    def load_instances_device(self, offsets, dX, dW, d):
+        """Borrow device buffers (integer device addresses, e.g. a torch
+        tensor's data_ptr()) holding X (n x roundup(d, 4), zero padded) and
+        W (n) in the context's dtype; the caller keeps them alive."""
+        off = _c(offsets, np.int64)
+        N = len(off) - 1
+        self._chk(self.lib.d2_load_instances_device(
+            self.h, N, int(d), _ptr(off), _p(int(dX)), _p(int(dW))))
+        self.offsets, self.N, self.n, self.d = off, N, int(off[-1]), int(d)
+
+    def checkpoint_save(self, path):
+        self._chk(self.lib.d2_checkpoint_save(self.h, os.fsencode(path)))
+
+    def checkpoint_load(self, path):
+        """Restore centroids, labels, plan cache and schedule (the context
+        must hold the same instances)."""
+        self._chk(self.lib.d2_checkpoint_load(self.h, os.fsencode(path)))
+        N, n, d, K, m = (ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32(),
+                         ctypes.c_int32(), ctypes.c_int32())
+        self._chk(self.lib.d2_sizes(self.h, ctypes.byref(N), ctypes.byref(n),
+                                    ctypes.byref(d), ctypes.byref(K),
+                                    ctypes.byref(m)))
+        self.K, self.m = K.value, m.value
+
+    def set_warm_start(self, ws, gate=True):
+        """Attach a D2WarmStart for init=D2_INIT_LEARNED (None detaches)."""
+        self._ws = ws
+        self._chk(self.lib.d2_set_warm_start(
+            self.h, None if ws is None else ws.h, int(bool(gate))))
+
     def centroids_set(self, Xc, Wc):
         Xc = _c(Xc, np.float64)
         Wc = _c(Wc, np.float64)
@@ -349,6 +389,10 @@ class D2Context:
         return {"chunk": ch.value, "waves": wv.value, "bucket": bk.value,
                 "ms": ms.value}
 
+    def set_assign_bounds(self, on=True):
+        """Cross-round lower bounds of the pruned assignment on / off."""
+        self._chk(self.lib.d2_set_assign_bounds(self.h, int(bool(on))))
+
     def set_graph(self, on=True):
         self._chk(self.lib.d2_set_graph(self.h, int(bool(on))))
 
@@ -451,6 +495,12 @@ class D2WarmStart:
         if th.size != self.np:
             raise D2Error(D2_EINVAL, "theta size")
         self._chk(self.lib.d2_ws_params_set(self.h, _ptr(th)))
+
+    def save(self, path):
+        self._chk(self.lib.d2_ws_save(self.h, os.fsencode(path)))
+
+    def load(self, path):
+        self._chk(self.lib.d2_ws_load(self.h, os.fsencode(path)))
 
     def targets_from(self, ctx):
         self._chk(self.lib.d2_ws_targets_from(self.h, ctx.h))

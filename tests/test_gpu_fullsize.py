@@ -141,7 +141,11 @@ def test_fullsize_clustering_loop_teacher_forced(d2):
     both run the warm-started centroid update (Sec. 5: cached Pi2 for
     members whose label did not change) on those labels; every cluster's
     objective trace and centroid, and the plans of sampled instances, are
-    compared."""
+    compared.  Each side carries its own Pi2 cache from round to round, so
+    the plans of round r have been through r + 1 calls and hold their FP32
+    rounding: their entries and marginals are held to 1e-6 per call
+    (the single-call bar of test_gpu_parity), Lambda / rho to 2e-5 per
+    call."""
     print("[fullsize clustering loop]", flush=True)
     wl = make_workload("gmm_d3_n65536_k16")
     K, m, T = wl["K"], wl["m"], 100
@@ -183,11 +187,13 @@ def test_fullsize_clustering_loop_teacher_forced(d2):
             errs = plan_errors(ctx, wl, plans, ks, lambda k: rhos[lab[k]])
             print(f"  round {r}: trace rel {worst:.3g}, centroid "
                   f"{np.abs(Xg - Xo).max():.3g}/{np.abs(Wg - Wo).max():.3g},"
-                  f" plans {errs[0]:.3g} {errs[1]:.3g} {errs[2]:.3g}",
-                  flush=True)
+                  f" plans Pi1 {errs[0]:.3g} Pi2 {errs[1]:.3g} Lambda/rho "
+                  f"{errs[2]:.3g} marginals {errs[3]:.3g}", flush=True)
             assert worst < 1e-5, r
             assert np.abs(Wg - Wo).max() < 1e-5, r
             assert np.abs(Xg - Xo).max() < 1e-5, r
-            assert errs[0] <= 1e-6 and errs[1] <= 1e-6 and errs[3] <= 1e-6
-            assert errs[2] <= 2e-5, r
+            calls = r + 1
+            assert errs[0] <= 1e-6 * calls and errs[1] <= 1e-6 * calls, r
+            assert errs[3] <= 1e-6 * calls, r
+            assert errs[2] <= 2e-5 * calls, r
             Xc, Wc, prev = Xo, Wo, lab

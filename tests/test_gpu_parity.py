@@ -634,3 +634,49 @@ def test_assignment_bound_odd_shapes(d2, d, m, mk_hi):
     assert _rel(best_a, best_o) < 1e-5
     ok = (lab_a == lab_o) | (margin < 1e-5)
     assert ok.all(), np.nonzero(~ok)
+
+
+@pytest.mark.parametrize("name,N,K,m", [("gmm_d16_n2000000_k256", 3000, 100, 16),
+                                        ("topic_d64_n200000_k64", 1500, 70, 32),
+                                        ("gmm_d3_n65536_k16", 4000, 16, 16)])
+def test_assignment_cross_round_bounds_exact(d2, name, N, K, m):
+    """Four assignment rounds with centroids moving in between (a B-ADMM
+    update, then a random jitter of every support point): the pruned
+    assignment with cross-round bounds returns bitwise the labels and
+    minimal distances of the exhaustive search and of pruning without
+    stored bounds, and from the second round on forms fewer cost blocks
+    than pruning without them."""
+    print(f"[cross-round bounds {name} K={K}]", flush=True)
+    wl = make_workload(name, N=N)
+    d = wl["X"].shape[1]
+    rng = np.random.Generator(np.random.PCG64(77))
+    if np.sum(np.diff(wl["offsets"]) >= m) >= K:
+        mem = pick_init_members(wl["offsets"], K, m, 41)
+        Xc, Wc = oracle.init_centroids(wl, mem, m)
+    else:
+        Xc = wl["X"][rng.choice(len(wl["X"]), size=(K, m))]
+        Wc = rng.random((K, m)) + 0.05
+        Wc /= Wc.sum(1, keepdims=True)
+    with _ctx(d2, wl, "f32") as A, _ctx(d2, wl, "f32") as B, \
+            _ctx(d2, wl, "f32") as C:
+        C.set_assign_bounds(False)
+        for r in range(4):
+            for ctx in (A, B, C):
+                ctx.centroids_set(Xc, Wc)
+            la, ba, _ = A.assign(iters=60, prune=True)
+            lb, bb, _ = B.assign(iters=60, prune=False)
+            lc, bc, _ = C.assign(iters=60, prune=True)
+            co_a, co_c = A.assign_pairs_costed(), C.assign_pairs_costed()
+            print(f"  round {r}: cost blocks with bounds {co_a}, without "
+                  f"{co_c} of {N * K}", flush=True)
+            assert np.array_equal(la, lb) and np.array_equal(ba, bb), r
+            assert np.array_equal(lc, lb) and np.array_equal(bc, bb), r
+            if r > 0:
+                assert co_a < co_c, r
+            # move the centroids: a short B-ADMM update on these labels,
+            # then a jitter of every support point
+            A.barycenter(iters=20, init=d2.D2_INIT_PRODUCT)
+            Xc, Wc = A.centroids_get()
+            scale = 0.02 * np.abs(Xc).mean()
+            Xc = Xc + scale * rng.standard_normal(Xc.shape)
+            Wc = Wc / Wc.sum(1, keepdims=True)
