@@ -96,6 +96,15 @@ def load_library(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise OSError(f"{path} is missing: build it with "
                       "`python -m paper_1510_00012_amd.build`")
+    try:
+        # PyTorch ships its own HIP runtime under the same soname as the
+        # system one libd2.so links against.  Loading torch first makes the
+        # library bind to that runtime, so that the process holds a single
+        # HIP runtime and torch tensors / streams can be handed to the
+        # library; loaded the other way round, torch finds no GPU.
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     sig = {
         "d2_create": ([ctypes.POINTER(_p), ctypes.c_int, ctypes.c_int, _p],
