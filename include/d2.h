@@ -314,6 +314,41 @@ d2_status d2_checkpoint_load(d2_ctx* ctx, const char* path);
 d2_status d2_copy_probe(int device, int64_t bytes, int32_t reps, double* gbs,
                         double* ms);
 
+/* Assignment step that allocates nothing, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Computes what d2_assign computes on a
+ * fresh context (no previous labels, no cross-round bounds): labels[k] =
+ * argmin_c of the B-ADMM transport value of `p` between centroid c and
+ * instance k, ties to the lowest c, dist[k] its minimal value.
+ * Everything is the caller's device memory on `device`:
+ *   offsets  N+1 int64 (offsets[0] = 0, 1 <= m_k <= mk_max),
+ *   X        n x xs values of `dtype` (float / double), xs = d rounded up
+ *            to a multiple of 4, padding columns 0, row-major,
+ *   W        n instance weights of `dtype` (each instance in the simplex),
+ *   Xc, Wc   K x m x d and K x m doubles (Wc rows are divided by their sum),
+ *   labels   N int32 (out), dist N doubles (out).
+ * The per-centroid data the kernels need besides these live in a fixed
+ * 8 MiB device array of the library, one per GPU, held until the process
+ * ends: K x pad(m) x (d + 1) doubles plus K x (pad(m) x xs + d + 1) values
+ * of `dtype` (256-byte aligned parts) must fit in it, else D2_EINVAL with
+ * the sizes in `err`.  The call only enqueues work on hip_stream (NULL: the
+ * device's null stream) and returns without waiting; the outputs are
+ * valid once the stream reaches that point.  Calls that overlap on one GPU
+ * (other streams, other host threads) share the array and race; calls on
+ * one stream are ordered.  Argument errors (D2_EINVAL, checked before any
+ * device call) and launch failures (D2_EDEVICE) write a message to err
+ * (err_len bytes with the terminating zero; err may be NULL).  The device
+ * data is not inspected: an instance with m_k < 1 or m_k > mk_max gets
+ * label -1 and a NaN distance; offsets outside X and W are undefined.
+ * N = 0 returns D2_OK without touching the device. */
+d2_status d2_assign_noalloc(int32_t device, void* hip_stream, d2_dtype dtype,
+                            int64_t N, int32_t d, int32_t mk_max,
+                            const int64_t* offsets, const void* X,
+                            const void* W, int32_t K, int32_t m,
+                            const double* Xc, const double* Wc,
+                            const d2_ot_params* p, int32_t* labels,
+                            double* dist, char* err, int32_t err_len);
+
 /* Sizes: N, n, d, K, m of the context (any pointer may be NULL). */
 d2_status d2_sizes(const d2_ctx* ctx, int64_t* N, int64_t* n, int32_t* d,
                    int32_t* K, int32_t* m);

@@ -10,7 +10,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libd2.so")
 SOURCES = ["d2_k_f64.hip", "d2_k_f64w.hip", "d2_k_f32.hip", "d2_k_f32w.hip",
-           "d2_k_f64p.hip", "d2_k_f32p.hip", "d2_api.hip", "d2_ws.hip"]
+           "d2_k_f64p.hip", "d2_k_f32p.hip", "d2_api.hip", "d2_ws.hip",
+           "d2_noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

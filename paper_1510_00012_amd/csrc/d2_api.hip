@@ -934,64 +934,6 @@ int slots_for(const d2_ctx* c) {
   return 1 << ilog2(std::max(1, need));
 }
 
-// Per-centroid mean (weights of the centroid) and support radius around it,
-// for the cheap assignment lower bound; the radius is rounded up slightly.
-// Per-centroid quantities of the assignment's lower bounds: the weighted
-// mean of the support, the largest distance of a support point from it
-// (inflated by 1e-6 relative so that rounding cannot make a bound
-// invalid), and the support in the device dtype with row stride xs.  One
-// wavefront per centroid, FP64 sums in index order.
-template <typename T>
-__global__ void __launch_bounds__(64)
-    k_cstats(const double* xc, const double* wc, int m, int MP, int d,
-             int xs, int K, T* cmu, T* crad, T* xct, const double* xref,
-             float* dlt) {
-  extern __shared__ double s_mu[];  // d
-  const int q = blockIdx.x, l = threadIdx.x;
-  const double* xq = xc + (size_t)q * MP * d;
-  const double* wq = wc + (size_t)q * MP;
-  for (int e = l; e < MP * xs; e += 64) {
-    const int i = e / xs, t = e % xs;
-    xct[(size_t)q * MP * xs + e] = t < d ? (T)xq[(size_t)i * d + t] : T(0);
-  }
-  double ws = 0.0;
-  for (int i = 0; i < m; ++i) ws += wq[i];
-  const double div = ws > 0 ? ws : 1.0;
-  for (int t = l; t < d; t += 64) {
-    double s = 0.0;
-    for (int i = 0; i < m; ++i) s += wq[i] * xq[(size_t)i * d + t] / div;
-    s_mu[t] = s;
-    cmu[(size_t)t * K + q] = (T)s;
-  }
-  __syncthreads();
-  double r = 0.0;
-  for (int i = l; i < m; i += 64) {
-    double s = 0.0;
-    for (int t = 0; t < d; ++t) {
-      const double df = xq[(size_t)i * d + t] - s_mu[t];
-      s += df * df;
-    }
-    r = fmax(r, sqrt(s));
-  }
-  for (int o = 32; o > 0; o >>= 1) r = fmax(r, __shfl_xor(r, o));
-  if (l == 0) crad[q] = (T)(r * (1.0 + 1e-6) + 1e-30);
-  if (xref) {
-    // drift: the largest distance a support point moved since xref
-    const double* xo = xref + (size_t)q * MP * d;
-    double g = 0.0;
-    for (int i = l; i < m; i += 64) {
-      double s = 0.0;
-      for (int t = 0; t < d; ++t) {
-        const double df = xq[(size_t)i * d + t] - xo[(size_t)i * d + t];
-        s += df * df;
-      }
-      g = fmax(g, sqrt(s));
-    }
-    for (int o = 32; o > 0; o >>= 1) g = fmax(g, __shfl_xor(g, o));
-    if (l == 0) dlt[q] = (float)(g * (1.0 + 1e-6) + 1e-30);
-  }
-}
-
 template <typename T>
 d2_status centroid_stats(d2_ctx* c) {
   const int K = c->K, MP = c->MP, d = c->d;
@@ -1002,7 +944,7 @@ d2_status centroid_stats(d2_ctx* c) {
     if ((s = dalloc(c, &c->d_xct, sizeof(T) * (size_t)K * MP * c->xs)))
       return s;
   }
-  hipLaunchKernelGGL(k_cstats<T>, dim3(K), dim3(64), sizeof(double) * d,
+  hipLaunchKernelGGL(d2k::k_cstats<T>, dim3(K), dim3(64), sizeof(double) * d,
                      c->stream, c->d_xc, c->d_wc, c->m, MP, d, c->xs, K,
                      (T*)c->d_cmu, (T*)c->d_crad, (T*)c->d_xct,
                      c->lbs_valid ? (const double*)c->d_xref : nullptr,

@@ -1261,10 +1261,12 @@ template <typename T> struct AssignArgs {
   double* best;
   int32_t* counts;      // N x 2 per instance: pairs run through the
                         // iterations, pairs whose cost block was formed
+                        // (null: not counted)
   const T* cmu;         // d x K weighted mean of each centroid's support
   const T* crad;        // K  radius of the support around that mean
   const T* xct;         // K x MP x xs centroid supports in the device dtype
-  const int32_t* list;  // instance ids of this launch (one slot class)
+  const int32_t* list;  // instance ids of this launch (one slot class);
+                        // null: instances 0 .. N-1
   // Cross-round bounds (pruning only): lbs[k * K + c] holds a lower bound
   // on sqrt(LB(k, c)), LB the column-relaxed bound below, valid for the
   // centroid supports of the last pruned assignment; dlt[c] bounds how far
@@ -1614,11 +1616,20 @@ __global__ void __launch_bounds__(256) k_assign(AssignArgs<T> a) {
   const int wave = uni(threadIdx.x / kWave);
   const int64_t q = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave;
   if (q >= a.N) return;  // whole wavefront exits together
-  const int64_t k = uni(a.list[q]);
+  const int64_t k = a.list ? uni(a.list[q]) : q;
   T* sw = reinterpret_cast<T*>(s_raw) +
           (int64_t)wave * (a.d + 2 * (kWave / MP) * R);
   Tile<T, MP> tl;
   tl.setup(a.off, nullptr, a.m, (int)k);
+  if (tl.mk < 1 || tl.nsl > R) {
+    // outside this kernel's tile shapes (only reachable through callers
+    // that hand over unchecked offsets): no support point is read
+    if (lane == 0) {
+      a.labels[k] = -1;
+      a.best[k] = __builtin_nan("");
+    }
+    return;
+  }
   const int prev = a.prev_valid ? uni(a.labels[k]) : -1;
   double bestv = 0.0;
   int bestc = -1, nevals = 0, ncost = 0;
@@ -1630,7 +1641,64 @@ __global__ void __launch_bounds__(256) k_assign(AssignArgs<T> a) {
     a.best[k] = bestv;
     // per-instance counts (plain stores: a counter shared by all
     // wavefronts serialises its atomic updates)
-    reinterpret_cast<int2*>(a.counts)[k] = make_int2(nevals, ncost);
+    if (a.counts)
+      reinterpret_cast<int2*>(a.counts)[k] = make_int2(nevals, ncost);
+  }
+}
+
+// Per-centroid quantities of the assignment's lower bounds: the weighted
+// mean of the support, the largest distance of a support point from it
+// (inflated by 1e-6 relative so that rounding cannot make a bound
+// invalid), and the support in the device dtype with row stride xs.  One
+// wavefront per centroid, FP64 sums in index order.
+template <typename T>
+__global__ void __launch_bounds__(64)
+    k_cstats(const double* xc, const double* wc, int m, int MP, int d,
+             int xs, int K, T* cmu, T* crad, T* xct, const double* xref,
+             float* dlt) {
+  extern __shared__ double s_mu[];  // d
+  const int q = blockIdx.x, l = threadIdx.x;
+  const double* xq = xc + (size_t)q * MP * d;
+  const double* wq = wc + (size_t)q * MP;
+  for (int e = l; e < MP * xs; e += 64) {
+    const int i = e / xs, t = e % xs;
+    xct[(size_t)q * MP * xs + e] = t < d ? (T)xq[(size_t)i * d + t] : T(0);
+  }
+  double ws = 0.0;
+  for (int i = 0; i < m; ++i) ws += wq[i];
+  const double div = ws > 0 ? ws : 1.0;
+  for (int t = l; t < d; t += 64) {
+    double s = 0.0;
+    for (int i = 0; i < m; ++i) s += wq[i] * xq[(size_t)i * d + t] / div;
+    s_mu[t] = s;
+    cmu[(size_t)t * K + q] = (T)s;
+  }
+  __syncthreads();
+  double r = 0.0;
+  for (int i = l; i < m; i += 64) {
+    double s = 0.0;
+    for (int t = 0; t < d; ++t) {
+      const double df = xq[(size_t)i * d + t] - s_mu[t];
+      s += df * df;
+    }
+    r = fmax(r, sqrt(s));
+  }
+  for (int o = 32; o > 0; o >>= 1) r = fmax(r, __shfl_xor(r, o));
+  if (l == 0) crad[q] = (T)(r * (1.0 + 1e-6) + 1e-30);
+  if (xref) {
+    // drift: the largest distance a support point moved since xref
+    const double* xo = xref + (size_t)q * MP * d;
+    double g = 0.0;
+    for (int i = l; i < m; i += 64) {
+      double s = 0.0;
+      for (int t = 0; t < d; ++t) {
+        const double df = xq[(size_t)i * d + t] - xo[(size_t)i * d + t];
+        s += df * df;
+      }
+      g = fmax(g, sqrt(s));
+    }
+    for (int o = 32; o > 0; o >>= 1) g = fmax(g, __shfl_xor(g, o));
+    if (l == 0) dlt[q] = (float)(g * (1.0 + 1e-6) + 1e-30);
   }
 }
 

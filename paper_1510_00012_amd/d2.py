@@ -35,7 +35,7 @@ EXPORTS = [
     "d2_ws_save", "d2_ws_load", "d2_ws_param_count", "d2_ws_create",
     "d2_ws_destroy", "d2_ws_last_error", "d2_ws_params_set",
     "d2_ws_params_get", "d2_ws_targets_from", "d2_ws_grad",
-    "d2_ws_train_step", "d2_ws_propose",
+    "d2_ws_train_step", "d2_ws_propose", "d2_assign_noalloc",
 ]
 
 
@@ -159,6 +159,10 @@ def load_library(path: str = LIB_PATH):
         "d2_ws_train_step": ([_p, _p, _p, _i32, ctypes.POINTER(WsOpt), _p],
                              ctypes.c_int),
         "d2_ws_propose": ([_p, _p, _i32, _p, _p, _p], ctypes.c_int),
+        "d2_assign_noalloc": ([_i32, _p, ctypes.c_int, _i64, _i32, _i32, _p,
+                               _p, _p, _i32, _i32, _p, _p,
+                               ctypes.POINTER(OtParams), _p, _p,
+                               ctypes.c_char_p, _i32], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -452,6 +456,23 @@ def copy_probe(device=0, mib=2048, reps=10):
     if st != D2_OK:
         raise D2Error(st, "d2_copy_probe failed")
     return g.value, t.value
+
+
+def assign_noalloc(N, d, mk_max, offsets, X, W, K, m, Xc, Wc, labels, dist,
+                   dtype="f32", iters=100, rho0=2.0, eps=1e-16, prune=True,
+                   device=0, stream=None):
+    """d2_assign_noalloc: every array argument is an integer device address
+    (e.g. a torch tensor's data_ptr()); the call only enqueues work on
+    `stream` (a hipStream_t as an integer, None: the null stream)."""
+    lib = load_library()
+    p = ot_params(iters, rho0, eps, prune)
+    err = ctypes.create_string_buffer(256)
+    st = lib.d2_assign_noalloc(
+        int(device), stream, D2_F32 if dtype == "f32" else D2_F64, int(N),
+        int(d), int(mk_max), offsets, X, W, int(K), int(m), Xc, Wc,
+        ctypes.byref(p), labels, dist, err, len(err))
+    if st != D2_OK:
+        raise D2Error(st, err.value.decode())
 
 
 def ws_param_count(m, d, hidden):
