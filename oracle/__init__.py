@@ -13,6 +13,12 @@ Distribution Clustering Using Wasserstein Barycenter with Sparse Support"):
   barycenter      Sec. 3.2, Algorithm "Centroid Update with B-ADMM"
   badmm_ot        Sec. 3.2 closed forms with w fixed (the Sec. 4 pilot use)
   assign          Algorithm "D2 Clustering", assignment loop
+  barycenter_sym, assign_sym, ot_cost
+                  the same over symbolic supports (Sec. 5: a finite symbol
+                  set with a given symbol-to-symbol dissimilarity table; the
+                  support is fixed, only weights are updated)
+  assign_multi    Sec. 5 multi-modal instances: the assignment distance is
+                  the sum over modalities
   cluster         Algorithm "D2 Clustering" with the Sec. 5 warm start
   exact_w2        Eq. (primal), solved as an LP (HiGHS)
   f_true          Eq. (centroid): (1/N) sum_k W^2(P, P^(k))
@@ -82,6 +88,21 @@ def _load():
                                _f64p, ctypes.c_int, ctypes.c_int, _f64p, _f64p,
                                ctypes.c_double, ctypes.c_int, ctypes.c_double,
                                _i32p, _f64p, _f64p]
+    lib.orc_barycenter_sym.argtypes = [
+        ctypes.c_int64, _i64p, _i64p, _i32p, _f64p, ctypes.c_int, _i32p,
+        ctypes.c_int, _f64p, _f64p, _u8p, _f64p, _f64p, _f64p,
+        ctypes.c_double, ctypes.c_int, ctypes.c_double, ctypes.c_int, _f64p,
+        _f64p, _f64p]
+    lib.orc_barycenter_sym.restype = ctypes.c_int
+    lib.orc_ot_cost.argtypes = [ctypes.c_int, ctypes.c_int, _f64p, _f64p,
+                                _f64p, ctypes.c_double, ctypes.c_int,
+                                ctypes.c_double, _f64p, _f64p, _f64p]
+    lib.orc_ot_cost.restype = ctypes.c_double
+    lib.orc_assign_sym.argtypes = [ctypes.c_int64, _i64p, _i32p, _f64p,
+                                   ctypes.c_int, ctypes.c_int, _i32p, _f64p,
+                                   ctypes.c_int, _f64p, ctypes.c_double,
+                                   ctypes.c_int, ctypes.c_double, _i32p,
+                                   _f64p, _f64p]
     lib.orc_num_threads.restype = ctypes.c_int
     lib.orc_set_num_threads.argtypes = [ctypes.c_int]
     _lib = lib
@@ -200,6 +221,79 @@ def badmm_ot(x, w, y, wy, rho0=2.0, T=100, eps=1e-16, return_plans=False):
     if not return_plans:
         return v
     return v, tuple(b.reshape(mk, m).T.copy() for b in bufs)
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def barycenter_sym(wl, members, xsym, w, plans=None, warm=None, rho0=2.0,
+                   T=100, eps=1e-16, rule=1):
+    """B-ADMM barycenter over symbolic supports (Sec. 5): `wl` holds
+    offsets, the instances' symbols `sym` (n), weights `W` and the S x S
+    table `D`; the centroid's symbols xsym (m) stay fixed.  Returns dict(w,
+    ftrace, rtrace, rho, plans) as barycenter does."""
+    off, sym, W, D = wl["offsets"], _i32(wl["sym"]), wl["W"], _f64(wl["D"])
+    S = D.shape[0]
+    xs_ = _i32(xsym)
+    m = len(xs_)
+    n = int(off[-1])
+    if plans is None:
+        plans = Plans(m, n)
+    mem = np.ascontiguousarray(members, dtype=np.int64)
+    wo = _f64(w).copy()
+    wa = None if warm is None else np.ascontiguousarray(warm, dtype=np.uint8)
+    ftr = np.zeros(max(T, 1))
+    rtr = np.zeros(max(T, 1))
+    rho = np.zeros(1)
+    rc = _load().orc_barycenter_sym(
+        len(mem), _p(mem, _i64p), _p(off, _i64p), _p(sym, _i32p),
+        _p(W, _f64p), m, _p(xs_, _i32p), S, _p(D, _f64p), _p(wo, _f64p),
+        _p(wa, _u8p), _p(plans.P1, _f64p), _p(plans.P2, _f64p),
+        _p(plans.L, _f64p), float(rho0), int(T), float(eps), int(rule),
+        _p(ftr, _f64p), _p(rtr, _f64p), _p(rho, _f64p))
+    if rc != 0:
+        raise ValueError("orc_barycenter_sym: bad arguments")
+    return {"w": wo, "ftrace": ftr[:T], "rtrace": rtr[:T],
+            "rho": float(rho[0]), "plans": plans}
+
+
+def ot_cost(C, w, wy, rho0=2.0, T=100, eps=1e-16):
+    """B-ADMM transport value <C, Pi1> for a given (m, mk) cost block."""
+    C = _f64(C)
+    m, mk = C.shape
+    Ccm = np.ascontiguousarray(C.T).ravel()  # column-major m x mk
+    return _load().orc_ot_cost(m, mk, _p(Ccm, _f64p), _p(_f64(w), _f64p),
+                               _p(_f64(wy), _f64p), float(rho0), int(T),
+                               float(eps), None, None, None)
+
+
+def assign_sym(wl, Xsym, Wc, rho0=2.0, T=100, eps=1e-16, want_dist=False):
+    """Symbolic assignment: labels, best D and (optionally) all D (N x K),
+    centroid c having symbols Xsym[c] (m) and weights Wc[c]."""
+    off, sym, W, D = wl["offsets"], _i32(wl["sym"]), wl["W"], _f64(wl["D"])
+    N = len(off) - 1
+    Xsym, Wc = _i32(Xsym), _f64(Wc)
+    K, m = Xsym.shape
+    lab = np.empty(N, dtype=np.int32)
+    best = np.empty(N)
+    dist = np.empty(N * K) if want_dist else None
+    _load().orc_assign_sym(N, _p(off, _i64p), _p(sym, _i32p), _p(W, _f64p),
+                           K, m, _p(Xsym, _i32p), _p(Wc, _f64p), D.shape[0],
+                           _p(D, _f64p), float(rho0), int(T), float(eps),
+                           _p(lab, _i32p), _p(best, _f64p), _p(dist, _f64p))
+    return lab, best, (dist.reshape(N, K) if want_dist else None)
+
+
+def assign_multi(dists):
+    """Sec. 5 multi-modal instances: the combined distance of (instance,
+    centroid) is the sum of the per-modality distances (each an N x K
+    array); labels = argmin with ties to the lowest centroid."""
+    tot = np.zeros_like(np.asarray(dists[0], dtype=np.float64))
+    for dm in dists:
+        tot = tot + np.asarray(dm, dtype=np.float64)
+    lab = np.argmin(tot, axis=1).astype(np.int32)
+    return lab, tot[np.arange(len(lab)), lab], tot
 
 
 def assign(wl, Xc, Wc, rho0=2.0, T=100, eps=1e-16, want_dist=False):

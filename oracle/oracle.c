@@ -108,6 +108,37 @@ int orc_ward_merge(int mk, int d, const double* y, const double* wy, int m,
 }
 
 /*
+ * Where the cost blocks of a run come from.  Euclidean (D == NULL): C^(k) =
+ * C(x, X^(k)) of Sec. 2 item 6, x the current centroid support (updated in
+ * place by the support step).  Symbolic (D != NULL, Sec. 5: support points
+ * are symbols of a finite set with a given symbol-to-symbol dissimilarity):
+ * C^(k)_ij = D[xsym[i] * S + ysym[off[k] + j]], the centroid's i-th symbol
+ * against the instance's j-th; the support never moves.
+ */
+typedef struct {
+  int d;
+  const double* X;
+  double* x;
+  int S;
+  const double* D;
+  const int32_t* xsym;
+  const int32_t* ysym;
+} orc_costsrc;
+
+static void member_cost(const orc_costsrc* cs, int64_t k, const int64_t* off,
+                        int m, double* C) {
+  int mk = (int)(off[k + 1] - off[k]);
+  if (!cs->D) {
+    orc_cost_block(m, mk, cs->d, cs->x, cs->X + off[k] * cs->d, C);
+    return;
+  }
+  for (int j = 0; j < mk; ++j)
+    for (int i = 0; i < m; ++i)
+      C[i + (int64_t)j * m] =
+          cs->D[(int64_t)cs->xsym[i] * cs->S + cs->ysym[off[k] + j]];
+}
+
+/*
  * B-ADMM barycenter of one cluster (Sec. 3.2, Algorithm "Centroid Update with
  * B-ADMM"; closed forms Eq. (badmmc0b), (badmmc0), (badmmc1b), (badmmc1);
  * weight rules Eq. (badmmw) = R1 and Eq. (badmmw2) = R2; dual step Eq.
@@ -122,6 +153,7 @@ int orc_ward_merge(int mk, int d, const double* y, const double* wy, int m,
  *    (xplan 0) or Pi1 (xplan 1), with the plan's own row sums as the
  *    denominator (for Pi2 this is exactly N w_i); a row with total mass
  *    below 1e-300 keeps its point; the cost is then recomputed, rho is not.
+ *    A symbolic run (Sec. 5) has no support step.
  *
  * Members are instance indices `mem` into the global ragged arrays
  * (off, X, W).  Plans P1, P2, L are global m x n arrays (see header); only
@@ -133,15 +165,17 @@ int orc_ward_merge(int mk, int d, const double* y, const double* wy, int m,
  * |Pi1_ij - Pi2_ij| (the residual of the splitting constraint Pi1 = Pi2
  * whose multiplier Eq. (badmm2) updates) after iteration n, and *rho_out the
  * rho used.  ftrace and rtrace may be NULL.
- * Returns 0, or -1 on bad arguments.
  */
-int orc_barycenter(int64_t nmem, const int64_t* mem, const int64_t* off, int d,
-                   const double* X, const double* W, int m, double* x,
-                   double* w, const uint8_t* warm, double* P1, double* P2,
-                   double* L, double rho0, int tau, int T, double eps, int rule,
-                   int xplan, double* ftrace, double* rtrace,
-                   double* rho_out) {
-  if (nmem <= 0 || m < 1 || d < 1 || T < 0 || tau < 1) return -1;
+static int badmm_cluster(int64_t nmem, const int64_t* mem, const int64_t* off,
+                         const orc_costsrc* src, const double* W, int m,
+                         double* w, const uint8_t* warm, double* P1,
+                         double* P2, double* L, double rho0, int tau, int T,
+                         double eps, int rule, int xplan, double* ftrace,
+                         double* rtrace, double* rho_out) {
+  if (nmem <= 0 || m < 1 || T < 0 || tau < 1) return -1;
+  const int d = src->d;
+  const double* X = src->X;
+  double* x = src->x;
   /* local cost storage: member q's block starts at coff[q] */
   int64_t* coff = (int64_t*)malloc(sizeof(int64_t) * (size_t)(nmem + 1));
   coff[0] = 0;
@@ -159,11 +193,7 @@ int orc_barycenter(int64_t nmem, const int64_t* mem, const int64_t* off, int d,
 
   /* cost blocks at the initial support */
 #pragma omp parallel for schedule(static)
-  for (int64_t q = 0; q < nmem; ++q) {
-    int64_t k = mem[q];
-    int mk = (int)(off[k + 1] - off[k]);
-    orc_cost_block(m, mk, d, x, X + off[k] * d, C + coff[q]);
-  }
+  for (int64_t q = 0; q < nmem; ++q) member_cost(src, mem[q], off, m, C + coff[q]);
   /* Eq. (rho), read as rho0 times the mean cost */
   double csum = 0.0;
   for (int64_t e = 0; e < coff[nmem]; ++e) csum += C[e];
@@ -268,7 +298,7 @@ int orc_barycenter(int64_t nmem, const int64_t* mem, const int64_t* off, int d,
     }
 
     /* support update, Eq. (updatex), every tau iterations */
-    if ((n + 1) % tau == 0) {
+    if (!src->D && (n + 1) % tau == 0) {
       const double* Pp = (xplan == 1) ? P1 : P2;
       for (int i = 0; i < m; ++i) {
         double den = 0.0;
@@ -288,11 +318,8 @@ int orc_barycenter(int64_t nmem, const int64_t* mem, const int64_t* off, int d,
         free(num);
       }
 #pragma omp parallel for schedule(static)
-      for (int64_t q = 0; q < nmem; ++q) {
-        int64_t k = mem[q];
-        int mk = (int)(off[k + 1] - off[k]);
-        orc_cost_block(m, mk, d, x, X + off[k] * d, C + coff[q]);
-      }
+      for (int64_t q = 0; q < nmem; ++q)
+        member_cost(src, mem[q], off, m, C + coff[q]);
     }
   }
   free(coff);
@@ -304,25 +331,54 @@ int orc_barycenter(int64_t nmem, const int64_t* mem, const int64_t* off, int d,
   return 0;
 }
 
+/* Euclidean barycenter (see badmm_cluster).  Returns 0, or -1 on bad
+ * arguments. */
+int orc_barycenter(int64_t nmem, const int64_t* mem, const int64_t* off, int d,
+                   const double* X, const double* W, int m, double* x,
+                   double* w, const uint8_t* warm, double* P1, double* P2,
+                   double* L, double rho0, int tau, int T, double eps, int rule,
+                   int xplan, double* ftrace, double* rtrace,
+                   double* rho_out) {
+  if (d < 1) return -1;
+  orc_costsrc src = {d, X, x, 0, NULL, NULL, NULL};
+  return badmm_cluster(nmem, mem, off, &src, W, m, w, warm, P1, P2, L, rho0,
+                       tau, T, eps, rule, xplan, ftrace, rtrace, rho_out);
+}
+
+/* Symbolic barycenter (Sec. 5): instance k's support points are the symbols
+ * ysym[off[k] .. off[k+1]), the centroid's the m symbols xsym, the cost the
+ * S x S table D (row: centroid symbol, column: instance symbol); only the
+ * weights w are updated.  Returns 0, or -1 on bad arguments. */
+int orc_barycenter_sym(int64_t nmem, const int64_t* mem, const int64_t* off,
+                       const int32_t* ysym, const double* W, int m,
+                       const int32_t* xsym, int S, const double* D, double* w,
+                       const uint8_t* warm, double* P1, double* P2, double* L,
+                       double rho0, int T, double eps, int rule,
+                       double* ftrace, double* rtrace, double* rho_out) {
+  if (S < 1 || !D) return -1;
+  orc_costsrc src = {0, NULL, NULL, S, D, xsym, ysym};
+  return badmm_cluster(nmem, mem, off, &src, W, m, w, warm, P1, P2, L, rho0,
+                       1, T, eps, rule, 0, ftrace, rtrace, rho_out);
+}
+
 /*
  * B-ADMM for a single transport problem with both marginals fixed: the
  * updates of Eq. (badmmc0b)-(badmmc1) and Eq. (badmm2) with w held at the
  * centroid's weights (no consensus step).  Pi2^0 = w_i w'_j, Lambda = 0,
  * rho = rho0 * mean(C) for this pair.  Returns <C, Pi1> after T >= 1
- * iterations; Pi1, Pi2, Lambda are written to p1, p2, lam when non-NULL
- * (column-major m x mk).  This is the assignment-step distance.
+ * iterations for the cost block C (column-major m x mk); Pi1, Pi2, Lambda
+ * are written to p1, p2, lam when non-NULL (column-major m x mk).  This is
+ * the assignment-step distance.
  */
-double orc_ot(int m, int mk, int d, const double* x, const double* w,
-              const double* y, const double* wy, double rho0, int T,
-              double eps, double* p1, double* p2, double* lam) {
+double orc_ot_cost(int m, int mk, const double* C, const double* w,
+                   const double* wy, double rho0, int T, double eps,
+                   double* p1, double* p2, double* lam) {
   size_t E = (size_t)m * mk;
-  double* C = (double*)malloc(sizeof(double) * E);
   double* A = (double*)malloc(sizeof(double) * E);
   double* B = (double*)malloc(sizeof(double) * E);
   double* P = (double*)malloc(sizeof(double) * E);
   double* L = (double*)malloc(sizeof(double) * E);
   double* r = (double*)malloc(sizeof(double) * (size_t)m);
-  orc_cost_block(m, mk, d, x, y, C);
   double csum = 0.0;
   for (size_t e = 0; e < E; ++e) csum += C[e];
   double rho = rho0 * csum / (double)E;
@@ -362,7 +418,18 @@ double orc_ot(int m, int mk, int d, const double* x, const double* w,
   if (p1) memcpy(p1, A, sizeof(double) * E);
   if (p2) memcpy(p2, P, sizeof(double) * E);
   if (lam) memcpy(lam, L, sizeof(double) * E);
-  free(C); free(A); free(B); free(P); free(L); free(r);
+  free(A); free(B); free(P); free(L); free(r);
+  return v;
+}
+
+/* orc_ot_cost on the squared-Euclidean cost between x (m x d) and y. */
+double orc_ot(int m, int mk, int d, const double* x, const double* w,
+              const double* y, const double* wy, double rho0, int T,
+              double eps, double* p1, double* p2, double* lam) {
+  double* C = (double*)malloc(sizeof(double) * (size_t)m * mk);
+  orc_cost_block(m, mk, d, x, y, C);
+  double v = orc_ot_cost(m, mk, C, w, wy, rho0, T, eps, p1, p2, lam);
+  free(C);
   return v;
 }
 
@@ -388,6 +455,38 @@ void orc_assign(int64_t N, const int64_t* off, int d, const double* X,
       if (dist) dist[k * K + c] = v;
       if (v < bv) { bv = v; bc = c; }
     }
+    labels[k] = bc;
+    if (best) best[k] = bv;
+  }
+}
+
+/*
+ * Assignment step over symbolic supports (Sec. 5): as orc_assign with the
+ * cost block of (centroid c, instance k) gathered from the S x S table D,
+ * C_ij = D[xsym[c*m + i] * S + ysym[off[k] + j]].
+ */
+void orc_assign_sym(int64_t N, const int64_t* off, const int32_t* ysym,
+                    const double* W, int K, int m, const int32_t* xsym,
+                    const double* Wc, int S, const double* D, double rho0,
+                    int T, double eps, int32_t* labels, double* best,
+                    double* dist) {
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t k = 0; k < N; ++k) {
+    int mk = (int)(off[k + 1] - off[k]);
+    double* C = (double*)malloc(sizeof(double) * (size_t)m * mk);
+    double bv = INFINITY;
+    int bc = 0;
+    for (int c = 0; c < K; ++c) {
+      for (int j = 0; j < mk; ++j)
+        for (int i = 0; i < m; ++i)
+          C[i + (int64_t)j * m] =
+              D[(int64_t)xsym[(int64_t)c * m + i] * S + ysym[off[k] + j]];
+      double v = orc_ot_cost(m, mk, C, Wc + (int64_t)c * m, W + off[k], rho0,
+                             T, eps, NULL, NULL, NULL);
+      if (dist) dist[k * K + c] = v;
+      if (v < bv) { bv = v; bc = c; }
+    }
+    free(C);
     labels[k] = bc;
     if (best) best[k] = bv;
   }

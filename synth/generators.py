@@ -34,6 +34,8 @@ __all__ = [
     "round_to_bf16",
     "warmstart_clusters",
     "deepsets_init_params",
+    "protein_symbol_workload",
+    "symbol_init_centroids",
 ]
 
 
@@ -141,6 +143,108 @@ def topic_sphere_workload(seed, N, d=64, n_topic=512, n_class=64, noise=0.3,
             "W": W, "classes": classes, "d": d}
 
 
+def protein_symbol_workload(seed, N, gram=1, n_family=10, len_lo=80,
+                            len_hi=400, alpha=0.5, n_amino=20, emb_dim=4,
+                            mk_cap=64):
+    """n-gram histograms of synthetic protein sequences over a symbol set
+    (stand-in for the paper's protein-sequence data: symbolic supports with
+    a given symbol-to-symbol dissimilarity, Sec. 5).
+
+    Each sequence belongs to one of n_family families; a family is a
+    first-order Markov chain over the n_amino residues (initial
+    distribution and transition rows Dirichlet(alpha)).  Sequence lengths
+    are uniform in [len_lo, len_hi].  Symbols: gram = 1, the residues
+    (S = n_amino); gram = 3, the tripeptides a n_amino^2 + b n_amino + c
+    (S = n_amino^3).  An instance is the set of distinct n-grams of its
+    sequence with their relative counts, cut to the mk_cap most frequent
+    (ties to the smaller symbol) and renormalised.  The dissimilarity table:
+    residues get random embeddings e_a ~ N(0, I_emb_dim) and
+    D1[a, b] = sum_t (e_a,t - e_b,t)^2 (direct differences); for 3-grams
+    D[(a,b,c), (x,y,z)] = D1[a,x] + D1[b,y] + D1[c,z].
+
+    Draw order: 1. embeddings, 2. family initial distributions, 3. family
+    transition rows, 4. per-sequence family, 5. per-sequence length,
+    6. residues, position by position for all sequences.
+    Returns offsets, sym (int32, n), W, D (S x S), classes, S."""
+    rng = _rng(seed)
+    A = n_amino
+    emb = rng.standard_normal((A, emb_dim))
+    init = rng.dirichlet(np.full(A, alpha), size=n_family)
+    trans = rng.dirichlet(np.full(A, alpha), size=(n_family, A))
+    fam = rng.integers(0, n_family, size=N)
+    lens = rng.integers(len_lo, len_hi + 1, size=N)
+    L = int(lens.max())
+    seq = np.zeros((N, L), dtype=np.int64)
+    cinit = np.cumsum(init, axis=1)
+    ctrans = np.cumsum(trans, axis=2)
+    u = rng.random(N)
+    seq[:, 0] = np.minimum((u[:, None] > cinit[fam]).sum(1), A - 1)
+    for t in range(1, L):
+        u = rng.random(N)
+        rows = ctrans[fam, seq[:, t - 1]]
+        seq[:, t] = np.minimum((u[:, None] > rows).sum(1), A - 1)
+    D1 = np.zeros((A, A))
+    for a in range(A):
+        for b in range(A):
+            acc = 0.0
+            for t in range(emb_dim):
+                df = emb[a, t] - emb[b, t]
+                acc += df * df
+            D1[a, b] = acc
+    if gram == 1:
+        S = A
+        D = D1
+    elif gram == 3:
+        S = A ** 3
+        idx = np.arange(S)
+        a, b, c = idx // (A * A), (idx // A) % A, idx % A
+        D = D1[a][:, a] + D1[b][:, b] + D1[c][:, c]
+    else:
+        raise ValueError("gram must be 1 or 3")
+    syms, ws, sizes = [], [], []
+    for k in range(N):
+        s_ = seq[k, :lens[k]]
+        if gram == 3:
+            s_ = s_[:-2] * (A * A) + s_[1:-1] * A + s_[2:]
+        vals, cnt = np.unique(s_, return_counts=True)
+        order = np.lexsort((vals, -cnt))[:mk_cap]
+        vals, cnt = vals[order], cnt[order].astype(np.float64)
+        syms.append(vals)
+        ws.append(cnt / cnt.sum())
+        sizes.append(len(vals))
+    offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    return {"offsets": offsets,
+            "sym": np.concatenate(syms).astype(np.int32),
+            "W": np.concatenate(ws), "D": np.ascontiguousarray(D),
+            "classes": fam.astype(np.int64), "S": S}
+
+
+def symbol_init_centroids(wl, labels, K, m):
+    """Initial symbolic centroids: for cluster c the m symbols carrying the
+    most weight summed over its members (ties to the smaller symbol;
+    clusters with fewer distinct symbols are filled up in the same order
+    over all instances), with uniform weights 1/m.  Returns csym (K x m,
+    int32) and Wc (K x m)."""
+    off, sym, W = wl["offsets"], wl["sym"], wl["W"]
+    S = wl["S"]
+    inst = np.repeat(np.arange(len(off) - 1), np.diff(off))
+    tot_all = np.bincount(sym, weights=W, minlength=S)
+    rank_all = np.lexsort((np.arange(S), -tot_all))
+    csym = np.zeros((K, m), dtype=np.int32)
+    for c in range(K):
+        sel = labels[inst] == c
+        tot = np.bincount(sym[sel], weights=W[sel], minlength=S)
+        order = np.lexsort((np.arange(S), -tot))
+        chosen = [int(v) for v in order if tot[v] > 0][:m]
+        for v in rank_all:
+            if len(chosen) == m:
+                break
+            if int(v) not in chosen:
+                chosen.append(int(v))
+        csym[c] = chosen
+    return csym, np.full((K, m), 1.0 / m)
+
+
 # The paper's workloads as parameter sets.  N can be overridden to get a
 # smaller instance of the same distribution (tests use this).
 WORKLOADS = {
@@ -160,6 +264,13 @@ WORKLOADS = {
                                   mk_hi=32, n_comp=1024, n_class=256,
                                   sigma=0.1, alpha=1.0, K=256, m=16, T=50,
                                   rounds=5, seed=4000),
+    # protein-sequence-like symbolic supports (Sec. 5): amino-acid
+    # histograms (S = 20, m = 20) and tripeptide histograms (S = 8000,
+    # m = 32), N = 10,742 sequences, K = 10 families
+    "protein_g1_n10742_k10": dict(kind="protein", N=10742, gram=1, K=10,
+                                  m=20, T=100, rounds=5, seed=6000),
+    "protein_g3_n10742_k10": dict(kind="protein", N=10742, gram=3, K=10,
+                                  m=32, T=100, rounds=5, seed=6100),
 }
 
 
@@ -175,6 +286,8 @@ def make_workload(name, seed=None, N=None, replicate=0):
         wl = gaussian_mixture_workload(seed, N, p["d"], p["mk_lo"], p["mk_hi"],
                                        p["n_comp"], p["n_class"], p["sigma"],
                                        p["alpha"])
+    elif p["kind"] == "protein":
+        wl = protein_symbol_workload(seed, N, gram=p["gram"])
     else:
         wl = topic_sphere_workload(seed, N, d=p["d"])
     wl.update(K=p["K"], m=p["m"], T=p["T"], rounds=p["rounds"], name=name,
