@@ -43,7 +43,8 @@ def log(msg):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("d2_kernels.hpp", "d2_api.hip"):
+    # the device code of the plan-update and auxiliary kernels
+    for f in ("d2_kernels.hpp", "d2_kinst.hpp"):
         with open(os.path.join(ROOT, "paper_1510_00012_amd", "csrc", f),
                   "rb") as fh:
             h.update(fh.read())

@@ -129,6 +129,33 @@ d2_status d2_load_instances_device(d2_ctx* ctx, int64_t N, int32_t d,
                                    const int64_t* offsets, const void* dX,
                                    const void* dW);
 
+/* Load N instances over a symbolic support set (Sec. 5: the support
+ * points are symbols of a finite set, e.g. amino acids or their n-grams,
+ * with a given symbol-to-symbol dissimilarity; the support vectors are then
+ * never updated).  offsets as in d2_load_instances; sym (n) holds each
+ * support point's symbol in [0, S); W (n) the weights (checked and
+ * renormalised as in d2_load_instances); D (S x S, row-major, finite,
+ * >= 0, 1 <= S <= 16384) the cost of centroid symbol a against instance
+ * symbol b at D[a * S + b] (it need not be symmetric).  All copied.  The
+ * context then reports d = 1; its centroids are set with
+ * d2_centroids_set_symbolic, d2_centroids_get returns each centroid
+ * point's symbol (as a double) in Xc, and d2_barycenter updates the
+ * weights only (the support step is skipped whatever fixed_support says).
+ * Not available on such a context (D2_EINVAL): d2_centroids_set,
+ * d2_centroids_init, d2_support_update, d2_objective_feasible, the
+ * learned warm start. */
+d2_status d2_load_instances_symbolic(d2_ctx* ctx, int64_t N,
+                                     const int64_t* offsets,
+                                     const int32_t* sym, const double* W,
+                                     int32_t S, const double* D);
+
+/* Centroids of a symbolic context: csym (K x m) are the support symbols of
+ * each centroid, in [0, S); Wc (K x m) rows in the simplex as in
+ * d2_centroids_set (whose plan-cache rule applies).  New symbols drop the
+ * assignment's cross-round bounds. */
+d2_status d2_centroids_set_symbolic(d2_ctx* ctx, int32_t K, int32_t m,
+                                    const int32_t* csym, const double* Wc);
+
 /* Set the K centroids: Xc is K x m x d, Wc is K x m (rows in the simplex,
  * |sum - 1| <= 1e-6, renormalised).  Requires loaded instances.  With K and
  * m unchanged the plan cache of the last d2_barycenter is kept, so that a
@@ -210,6 +237,33 @@ typedef void (*d2_round_cb)(const d2_round_info* info, void* user);
  * warm start (Sec. 5).  cb may be NULL. */
 d2_status d2_cluster(d2_ctx* ctx, int32_t rounds, const d2_badmm_params* bp,
                      const d2_ot_params* op, d2_round_cb cb, void* user);
+
+/* Multi-modal instances (Sec. 5: an instance is an array of distributions,
+ * e.g. a protein's amino-acid and tripeptide histograms).  Modality i of
+ * every instance lives in context ctxs[i] (its own supports, d, m, m_k,
+ * vector or symbolic); all contexts are on one device with the same N and
+ * K, and instance k of each is the same object.  The assignment distance
+ * of (instance, centroid) is the sum over modalities of the B-ADMM
+ * transport values of `p`; labels = argmin, ties to the lowest centroid.
+ * Every pair of every modality is evaluated (no pruning); the per-pair
+ * distances are summed in modality order in an N x K double buffer of
+ * ctxs[0].  The labels (and the minimal summed distances) are written to
+ * every context; labels_out (N), dist_out (N) and n_changed (against the
+ * previous labels of ctxs[0]) may be NULL.  Errors are reported through
+ * ctxs[0]. */
+d2_status d2_assign_multi(int32_t n_modal, d2_ctx* const* ctxs,
+                          const d2_ot_params* p, int32_t* labels_out,
+                          double* dist_out, int64_t* n_changed);
+
+/* D2-clustering of multi-modal instances: `rounds` rounds of
+ * d2_assign_multi followed by d2_barycenter on every modality's context
+ * (the modalities' centroids are updated separately, Sec. 5; product start
+ * in a first round without a plan cache, else bp->init).  The callback
+ * gets the summed barycenter time of the modalities. */
+d2_status d2_cluster_multi(int32_t n_modal, d2_ctx* const* ctxs,
+                           int32_t rounds, const d2_badmm_params* bp,
+                           const d2_ot_params* op, d2_round_cb cb,
+                           void* user);
 
 /* Objective trace of the last d2_barycenter: trace[n*K + c] =
  * (1/N_c) sum_k <C^(k), Pi1^(k)> of iteration n (0 for empty clusters);

@@ -12,6 +12,7 @@
 #include "../../include/d2.h"
 #include "d2_ctx.hpp"
 #include "d2_kernels.hpp"
+#include "d2_lists.hpp"
 
 static const char* kKindNames[kKinds] = {"rho_cost", "init_a", "iter_ba",
                                          "b_final", "xnum_only", "assign",
@@ -144,6 +145,8 @@ void free_bounds(d2_ctx* c) {
 void free_centroids(d2_ctx* c) {
   drop_graph(c);
   free_bounds(c);
+  dfree(c->d_csym);
+  c->h_csym.clear();
   dfree(c->d_cmu);
   dfree(c->d_crad);
   dfree(c->d_xct);
@@ -166,6 +169,25 @@ void free_instances(d2_ctx* c) {
   }
   dfree(c->d_X);
   dfree(c->d_W);
+  dfree(c->d_isym);
+  dfree(c->d_D);
+  c->sym = false;
+  c->S = 0;
+  dfree(c->d_cache_labels);
+  dfree(c->d_prev_labels);
+  dfree(c->d_nchg);
+  dfree(c->d_bkt);
+  c->bkt_MP = 0;
+  c->bkt_pct = -1;
+  dfree(c->d_tcnt);
+  dfree(c->d_tsum);
+  c->tcnt_cap = 0;
+  dfree(c->d_keys);
+  c->keys_cap = 0;
+  dfree(c->d_dall);
+  c->dall_cap = 0;
+  c->hlab_ok = c->hcache_ok = true;
+  c->cache_gen = ~0ull;
   dfree(c->d_labels);
   dfree(c->d_best);
   dfree(c->d_pairs);
@@ -343,6 +365,158 @@ int slot_class(const d2_ctx* c, int64_t k) {
   return ilog2(std::max(1, (mk + cps - 1) / cps));
 }
 
+// Bucket launch capacities that hold for any labels: bucket b never has
+// more than ceil(instances of b / chunk) + K chunks (one partial chunk per
+// cluster), and the chunk total never exceeds ceil(N / chunk) + 6 K.  A
+// captured launch sequence therefore stays valid across rounds.  Also
+// (re)allocates the list buffers for those capacities.
+d2_status list_capacities(d2_ctx* c, int nbk, const std::vector<int>& bR,
+                          const int64_t* inst_b) {
+  const int K = c->K;
+  const int64_t N = c->N;
+  const int CH = c->chunk_inst;
+  const int cap = (int)((N + CH - 1) / CH) + K * 6;
+  if (cap > c->nch_cap || !c->d_work) {
+    free_lists(c);
+    d2_status s;
+    c->nch_cap = cap;
+    if ((s = dalloc(c, (void**)&c->d_work, sizeof(int32_t) * N))) return s;
+    if ((s = dalloc(c, (void**)&c->d_chunks, sizeof(d2k::Chunk) * cap)))
+      return s;
+    if ((s = dalloc(c, (void**)&c->d_ctab, sizeof(int2) * K))) return s;
+    if ((s = dalloc(c, (void**)&c->d_ninv, sizeof(double) * K))) return s;
+    if ((s = dalloc(c, (void**)&c->d_cinv, sizeof(double) * K))) return s;
+    if ((s = dalloc(c, (void**)&c->d_warm, N))) return s;
+    if ((s = dalloc(c, (void**)&c->d_part,
+                    sizeof(double) * 2 * cap * (c->MP + 2))))
+      return s;
+    if ((s = dalloc(c, (void**)&c->d_nch, sizeof(int)))) return s;
+    if ((s = dalloc(c, (void**)&c->d_bcnt, sizeof(int) * 6))) return s;
+    if ((s = dalloc(c, (void**)&c->d_partx,
+                    sizeof(double) * 2 * cap * c->MP * (c->d + 1))))
+      return s;
+  }
+  int want[6] = {0, 0, 0, 0, 0, 0};
+  for (int b = 0; b < nbk; ++b)
+    want[b] = (int)((inst_b[b] + CH - 1) / CH) + K;
+  bool same = nbk == c->nbk;
+  for (int b = 0; same && b < 6; ++b)
+    same = (b < nbk ? bR[b] : 0) == c->bk_R[b] && want[b] == c->bk_cap[b];
+  if (!same) {
+    drop_graph(c);
+    int total = 0;
+    for (int b = 0; b < 6; ++b) {
+      c->bk_R[b] = b < nbk ? bR[b] : 0;
+      c->bk_cap[b] = want[b];
+      c->bk_off[b] = total;
+      total += want[b];
+    }
+    c->nbk = nbk;
+    if (total > c->blist_cap) {
+      dfree(c->d_blist);
+      d2_status s = dalloc(c, (void**)&c->d_blist, sizeof(int32_t) * total);
+      if (s) return s;
+      c->blist_cap = total;
+    }
+  }
+  return D2_OK;
+}
+
+// The work list built on the device from the device labels (d2_lists.hpp):
+// the same lists as the host construction below, entry for entry.
+d2_status build_lists_device(d2_ctx* c, bool warm_start, int nbk,
+                             const std::vector<int>& bR, const int* bidx_of) {
+  const int K = c->K;
+  const int64_t N = c->N;
+  const int G = K * nbk;
+  d2_status s;
+  // per-instance bucket, for this pad(m) and merge threshold
+  if (c->bkt_MP != c->MP || c->bkt_pct != c->bucket_min_pct || !c->d_bkt) {
+    std::vector<uint8_t> hb(N);
+    for (int64_t k = 0; k < N; ++k) hb[k] = (uint8_t)bidx_of[c->h_cls[k]];
+    if (!c->d_bkt && (s = dalloc(c, (void**)&c->d_bkt, N))) return s;
+    HIPCHK(c, hipMemcpy(c->d_bkt, hb.data(), N, hipMemcpyHostToDevice));
+    c->bkt_MP = c->MP;
+    c->bkt_pct = c->bucket_min_pct;
+  }
+  int64_t inst_b[6] = {0, 0, 0, 0, 0, 0};
+  for (int q = 0; q < 6; ++q) inst_b[bidx_of[q]] += c->cls_cnt[q];
+  if ((s = list_capacities(c, nbk, bR, inst_b))) return s;
+  const int ntiles = (int)((N + d2l::kTile - 1) / d2l::kTile);
+  if ((int64_t)ntiles * G > c->tcnt_cap) {
+    dfree(c->d_tcnt);
+    dfree(c->d_tsum);
+    c->tcnt_cap = 0;
+    const size_t b = sizeof(int32_t) * (size_t)ntiles * G;
+    if ((s = dalloc(c, (void**)&c->d_tcnt, b))) return s;
+    if ((s = dalloc(c, (void**)&c->d_tsum, b))) return s;
+    c->tcnt_cap = (int64_t)ntiles * G;
+  }
+  if (G > c->keys_cap) {
+    dfree(c->d_keys);
+    c->keys_cap = 0;
+    if ((s = dalloc(c, (void**)&c->d_keys, sizeof(int64_t) * 5 * G)))
+      return s;
+    c->keys_cap = G;
+  }
+  int64_t* kcnt = c->d_keys;
+  int64_t* ksum = kcnt + G;
+  int64_t* kstart = ksum + G;
+  int64_t* kchunk = kstart + G;
+  int64_t* kbofs = kchunk + G;
+  const bool any_warm = warm_start && c->have_cache;
+  hipLaunchKernelGGL(d2l::k_list_count, dim3(ntiles), dim3(64), 0, c->stream,
+                     c->d_labels, c->d_bkt, c->d_off, N, nbk, G, c->d_tcnt,
+                     c->d_tsum, any_warm ? c->d_cache_labels : nullptr,
+                     c->d_warm);
+  HIPCHK(c, hipGetLastError());
+  hipLaunchKernelGGL(d2l::k_list_tiles, dim3((G + 255) / 256), dim3(256), 0,
+                     c->stream, c->d_tcnt, c->d_tsum, ntiles, G, kcnt, ksum);
+  HIPCHK(c, hipGetLastError());
+  d2l::LayoutArgs la;
+  la.kcnt = kcnt;
+  la.ksum = ksum;
+  la.kstart = kstart;
+  la.kchunk = kchunk;
+  la.kbofs = kbofs;
+  la.ctab = c->d_ctab;
+  la.ninv = c->d_ninv;
+  la.cinv = c->d_cinv;
+  la.nch = c->d_nch;
+  la.bcnt = c->d_bcnt;
+  la.K = K;
+  la.nbk = nbk;
+  la.G = G;
+  la.chunk = c->chunk_inst;
+  la.m = c->m;
+  hipLaunchKernelGGL(d2l::k_list_layout, dim3(1), dim3(1024), 0, c->stream,
+                     la);
+  HIPCHK(c, hipGetLastError());
+  hipLaunchKernelGGL(d2l::k_list_scatter, dim3(ntiles), dim3(64), 0,
+                     c->stream, c->d_labels, c->d_bkt, N, nbk, G, c->d_tcnt,
+                     kstart, c->d_work);
+  HIPCHK(c, hipGetLastError());
+  d2l::ChunkArgs ca;
+  ca.kcnt = kcnt;
+  ca.kstart = kstart;
+  ca.kchunk = kchunk;
+  ca.kbofs = kbofs;
+  ca.nch = c->d_nch;
+  ca.chunks = c->d_chunks;
+  ca.blist = c->d_blist;
+  for (int b = 0; b < 6; ++b) ca.boff[b] = c->bk_off[b];
+  ca.G = G;
+  ca.nbk = nbk;
+  ca.chunk = c->chunk_inst;
+  ca.cap = c->nch_cap;
+  hipLaunchKernelGGL(d2l::k_list_chunks, dim3((c->nch_cap + 255) / 256),
+                     dim3(256), 0, c->stream, ca);
+  HIPCHK(c, hipGetLastError());
+  c->host_ctab = false;
+  c->lists_valid = true;
+  return D2_OK;
+}
+
 // Cluster-sorted work list, chunks and per-cluster tables for the labels.
 // Inside a cluster, instances are ordered by slot bucket and every chunk
 // holds one bucket, so a cluster's chunks stay contiguous (the per-cluster
@@ -354,10 +528,14 @@ d2_status build_lists(d2_ctx* c, bool warm_start) {
   if (c->cls_MP != c->MP) {
     // slot class of every instance and the plan entries per class
     c->h_cls.resize(N);
-    for (int q = 0; q < 6; ++q) c->cls_ent[q] = 0.0;
+    for (int q = 0; q < 6; ++q) {
+      c->cls_ent[q] = 0.0;
+      c->cls_cnt[q] = 0;
+    }
     for (int64_t k = 0; k < N; ++k) {
       c->h_cls[k] = (uint8_t)slot_class(c, k);
       c->cls_ent[c->h_cls[k]] += (double)(c->h_off[k + 1] - c->h_off[k]);
+      c->cls_cnt[c->h_cls[k]]++;
     }
     c->cls_MP = c->MP;
   }
@@ -386,6 +564,11 @@ d2_status build_lists(d2_ctx* c, bool warm_start) {
   for (int q = 0; q < 6; ++q)
     for (int b = 0; b < nbk; ++b)
       if (bmap[q] >= 0 && (1 << bmap[q]) == bR[b]) bidx_of[q] = b;
+  if ((int64_t)K * nbk <= d2l::kMaxKeys)
+    return build_lists_device(c, warm_start, nbk, bR, bidx_of);
+  // many clusters: the list is built on the host from the host labels
+  HIPCHK(c, c->sync_labels());
+  if (warm_start && c->have_cache) HIPCHK(c, c->sync_cache_labels());
   // one pass: (cluster, bucket) key per instance and the counts
   std::vector<int64_t> cnt(K, 0), ncols(K, 0);
   std::vector<int64_t> kcnt((size_t)K * nbk, 0);
@@ -435,48 +618,11 @@ d2_status build_lists(d2_ctx* c, bool warm_start) {
     }
   }
   c->nchunks = (int)chunks.size();
-  int cap = (int)((N + CH - 1) / CH) + K * 6;
-  if (cap > c->nch_cap || !c->d_work) {
-    free_lists(c);
-    d2_status s;
-    c->nch_cap = cap;
-    if ((s = dalloc(c, (void**)&c->d_work, sizeof(int32_t) * N))) return s;
-    if ((s = dalloc(c, (void**)&c->d_chunks, sizeof(d2k::Chunk) * cap)))
-      return s;
-    if ((s = dalloc(c, (void**)&c->d_ctab, sizeof(int2) * K))) return s;
-    if ((s = dalloc(c, (void**)&c->d_ninv, sizeof(double) * K))) return s;
-    if ((s = dalloc(c, (void**)&c->d_cinv, sizeof(double) * K))) return s;
-    if ((s = dalloc(c, (void**)&c->d_warm, N))) return s;
-    if ((s = dalloc(c, (void**)&c->d_part,
-                    sizeof(double) * 2 * cap * (c->MP + 2))))
-      return s;
-    if ((s = dalloc(c, (void**)&c->d_nch, sizeof(int)))) return s;
-    if ((s = dalloc(c, (void**)&c->d_bcnt, sizeof(int) * 6))) return s;
-    if ((s = dalloc(c, (void**)&c->d_partx,
-                    sizeof(double) * 2 * cap * c->MP * (c->d + 1))))
-      return s;
-  }
-  // bucket grids: kept while the bucket set is unchanged and the counts
-  // fit (a captured launch sequence stays valid), else resized with slack
-  bool same = nbk == c->nbk;
-  for (int b = 0; same && b < nbk; ++b)
-    same = bR[b] == c->bk_R[b] && (int)blists[b].size() <= c->bk_cap[b];
-  if (!same) {
-    drop_graph(c);
-    int total = 0;
-    for (int b = 0; b < 6; ++b) {
-      c->bk_R[b] = b < nbk ? bR[b] : 0;
-      c->bk_cap[b] = b < nbk ? (int)(blists[b].size() * 5 / 4) + 8 : 0;
-      c->bk_off[b] = total;
-      total += c->bk_cap[b];
-    }
-    c->nbk = nbk;
-    if (total > c->blist_cap) {
-      dfree(c->d_blist);
-      d2_status s = dalloc(c, (void**)&c->d_blist, sizeof(int32_t) * total);
-      if (s) return s;
-      c->blist_cap = total;
-    }
+  {
+    int64_t inst_b[6] = {0, 0, 0, 0, 0, 0};
+    for (int q = 0; q < 6; ++q) inst_b[bidx_of[q]] += c->cls_cnt[q];
+    d2_status s = list_capacities(c, nbk, bR, inst_b);
+    if (s) return s;
   }
   for (int b = 0; b < nbk; ++b) c->bk_cnt[b] = (int)blists[b].size();
   for (int b = nbk; b < 6; ++b) c->bk_cnt[b] = 0;
@@ -504,6 +650,7 @@ d2_status build_lists(d2_ctx* c, bool warm_start) {
                      sizeof(int32_t) * blists[b].size()});
   d2_status su = stage_uploads(c, ups);
   if (su) return su;
+  c->host_ctab = true;
   c->lists_valid = true;
   return D2_OK;
 }
@@ -526,7 +673,7 @@ d2_status ensure_plans(d2_ctx* c) {
   if ((s = dalloc(c, &c->d_P1, bytes))) return s;
   if ((s = dalloc(c, &c->d_P2, bytes))) return s;
   if ((s = dalloc(c, &c->d_L, bytes))) return s;
-  c->onfly = c->d <= 4;
+  c->onfly = c->d <= 4 && !c->sym;
   if (!c->onfly && (s = dalloc(c, &c->d_C, bytes))) return s;
   return D2_OK;
 }
@@ -620,6 +767,10 @@ d2k::Args<T> make_args(d2_ctx* c, const d2_badmm_params* p) {
   a.xs = c->xs;
   a.rule = p ? p->rule : 1;
   a.ps = c->MP + 2;
+  a.dsym = c->sym ? (const T*)c->d_D : nullptr;
+  a.isym = c->d_isym;
+  a.csym = c->d_csym;
+  a.S = c->S;
   return a;
 }
 
@@ -671,7 +822,7 @@ d2_status launch_aux(d2_ctx* c, const d2k::Args<T>& a0, int mode, int& nl) {
   // large d: the cost pass reads the centroid support from LDS
   const size_t stage = (size_t)c->MP * (c->xs + 4) * sizeof(T);
   a.xstage = 0;
-  if (mode == d2k::kRho && !c->onfly && stage <= 64 * 1024) {
+  if (mode == d2k::kRho && !c->onfly && !c->sym && stage <= 64 * 1024) {
     a.xstage = 1;
     shm = stage;
   }
@@ -914,10 +1065,22 @@ d2_status run_barycenter(d2_ctx* c, const d2_badmm_params* p,
                                 "(centroids restored)");
   }
   c->trace_rows = T_;
-  c->h_cache_labels = c->h_labels;
+  // the labels of this update are those of the cached plans
+  HIPCHK(c, hipMemcpyAsync(c->d_cache_labels, c->d_labels,
+                           sizeof(int32_t) * c->N, hipMemcpyDeviceToDevice,
+                           c->stream));
+  c->cache_gen = c->label_gen;
+  c->hcache_ok = c->hlab_ok;
+  if (c->hlab_ok) c->h_cache_labels = c->h_labels;
   c->have_cache = true;
   if (st) {
     st->iters = T_;
+    if (!c->host_ctab) {
+      c->h_ctab.resize(K);
+      HIPCHK(c, hipMemcpy(c->h_ctab.data(), c->d_ctab, sizeof(int2) * K,
+                          hipMemcpyDeviceToHost));
+      c->host_ctab = true;
+    }
     int ne = 0;
     for (int q = 0; q < K; ++q) ne += c->h_ctab[q].y == 0;
     st->n_empty = ne;
@@ -974,11 +1137,13 @@ bool ensure_bounds(d2_ctx* c) {
 }
 
 template <typename T>
-d2_status run_assign(d2_ctx* c, const d2_ot_params* p, float* ms_out) {
+d2_status run_assign(d2_ctx* c, const d2_ot_params* p, float* ms_out,
+                     double* dall = nullptr) {
   const auto& kt = kern<T>();
   auto fn = kt.asg[ilog2(c->MP) - 3][ilog2(c->R)];
   if (!fn) return c->fail(D2_EINVAL, "no kernel for this tile shape");
-  d2k::AssignArgs<T> a;
+  d2k::AssignArgs<T> a{};
+  a.dall = dall;
   a.off = c->d_off;
   a.X = (const T*)c->d_X;
   a.W = (const T*)c->d_W;
@@ -996,6 +1161,10 @@ d2_status run_assign(d2_ctx* c, const d2_ot_params* p, float* ms_out) {
   }
   a.lbs = bounds ? c->d_lbs : nullptr;
   a.dlt = c->d_dlt;
+  a.dsym = c->sym ? (const T*)c->d_D : nullptr;
+  a.isym = c->d_isym;
+  a.csym = c->d_csym;
+  a.S = c->S;
   a.lbs_in = bounds && c->lbs_valid ? 1 : 0;
   a.cmu = (const T*)c->d_cmu;
   a.crad = (const T*)c->d_crad;
@@ -1095,6 +1264,41 @@ d2_status run_assign(d2_ctx* c, const d2_ot_params* p, float* ms_out) {
   if (ms_out) *ms_out = ms;
   c->last_pairs = c->N * (int64_t)c->K;
   return D2_OK;
+}
+
+// Number of instances whose label differs from the previous one (integer
+// sums, so the count does not depend on the order of the atomic adds).
+__global__ void __launch_bounds__(256)
+    k_count_changes(const int32_t* __restrict__ a,
+                    const int32_t* __restrict__ b, int64_t N,
+                    int64_t* __restrict__ out) {
+  int64_t n = 0;
+  const int64_t st = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < N;
+       k += st)
+    n += a[k] != b[k];
+  for (int o = 32; o > 0; o >>= 1) n += __shfl_xor(n, o);
+  if ((threadIdx.x & 63) == 0 && n) atomicAdd((unsigned long long*)out,
+                                              (unsigned long long)n);
+}
+
+// Multi-modal assignment (Sec. 5): label = argmin over centroids of the
+// summed per-modality distances dall (N x K), ties to the lowest index.
+__global__ void __launch_bounds__(256)
+    k_argmin_rows(const double* __restrict__ dall, int64_t N, int K,
+                  int32_t* __restrict__ labels, double* __restrict__ best) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= N) return;
+  const double* r = dall + k * K;
+  int bc = 0;
+  double bv = r[0];
+  for (int c = 1; c < K; ++c)
+    if (r[c] < bv) {
+      bv = r[c];
+      bc = c;
+    }
+  labels[k] = bc;
+  best[k] = bv;
 }
 
 // Device-copy probe: each thread moves 4 x 16 bytes per step (all four
@@ -1238,12 +1442,18 @@ d2_status adopt_offsets(d2_ctx* c, int64_t N, int32_t d,
   d2_status s;
   if ((s = dalloc(c, (void**)&c->d_off, sizeof(int64_t) * (N + 1)))) return s;
   if ((s = dalloc(c, (void**)&c->d_labels, sizeof(int32_t) * N))) return s;
+  if ((s = dalloc(c, (void**)&c->d_cache_labels, sizeof(int32_t) * N)))
+    return s;
+  if ((s = dalloc(c, (void**)&c->d_prev_labels, sizeof(int32_t) * N)))
+    return s;
+  if ((s = dalloc(c, (void**)&c->d_nchg, sizeof(int64_t)))) return s;
   if ((s = dalloc(c, (void**)&c->d_best, sizeof(double) * N))) return s;
   if ((s = dalloc(c, (void**)&c->d_pairs, 2 * sizeof(int32_t) * N)))
     return s;
   HIPCHK(c, hipMemcpy(c->d_off, offsets, sizeof(int64_t) * (N + 1),
                       hipMemcpyHostToDevice));
   c->h_labels.assign(N, 0);
+  c->hlab_ok = true;
   ++c->label_gen;
   return D2_OK;
 }
@@ -1305,24 +1515,27 @@ d2_status instance_hash(d2_ctx* c, uint64_t* out) {
     return D2_OK;
   }
   unsigned long long* d = nullptr;
-  d2_status s = dalloc(c, (void**)&d, sizeof(unsigned long long) * 3);
-  if (s) return s;
-  const void* src[3] = {c->d_off, c->d_X, c->d_W};
-  const int64_t words[3] = {2 * (c->N + 1),
+  // symbolic instances: also their symbols and the symbol table
+  const void* src[5] = {c->d_off, c->d_X, c->d_W, c->d_isym, c->d_D};
+  const int64_t words[5] = {2 * (c->N + 1),
                             (int64_t)(c->esz() / 4) * c->n * c->xs,
-                            (int64_t)(c->esz() / 4) * c->n};
+                            (int64_t)(c->esz() / 4) * c->n, c->n,
+                            (int64_t)(c->esz() / 4) * c->S * c->S};
+  const int nsrc = c->sym ? 5 : 3;
+  d2_status s0 = dalloc(c, (void**)&d, sizeof(unsigned long long) * 5);
+  if (s0) return s0;
   d2_status st = D2_OK;
-  if (hipMemsetAsync(d, 0, sizeof(unsigned long long) * 3, c->stream) !=
+  if (hipMemsetAsync(d, 0, sizeof(unsigned long long) * 5, c->stream) !=
       hipSuccess)
     st = c->fail(D2_EDEVICE, "hipMemsetAsync");
-  for (int q = 0; q < 3 && !st; ++q) {
+  for (int q = 0; q < nsrc && !st; ++q) {
     hipLaunchKernelGGL(k_fingerprint, dim3(1024), dim3(256), 0, c->stream,
                        (const uint32_t*)src[q], words[q],
                        (unsigned long long)(q + 1), d + q);
     if (hipGetLastError() != hipSuccess)
       st = c->fail(D2_EDEVICE, "k_fingerprint launch");
   }
-  unsigned long long h[3] = {0, 0, 0};
+  unsigned long long h[5] = {0, 0, 0, 0, 0};
   if (!st && hipMemcpyAsync(h, d, sizeof(h), hipMemcpyDeviceToHost,
                             c->stream) != hipSuccess)
     st = c->fail(D2_EDEVICE, "hipMemcpyAsync");
@@ -1330,7 +1543,8 @@ d2_status instance_hash(d2_ctx* c, uint64_t* out) {
     st = c->fail(D2_EDEVICE, "hipStreamSynchronize");
   dfree(d);
   if (st) return st;
-  c->inst_hash = (h[0] * 31 + h[1]) * 31 + h[2] + (uint64_t)c->dt;
+  c->inst_hash = (((h[0] * 31 + h[1]) * 31 + h[2]) * 31 + h[3]) * 31 + h[4] +
+                 (uint64_t)c->dt;
   if (!c->inst_hash) c->inst_hash = 1;
   *out = c->inst_hash;
   return D2_OK;
@@ -1442,9 +1656,47 @@ d2_status d2_load_instances_device(d2_ctx* c, int64_t N, int32_t d,
   return D2_OK;
 }
 
-d2_status d2_centroids_set(d2_ctx* c, int32_t K, int32_t m, const double* Xc,
-                           const double* Wc) {
+d2_status d2_load_instances_symbolic(d2_ctx* c, int64_t N,
+                                     const int64_t* offsets,
+                                     const int32_t* sym, const double* W,
+                                     int32_t S, const double* D) {
   if (!c) return D2_EINVAL;
+  int mkmax = 0;
+  d2_status s = check_offsets(c, N, 1, offsets, mkmax);
+  if (s) return s;
+  if (!sym || !W || !D) return c->fail(D2_EINVAL, "null symbols, W or D");
+  if (S < 1 || S > 16384)
+    return c->fail(D2_EINVAL, "the symbol count S must be in [1, 16384]");
+  const int64_t n = offsets[N];
+  for (int64_t k = 0; k < N; ++k)
+    for (int64_t j = offsets[k]; j < offsets[k + 1]; ++j)
+      if (sym[j] < 0 || sym[j] >= S)
+        return c->fail(D2_EINVAL, "instance " + std::to_string(k) +
+                                      ": symbol out of range");
+  for (int64_t q = 0; q < (int64_t)S * S; ++q)
+    if (!(D[q] >= 0.0) || !std::isfinite(D[q]))
+      return c->fail(D2_EINVAL, "the symbol table must be finite and >= 0");
+  // the weights are checked and renormalised as for vector supports; the
+  // support coordinates are a zero column (d = 1)
+  std::vector<double> zx((size_t)n, 0.0);
+  if ((s = d2_load_instances(c, N, 1, offsets, zx.data(), W))) return s;
+  if ((s = dalloc(c, (void**)&c->d_isym, sizeof(int32_t) * n))) return s;
+  HIPCHK(c, hipMemcpy(c->d_isym, sym, sizeof(int32_t) * n,
+                      hipMemcpyHostToDevice));
+  if ((s = dalloc(c, &c->d_D, c->esz() * (size_t)S * S))) return s;
+  if (c->dt == D2_F64) {
+    if ((s = upload_conv<double>(c, c->d_D, D, (size_t)S * S))) return s;
+  } else {
+    if ((s = upload_conv<float>(c, c->d_D, D, (size_t)S * S))) return s;
+  }
+  c->sym = true;
+  c->S = S;
+  c->inst_hash = 0;
+  return D2_OK;
+}
+
+static d2_status centroids_set_impl(d2_ctx* c, int32_t K, int32_t m,
+                             const double* Xc, const double* Wc) {
   if (!c->N) return c->fail(D2_ESTATE, "load instances first");
   if (K < 1 || !Xc || !Wc) return c->fail(D2_EINVAL, "bad centroid arguments");
   d2_status s = check_limits(c, m);
@@ -1474,6 +1726,50 @@ d2_status d2_centroids_set(d2_ctx* c, int32_t K, int32_t m, const double* Xc,
   return D2_OK;
 }
 
+d2_status d2_centroids_set(d2_ctx* c, int32_t K, int32_t m, const double* Xc,
+                           const double* Wc) {
+  if (!c) return D2_EINVAL;
+  if (c->sym)
+    return c->fail(D2_EINVAL, "symbolic instances: set the centroids with "
+                              "d2_centroids_set_symbolic");
+  return centroids_set_impl(c, K, m, Xc, Wc);
+}
+
+d2_status d2_centroids_set_symbolic(d2_ctx* c, int32_t K, int32_t m,
+                                    const int32_t* csym, const double* Wc) {
+  if (!c) return D2_EINVAL;
+  if (!c->sym)
+    return c->fail(D2_ESTATE, "load symbolic instances first");
+  if (K < 1 || m < 1 || !csym || !Wc)
+    return c->fail(D2_EINVAL, "bad centroid arguments");
+  for (int64_t q = 0; q < (int64_t)K * m; ++q)
+    if (csym[q] < 0 || csym[q] >= c->S)
+      return c->fail(D2_EINVAL, "centroid symbol out of range at " +
+                                    std::to_string(q));
+  std::vector<double> zx((size_t)K * m, 0.0);
+  d2_status s = centroids_set_impl(c, K, m, zx.data(), Wc);
+  if (s) return s;
+  const int MP = c->MP;
+  std::vector<int32_t> hs((size_t)K * MP, 0);
+  for (int q = 0; q < K; ++q)
+    for (int i = 0; i < m; ++i)
+      hs[(size_t)q * MP + i] = csym[(size_t)q * m + i];
+  if (!c->d_csym || c->h_csym.size() != (size_t)K * m) {
+    dfree(c->d_csym);
+    drop_graph(c);
+    if ((s = dalloc(c, (void**)&c->d_csym, sizeof(int32_t) * hs.size())))
+      return s;
+  }
+  HIPCHK(c, hipMemcpy(c->d_csym, hs.data(), sizeof(int32_t) * hs.size(),
+                      hipMemcpyHostToDevice));
+  // the stored assignment bounds refer to the previous symbols
+  if (c->h_csym.size() != (size_t)K * m ||
+      !std::equal(c->h_csym.begin(), c->h_csym.end(), csym))
+    c->lbs_valid = false;
+  c->h_csym.assign(csym, csym + (size_t)K * m);
+  return D2_OK;
+}
+
 d2_status d2_centroids_get(d2_ctx* c, double* Xc, double* Wc) {
   if (!c) return D2_EINVAL;
   if (!c->d_xc) return c->fail(D2_ESTATE, "no centroids");
@@ -1488,7 +1784,9 @@ d2_status d2_centroids_get(d2_ctx* c, double* Xc, double* Wc) {
   for (int q = 0; q < K; ++q)
     for (int i = 0; i < m; ++i) {
       if (Wc) Wc[(size_t)q * m + i] = hw[(size_t)q * MP + i];
-      if (Xc)
+      if (Xc && c->sym)
+        Xc[(size_t)q * m + i] = (double)c->h_csym[(size_t)q * m + i];
+      else if (Xc)
         for (int t = 0; t < d; ++t)
           Xc[((size_t)q * m + i) * d + t] = hx[((size_t)q * MP + i) * d + t];
     }
@@ -1500,6 +1798,9 @@ d2_status d2_centroids_init(d2_ctx* c, int32_t K, int32_t m,
   if (!c) return D2_EINVAL;
   if (!c->N) return c->fail(D2_ESTATE, "load instances first");
   if (K < 1 || !members) return c->fail(D2_EINVAL, "bad init arguments");
+  if (c->sym)
+    return c->fail(D2_EINVAL, "symbolic instances: the merge initialisation "
+                              "needs vector supports");
   d2_status s = check_limits(c, m);
   if (s) return s;
   const int d = c->d;
@@ -1551,8 +1852,13 @@ d2_status d2_labels_set(d2_ctx* c, const int32_t* labels) {
     if (labels[k] < 0 || labels[k] >= c->K)
       return c->fail(D2_EINVAL, "label out of range at " + std::to_string(k));
   HIPCHK(c, hipSetDevice(c->device));
+  HIPCHK(c, c->sync_labels());
+  const bool same =
+      c->have_labels && std::equal(c->h_labels.begin(), c->h_labels.end(),
+                                   labels);
   c->h_labels.assign(labels, labels + c->N);
-  ++c->label_gen;
+  c->hlab_ok = true;
+  if (!same) ++c->label_gen;
   HIPCHK(c, hipMemcpy(c->d_labels, labels, sizeof(int32_t) * c->N,
                       hipMemcpyHostToDevice));
   c->have_labels = true;
@@ -1564,6 +1870,9 @@ d2_status d2_labels_get(d2_ctx* c, int32_t* labels) {
   if (!c) return D2_EINVAL;
   if (!c->have_labels) return c->fail(D2_ESTATE, "no labels");
   if (!labels) return c->fail(D2_EINVAL, "null labels");
+  HIPCHK(c, hipSetDevice(c->device));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, c->sync_labels());
   std::copy(c->h_labels.begin(), c->h_labels.end(), labels);
   return D2_OK;
 }
@@ -1575,20 +1884,34 @@ d2_status d2_assign(d2_ctx* c, const d2_ot_params* p, int32_t* labels_out,
   if (!p || p->iters < 1 || !(p->rho0 > 0) || !(p->eps >= 0))
     return c->fail(D2_EINVAL, "bad transport parameters");
   HIPCHK(c, hipSetDevice(c->device));
+  // the labels before the assignment, for the count of changes
+  if (c->have_labels)
+    HIPCHK(c, hipMemcpyAsync(c->d_prev_labels, c->d_labels,
+                             sizeof(int32_t) * c->N, hipMemcpyDeviceToDevice,
+                             c->stream));
   d2_status s = c->dt == D2_F64 ? run_assign<double>(c, p, nullptr)
                                 : run_assign<float>(c, p, nullptr);
   if (s) return s;
-  std::vector<int32_t> lab(c->N);
-  HIPCHK(c, hipMemcpy(lab.data(), c->d_labels, sizeof(int32_t) * c->N,
-                      hipMemcpyDeviceToHost));
-  int64_t changed = 0;
-  for (int64_t k = 0; k < c->N; ++k)
-    changed += (!c->have_labels || lab[k] != c->h_labels[k]);
-  c->h_labels.swap(lab);
-  ++c->label_gen;
+  int64_t changed = c->N;
+  if (c->have_labels) {
+    HIPCHK(c, hipMemsetAsync(c->d_nchg, 0, sizeof(int64_t), c->stream));
+    hipLaunchKernelGGL(k_count_changes, dim3(512), dim3(256), 0, c->stream,
+                       c->d_labels, c->d_prev_labels, c->N, c->d_nchg);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipMemcpyAsync(&changed, c->d_nchg, sizeof(int64_t),
+                             hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
+  if (changed > 0) {
+    ++c->label_gen;
+    c->hlab_ok = false;
+    c->lists_valid = false;
+  }
   c->have_labels = true;
-  c->lists_valid = false;
-  if (labels_out) std::copy(c->h_labels.begin(), c->h_labels.end(), labels_out);
+  if (labels_out) {
+    HIPCHK(c, c->sync_labels());
+    std::copy(c->h_labels.begin(), c->h_labels.end(), labels_out);
+  }
   if (dist_out)
     HIPCHK(c, hipMemcpy(dist_out, c->d_best, sizeof(double) * c->N,
                         hipMemcpyDeviceToHost));
@@ -1630,6 +1953,8 @@ d2_status d2_barycenter(d2_ctx* c, const d2_badmm_params* p,
     return c->fail(D2_EINVAL, "bad B-ADMM parameters");
   if (p->init == D2_INIT_LEARNED && !c->ws)
     return c->fail(D2_ESTATE, "D2_INIT_LEARNED needs d2_set_warm_start");
+  if (p->init == D2_INIT_LEARNED && c->sym)
+    return c->fail(D2_EINVAL, "no learned warm start for symbolic supports");
   HIPCHK(c, hipSetDevice(c->device));
   d2_status s;
   if (p->init == D2_INIT_LEARNED) {
@@ -1644,13 +1969,18 @@ d2_status d2_barycenter(d2_ctx* c, const d2_badmm_params* p,
   }
   if ((s = ensure_plans(c))) return s;
   if ((s = build_lists(c, p->init == D2_INIT_CACHED))) return s;
-  return c->dt == D2_F64 ? run_barycenter<double>(c, p, st)
-                         : run_barycenter<float>(c, p, st);
+  // symbolic supports never move: the support step is skipped (Sec. 5)
+  d2_badmm_params q = *p;
+  if (c->sym) q.fixed_support = 1;
+  return c->dt == D2_F64 ? run_barycenter<double>(c, &q, st)
+                         : run_barycenter<float>(c, &q, st);
 }
 
 d2_status d2_support_update(d2_ctx* c) {
   if (!c) return D2_EINVAL;
-  if (!c->have_cache || !c->have_labels || c->h_cache_labels != c->h_labels)
+  if (c->sym)
+    return c->fail(D2_EINVAL, "symbolic supports are fixed (Sec. 5)");
+  if (!c->have_cache || !c->have_labels || c->cache_gen != c->label_gen)
     return c->fail(D2_ESTATE, "need a barycenter on the current labels");
   HIPCHK(c, hipSetDevice(c->device));
   d2_status s;
@@ -1697,6 +2027,137 @@ d2_status d2_cluster(d2_ctx* c, int32_t rounds, const d2_badmm_params* bp,
     d2_badmm_stats st;
     if ((s = d2_barycenter(c, &q, &st))) return s;
     info.ms_barycenter = st.ms;
+    if (cb) cb(&info, user);
+  }
+  return D2_OK;
+}
+
+d2_status d2_assign_multi(int32_t n_modal, d2_ctx* const* ctxs,
+                          const d2_ot_params* p, int32_t* labels_out,
+                          double* dist_out, int64_t* n_changed) {
+  if (n_modal < 1 || !ctxs || !ctxs[0]) return D2_EINVAL;
+  d2_ctx* c0 = ctxs[0];
+  if (!p || p->iters < 1 || !(p->rho0 > 0) || !(p->eps >= 0))
+    return c0->fail(D2_EINVAL, "bad transport parameters");
+  for (int i = 0; i < n_modal; ++i) {
+    d2_ctx* c = ctxs[i];
+    if (!c) return c0->fail(D2_EINVAL, "null context");
+    if (!c->N || !c->K)
+      return c0->fail(D2_ESTATE, "modality " + std::to_string(i) +
+                                     ": need instances, centroids");
+    if (c->device != c0->device || c->N != c0->N || c->K != c0->K)
+      return c0->fail(D2_EINVAL, "modality " + std::to_string(i) +
+                                     ": device, N or K differ");
+  }
+  HIPCHK(c0, hipSetDevice(c0->device));
+  const int64_t N = c0->N;
+  const int K = c0->K;
+  const size_t need = (size_t)N * K;
+  if (need > c0->dall_cap) {
+    dfree(c0->d_dall);
+    c0->dall_cap = 0;
+    d2_status s = dalloc(c0, (void**)&c0->d_dall, sizeof(double) * need);
+    if (s) return s;
+    c0->dall_cap = need;
+  }
+  // every modality's distances, all pairs, summed in modality order
+  for (int i = 0; i < n_modal; ++i)
+    HIPCHK(c0, hipStreamSynchronize(ctxs[i]->stream));
+  HIPCHK(c0, hipMemsetAsync(c0->d_dall, 0, sizeof(double) * need,
+                            c0->stream));
+  HIPCHK(c0, hipStreamSynchronize(c0->stream));
+  d2_ot_params q = *p;
+  q.prune = 0;
+  for (int i = 0; i < n_modal; ++i) {
+    d2_ctx* c = ctxs[i];
+    if (c->have_labels)
+      HIPCHK(c0, hipMemcpyAsync(c->d_prev_labels, c->d_labels,
+                                sizeof(int32_t) * N, hipMemcpyDeviceToDevice,
+                                c->stream));
+    d2_status s = c->dt == D2_F64
+                      ? run_assign<double>(c, &q, nullptr, c0->d_dall)
+                      : run_assign<float>(c, &q, nullptr, c0->d_dall);
+    if (s) {
+      if (c != c0) c0->fail(s, "modality " + std::to_string(i) + ": " + c->err);
+      return s;
+    }
+  }
+  hipLaunchKernelGGL(k_argmin_rows, dim3((unsigned)((N + 255) / 256)),
+                     dim3(256), 0, c0->stream, c0->d_dall, N, K, c0->d_labels,
+                     c0->d_best);
+  HIPCHK(c0, hipGetLastError());
+  HIPCHK(c0, hipStreamSynchronize(c0->stream));
+  int64_t ch0 = N;
+  for (int i = 0; i < n_modal; ++i) {
+    d2_ctx* c = ctxs[i];
+    if (c != c0) {
+      HIPCHK(c0, hipMemcpyAsync(c->d_labels, c0->d_labels,
+                                sizeof(int32_t) * N, hipMemcpyDeviceToDevice,
+                                c->stream));
+      HIPCHK(c0, hipMemcpyAsync(c->d_best, c0->d_best, sizeof(double) * N,
+                                hipMemcpyDeviceToDevice, c->stream));
+    }
+    int64_t changed = N;
+    if (c->have_labels) {
+      HIPCHK(c0, hipMemsetAsync(c->d_nchg, 0, sizeof(int64_t), c->stream));
+      hipLaunchKernelGGL(k_count_changes, dim3(512), dim3(256), 0, c->stream,
+                         c->d_labels, c->d_prev_labels, N, c->d_nchg);
+      HIPCHK(c0, hipGetLastError());
+      HIPCHK(c0, hipMemcpyAsync(&changed, c->d_nchg, sizeof(int64_t),
+                                hipMemcpyDeviceToHost, c->stream));
+    }
+    HIPCHK(c0, hipStreamSynchronize(c->stream));
+    if (changed > 0) {
+      ++c->label_gen;
+      c->hlab_ok = false;
+      c->lists_valid = false;
+    }
+    c->have_labels = true;
+    if (i == 0) ch0 = changed;
+  }
+  if (labels_out) {
+    HIPCHK(c0, c0->sync_labels());
+    std::copy(c0->h_labels.begin(), c0->h_labels.end(), labels_out);
+  }
+  if (dist_out)
+    HIPCHK(c0, hipMemcpy(dist_out, c0->d_best, sizeof(double) * N,
+                         hipMemcpyDeviceToHost));
+  if (n_changed) *n_changed = ch0;
+  return D2_OK;
+}
+
+d2_status d2_cluster_multi(int32_t n_modal, d2_ctx* const* ctxs,
+                           int32_t rounds, const d2_badmm_params* bp,
+                           const d2_ot_params* op, d2_round_cb cb,
+                           void* user) {
+  if (n_modal < 1 || !ctxs || !ctxs[0]) return D2_EINVAL;
+  d2_ctx* c0 = ctxs[0];
+  if (rounds < 0 || !bp || !op) return c0->fail(D2_EINVAL, "bad arguments");
+  std::vector<double> best(c0->N);
+  for (int r = 0; r < rounds; ++r) {
+    d2_round_info info;
+    std::memset(&info, 0, sizeof(info));
+    info.round = r;
+    int64_t changed = 0;
+    d2_status s = d2_assign_multi(n_modal, ctxs, op, nullptr, best.data(),
+                                  &changed);
+    if (s) return s;
+    double sum = 0.0;
+    for (double v : best) sum += v;
+    info.n_changed = changed;
+    info.assign_obj = sum / (double)c0->N;
+    // the modalities' centroids are updated separately (Sec. 5)
+    for (int i = 0; i < n_modal; ++i) {
+      d2_ctx* c = ctxs[i];
+      d2_badmm_params q = *bp;
+      q.init = (r == 0 && !c->have_cache) ? D2_INIT_PRODUCT : bp->init;
+      d2_badmm_stats st;
+      if ((s = d2_barycenter(c, &q, &st))) {
+        if (c != c0) c0->fail(s, "modality " + std::to_string(i) + ": " + c->err);
+        return s;
+      }
+      info.ms_barycenter += st.ms;
+    }
     if (cb) cb(&info, user);
   }
   return D2_OK;
@@ -1999,11 +2460,19 @@ d2_status d2_checkpoint_save(d2_ctx* c, const char* path) {
   h.plan_elems = h.have_cache ? c->h_pofs[c->N] : 0;
   d2_status s = instance_hash(c, &h.inst_hash);
   if (s) return s;
+  HIPCHK(c, c->sync_labels());
+  if (h.have_cache) HIPCHK(c, c->sync_cache_labels());
   std::vector<double> hx((size_t)c->K * c->MP * c->d), hw((size_t)c->K * c->MP);
   HIPCHK(c, hipMemcpy(hx.data(), c->d_xc, hx.size() * 8,
                       hipMemcpyDeviceToHost));
   HIPCHK(c, hipMemcpy(hw.data(), c->d_wc, hw.size() * 8,
                       hipMemcpyDeviceToHost));
+  // symbolic supports (d = 1, zero coordinates): the centroid symbols take
+  // the place of the coordinates
+  if (c->sym)
+    for (int q = 0; q < c->K; ++q)
+      for (int i = 0; i < c->m; ++i)
+        hx[(size_t)q * c->MP + i] = (double)c->h_csym[(size_t)q * c->m + i];
   const std::string tmp = std::string(path) + ".tmp";
   FILE* f = fopen(tmp.c_str(), "wb");
   if (!f) return c->fail(D2_EINVAL, "cannot open " + tmp + " for writing");
@@ -2078,6 +2547,18 @@ d2_status d2_checkpoint_load(d2_ctx* c, const char* path) {
     return bad("truncated centroids");
   if (!finite_all(hx.data(), hx.size()) || !finite_all(hw.data(), hw.size()))
     return bad("non-finite centroids");
+  std::vector<int32_t> csym;
+  if (c->sym) {
+    csym.resize((size_t)h.K * h.m);
+    for (int q = 0; q < h.K; ++q)
+      for (int i = 0; i < h.m; ++i) {
+        const double v = hx[(size_t)q * h.MP + i];
+        if (!(v >= 0.0 && v < (double)c->S && v == std::floor(v)))
+          return bad("centroid symbol out of range");
+        csym[(size_t)q * h.m + i] = (int32_t)v;
+      }
+    std::fill(hx.begin(), hx.end(), 0.0);
+  }
   if (h.have_labels) {
     lab.resize(c->N);
     if (!read_all(f, hs, lab.data(), sizeof(int32_t) * c->N))
@@ -2114,6 +2595,18 @@ d2_status d2_checkpoint_load(d2_ctx* c, const char* path) {
                       hipMemcpyHostToDevice));
   c->R = slots_for(c);
   free_bounds(c);
+  if (c->sym) {
+    std::vector<int32_t> hs((size_t)h.K * h.MP, 0);
+    for (int q = 0; q < h.K; ++q)
+      for (int i = 0; i < h.m; ++i)
+        hs[(size_t)q * h.MP + i] = csym[(size_t)q * h.m + i];
+    if (!c->d_csym &&
+        (s = dalloc(c, (void**)&c->d_csym, sizeof(int32_t) * hs.size())))
+      return s;
+    HIPCHK(c, hipMemcpy(c->d_csym, hs.data(), sizeof(int32_t) * hs.size(),
+                        hipMemcpyHostToDevice));
+    c->h_csym = csym;
+  }
   if ((s = d2_set_schedule(c, h.chunk, h.waves))) return s;
   if ((s = d2_set_bucketing(c, h.bucket))) return s;
   c->lists_valid = false;
@@ -2126,13 +2619,19 @@ d2_status d2_checkpoint_load(d2_ctx* c, const char* path) {
   } else {
     c->h_labels.assign(c->N, 0);
   }
+  c->hlab_ok = true;
   ++c->label_gen;
   c->have_cache = false;
   if (h.have_cache) {
     if ((s = ensure_plans(c))) return s;
     HIPCHK(c, hipMemcpy(c->d_P2, plans.data(), plans.size(),
                         hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->d_cache_labels, clab.data(),
+                        sizeof(int32_t) * c->N, hipMemcpyHostToDevice));
     c->h_cache_labels = clab;
+    c->hcache_ok = true;
+    c->cache_gen = (c->have_labels && clab == lab) ? c->label_gen
+                                                    : c->label_gen - 1;
     c->have_cache = true;
   }
   c->trace_rows = 0;

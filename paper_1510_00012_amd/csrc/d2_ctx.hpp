@@ -29,6 +29,15 @@ struct d2_ctx {
   void* d_X = nullptr;
   void* d_W = nullptr;
   bool borrowed = false;  // d_X, d_W belong to the caller (device load)
+  // symbolic supports (d2_load_instances_symbolic): d = 1 with zero X,
+  // instance symbols, the S x S table in the device dtype, and the
+  // centroids' symbols (K x MP, host copy K x m)
+  bool sym = false;
+  int S = 0;
+  int32_t* d_isym = nullptr;
+  void* d_D = nullptr;
+  int32_t* d_csym = nullptr;
+  std::vector<int32_t> h_csym;
   // learned warm start used by D2_INIT_LEARNED (owned by the caller)
   d2_ws* ws = nullptr;
   int ws_gate = 1;
@@ -41,11 +50,21 @@ struct d2_ctx {
   double* d_wsave = nullptr;  // (restored if it fails numerically)
   double* d_rho = nullptr;
   int* d_cnt = nullptr;
-  // labels
+  // labels: d_labels is authoritative; h_labels mirrors it when hlab_ok
+  // (the assignment leaves the labels on the device).  d_cache_labels are
+  // the labels of the last centroid update (whose Pi2 is cached), mirrored
+  // in h_cache_labels when hcache_ok.  label_gen changes whenever the
+  // labels do; cache_gen is its value at the last centroid update.
   std::vector<int32_t> h_labels, h_cache_labels;
   bool have_labels = false, have_cache = false;
-  uint64_t label_gen = 0;  // bumped whenever h_labels changes
+  bool hlab_ok = true, hcache_ok = true;
+  uint64_t label_gen = 0, cache_gen = ~0ull;
   int32_t* d_labels = nullptr;
+  int32_t* d_cache_labels = nullptr;
+  int32_t* d_prev_labels = nullptr;  // labels before the last assignment
+  int64_t* d_nchg = nullptr;         // label changes of the last assignment
+  double* d_dall = nullptr;          // N x K summed multi-modal distances
+  size_t dall_cap = 0;
   double* d_best = nullptr;
   int32_t* d_pairs = nullptr;  // N x 2: per instance of the last assignment,
                                // transports run and cost blocks formed
@@ -101,11 +120,22 @@ struct d2_ctx {
   std::vector<uint8_t> h_cls;
   int cls_MP = 0;
   double cls_ent[6] = {};
+  int64_t cls_cnt[6] = {};  // instances per slot class
+  bool host_ctab = false;   // h_ctab matches d_ctab (host-built lists)
   std::vector<uint32_t> h_key;
   std::vector<int32_t> h_work;
   std::vector<uint8_t> h_warm;  // slot classes under this % of entries merge up
   std::vector<int2> h_ctab;
   bool lists_valid = false;
+  // device construction of the work list: per-instance slot bucket (for
+  // bkt_MP / bkt_pct), per-tile key histograms and per-key scratch
+  uint8_t* d_bkt = nullptr;
+  int bkt_MP = 0, bkt_pct = -1;
+  int32_t* d_tcnt = nullptr;
+  int32_t* d_tsum = nullptr;
+  int64_t tcnt_cap = 0;
+  int64_t* d_keys = nullptr;  // 5 x G: counts, support sums, starts,
+  int keys_cap = 0;           // first chunks, bucket offsets
   // objective trace of the last barycenter
   double* d_trace = nullptr;
   double* d_rtrace = nullptr;  // residual trace, same shape as d_trace
@@ -137,6 +167,23 @@ struct d2_ctx {
   d2_status fail(d2_status s, const std::string& msg) {
     err = msg;
     return s;
+  }
+  // host mirrors of the device labels, refreshed on demand
+  hipError_t sync_labels() {
+    if (hlab_ok || !d_labels) return hipSuccess;
+    h_labels.resize(N);
+    hipError_t e = hipMemcpy(h_labels.data(), d_labels, sizeof(int32_t) * N,
+                             hipMemcpyDeviceToHost);
+    if (e == hipSuccess) hlab_ok = true;
+    return e;
+  }
+  hipError_t sync_cache_labels() {
+    if (hcache_ok || !d_cache_labels) return hipSuccess;
+    h_cache_labels.resize(N);
+    hipError_t e = hipMemcpy(h_cache_labels.data(), d_cache_labels,
+                             sizeof(int32_t) * N, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) hcache_ok = true;
+    return e;
   }
   size_t esz() const { return dt == D2_F64 ? 8 : 4; }
 };

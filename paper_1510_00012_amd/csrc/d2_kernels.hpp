@@ -213,6 +213,15 @@ template <typename T> struct Args {
   int m, d, xs, rule, ps;
   int recost;             // cached cost: recompute from xc and store
   int xstage;             // centroid support staged in LDS for cost work
+  // Symbolic supports (Sec. 5): when dsym is set, support points are
+  // symbols and the cost of centroid row i against support point j is
+  // dsym[csym[c * MP + i] * S + isym[j]] (S x S table, device dtype); the
+  // rho pass gathers it into the cost cache, which every later launch
+  // reads.
+  const T* dsym;
+  const int32_t* isym;    // n instance symbols
+  const int32_t* csym;    // K x MP centroid symbols
+  int S;
 };
 
 struct FinArgs {
@@ -1023,6 +1032,7 @@ __global__ void __launch_bounds__(256) k_iter_ba(Args<T> a) {
 template <typename T, int MP, int NS, int MODE>
 __device__ __forceinline__ void aux_tile(const Args<T>& a, const Tile<T, MP>& tl,
                                          int k, int mode_arg, const double* xrow,
+                                         int64_t srow,
                                          const T (&xr)[4], const T* xl, T wi,
                                          T rho, T a2, T eps, double& accw,
                                          double& accf, double& accr,
@@ -1053,7 +1063,8 @@ __device__ __forceinline__ void aux_tile(const Args<T>& a, const Tile<T, MP>& tl
     if (xl) cost_tile<T, MP, NS>(a, tl, xl, cs);
 #pragma unroll
     for (int r = 0; r < NS; ++r) {
-      T cv = xl ? cs[r] : cost_of(r);
+      const T cv = a.dsym ? a.dsym[srow + a.isym[tl.o + tl.colc(r)]]
+                          : (xl ? cs[r] : cost_of(r));
       if (v[r]) {
         if (a.Cc) a.Cc[tl.eidx(r, a.m)] = cv;
         s += cv;
@@ -1162,6 +1173,9 @@ __global__ void __launch_bounds__(256) k_aux(Args<T> a, int mode_arg) {
     for (int t = 0; t < 4; ++t)
       if (t < d && rowok) xr[t] = (T)xrow[t];
   }
+  // symbolic supports: this row's offset into the symbol table
+  const int64_t srow =
+      a.dsym ? (int64_t)a.csym[(int64_t)c * MP + (rowok ? i : 0)] * a.S : 0;
   const int nrec = MP * (d + 1);
   double* accx = s_dyn + (int64_t)wave * nrec;
   if (xrecs)
@@ -1177,8 +1191,8 @@ __global__ void __launch_bounds__(256) k_aux(Args<T> a, int mode_arg) {
     const int k = uni(a.work[pos]);
     tl.setup(a.off, a.pofs, a.m, k);
     with_slots<R>(tl.nsl, [&]<int NS>() {
-      aux_tile<T, MP, NS, MODE>(a, tl, k, mode, xrow, xr, xl, wi, rho, a2, eps,
-                          accw, accf, accr, accx);
+      aux_tile<T, MP, NS, MODE>(a, tl, k, mode, xrow, srow, xr, xl, wi, rho,
+                                a2, eps, accw, accf, accr, accx);
     });
   }
   if (mode == kRho) {
@@ -1275,6 +1289,15 @@ template <typename T> struct AssignArgs {
   float* lbs;
   const float* dlt;
   int lbs_in;
+  // symbolic supports (as in Args; null dsym: squared Euclidean costs)
+  const T* dsym;
+  const int32_t* isym;
+  const int32_t* csym;
+  int S;
+  // every pair's distance added to dall[k * K + c] (exhaustive launches of
+  // multi-modal instances, whose combined distance sums the modalities);
+  // null: not stored
+  double* dall;
   int64_t N;            // instances in this launch
   double rho0, eps;
   int m, d, xs, K, iters, prune, prev_valid;
@@ -1333,6 +1356,14 @@ __device__ __forceinline__ void pair_costs(const AssignArgs<T>& a,
                                            T (&cs)[NS]) {
   using V4 = typename Vec4<T>::type;
   const Tile<T, MP> tl = tl0.fresh();
+  if (a.dsym) {
+    // symbolic supports: the costs are gathered from the symbol table
+    const int64_t srow = (int64_t)a.csym[(int64_t)c * MP + tl.ic] * a.S;
+#pragma unroll
+    for (int r = 0; r < NS; ++r)
+      cs[r] = tl.valid(r) ? a.dsym[srow + a.isym[tl.o + tl.colc(r)]] : T(0);
+    return;
+  }
   const uint32_t rowb = (uint32_t)a.xs * (uint32_t)sizeof(T);
   const Rsrc rY = make_rsrc(a.X + tl.o * a.xs, (uint32_t)tl.mk * rowb);
   const Rsrc rC = make_rsrc(a.xct + (int64_t)c * MP * a.xs, MP * rowb);
@@ -1483,6 +1514,7 @@ __device__ __forceinline__ void assign_tile(const AssignArgs<T>& a,
     wk[r] = tl.valid(r) ? a.W[tl.o + tl.colc(r)] : T(0);
   auto consider = [&](int c) {
     const double val = pair_value<T, MP, NS>(a, tl, c, cs, wk);
+    if (a.dall && lane == 0) a.dall[kinst * a.K + c] += val;
     ++nevals;
     if (bestc < 0 || val < bestv || (val == bestv && c < bestc)) {
       bestv = val;

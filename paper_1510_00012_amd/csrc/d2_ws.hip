@@ -853,6 +853,8 @@ d2_status refresh(d2_ws* w, hipStream_t st) {
 d2_status ensure_lists(d2_ws* w, d2_ctx* c) {
   if (w->lctx == c && w->lgen == c->label_gen && w->lK == c->K)
     return D2_OK;
+  WSCHK(w, hipStreamSynchronize(c->stream));
+  WSCHK(w, c->sync_labels());
   const int K = c->K;
   std::vector<int64_t> cnt(K + 1, 0);
   std::vector<int32_t> nmem(K, 0);
@@ -1116,6 +1118,8 @@ d2_status check_pair(d2_ws* w, d2_ctx* c) {
     return w->fail(D2_EINVAL, "context and warm start on different devices");
   if (!c->N || !c->K || !c->have_labels)
     return w->fail(D2_ESTATE, "context needs instances, centroids, labels");
+  if (c->sym)
+    return w->fail(D2_EINVAL, "symbolic supports have no coordinates");
   if (c->m != w->m || c->d != w->d)
     return w->fail(D2_EINVAL, "context m / d differ from the network's");
   return D2_OK;
@@ -1497,9 +1501,13 @@ d2_status d2_objective_feasible(d2_ctx* c, double* per_instance,
   if (!c) return D2_EINVAL;
   if (!c->d_P1 || !c->have_cache || !c->have_labels)
     return c->fail(D2_ESTATE, "no plans yet");
-  if (c->h_cache_labels != c->h_labels)
+  if (c->cache_gen != c->label_gen)
     return c->fail(D2_ESTATE, "labels changed since the last barycenter");
+  if (c->sym)
+    return c->fail(D2_EINVAL, "not available for symbolic supports");
   HIPCHK(c, hipSetDevice(c->device));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, c->sync_labels());
   std::vector<double> val(c->N);
   double* dv = nullptr;
   if (hipMalloc((void**)&dv, sizeof(double) * c->N) != hipSuccess)

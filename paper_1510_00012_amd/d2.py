@@ -36,6 +36,8 @@ EXPORTS = [
     "d2_ws_destroy", "d2_ws_last_error", "d2_ws_params_set",
     "d2_ws_params_get", "d2_ws_targets_from", "d2_ws_grad",
     "d2_ws_train_step", "d2_ws_propose", "d2_assign_noalloc",
+    "d2_load_instances_symbolic", "d2_centroids_set_symbolic",
+    "d2_assign_multi", "d2_cluster_multi",
 ]
 
 
@@ -159,6 +161,14 @@ def load_library(path: str = LIB_PATH):
         "d2_ws_train_step": ([_p, _p, _p, _i32, ctypes.POINTER(WsOpt), _p],
                              ctypes.c_int),
         "d2_ws_propose": ([_p, _p, _i32, _p, _p, _p], ctypes.c_int),
+        "d2_load_instances_symbolic": ([_p, _i64, _p, _p, _p, _i32, _p],
+                                       ctypes.c_int),
+        "d2_centroids_set_symbolic": ([_p, _i32, _i32, _p, _p], ctypes.c_int),
+        "d2_assign_multi": ([_i32, _p, ctypes.POINTER(OtParams), _p, _p, _p],
+                            ctypes.c_int),
+        "d2_cluster_multi": ([_i32, _p, _i32, ctypes.POINTER(BadmmParams),
+                              ctypes.POINTER(OtParams), ROUND_CB, _p],
+                             ctypes.c_int),
         "d2_assign_noalloc": ([_i32, _p, ctypes.c_int, _i64, _i32, _i32, _p,
                                _p, _p, _i32, _i32, _p, _p,
                                ctypes.POINTER(OtParams), _p, _p,
@@ -268,6 +278,26 @@ class D2Context:
         self._chk(self.lib.d2_load_instances_device(
             self.h, N, int(d), _ptr(off), _p(int(dX)), _p(int(dW))))
         self.offsets, self.N, self.n, self.d = off, N, int(off[-1]), int(d)
+
+    def load_instances_symbolic(self, offsets, sym, W, D):
+        """Instances over a symbol set: sym (n) symbol ids, W (n) weights,
+        D (S x S) the symbol-to-symbol cost table."""
+        off = _c(offsets, np.int64)
+        sym = _c(sym, np.int32)
+        W = _c(W, np.float64)
+        D = _c(D, np.float64)
+        self._chk(self.lib.d2_load_instances_symbolic(
+            self.h, len(off) - 1, _ptr(off), _ptr(sym), _ptr(W), D.shape[0],
+            _ptr(D)))
+        self.offsets, self.N, self.n, self.d = off, len(off) - 1, int(off[-1]), 1
+
+    def centroids_set_symbolic(self, csym, Wc):
+        csym = _c(csym, np.int32)
+        Wc = _c(Wc, np.float64)
+        K, m = csym.shape
+        self._chk(self.lib.d2_centroids_set_symbolic(self.h, K, m, _ptr(csym),
+                                                     _ptr(Wc)))
+        self.K, self.m = K, m
 
     def checkpoint_save(self, path):
         self._chk(self.lib.d2_checkpoint_save(self.h, os.fsencode(path)))
@@ -473,6 +503,46 @@ def assign_noalloc(N, d, mk_max, offsets, X, W, K, m, Xc, Wc, labels, dist,
         ctypes.byref(p), labels, dist, err, len(err))
     if st != D2_OK:
         raise D2Error(st, err.value.decode())
+
+
+def _ctx_array(ctxs):
+    arr = (ctypes.c_void_p * len(ctxs))(*[c.h for c in ctxs])
+    return arr
+
+
+def assign_multi(ctxs, iters=100, rho0=2.0, eps=1e-16):
+    """d2_assign_multi over the modality contexts `ctxs` (D2Context list):
+    (labels, minimal summed distances, labels changed)."""
+    c0 = ctxs[0]
+    lab = np.empty(c0.N, dtype=np.int32)
+    dist = np.empty(c0.N)
+    nch = ctypes.c_int64(0)
+    p = ot_params(iters, rho0, eps, False)
+    c0._chk(c0.lib.d2_assign_multi(len(ctxs), _ctx_array(ctxs),
+                                   ctypes.byref(p), _ptr(lab), _ptr(dist),
+                                   ctypes.byref(nch)))
+    return lab, dist, int(nch.value)
+
+
+def cluster_multi(ctxs, rounds, iters=100, tau=10, rho0=2.0, eps=1e-16,
+                  rule=1, assign_iters=100):
+    """d2_cluster_multi: per-round records (dicts) of the callback."""
+    c0 = ctxs[0]
+    recs = []
+
+    def cb(info, user):
+        i = info.contents
+        recs.append({"round": i.round, "n_changed": i.n_changed,
+                     "assign_obj": i.assign_obj,
+                     "ms_barycenter": i.ms_barycenter})
+
+    ccb = ROUND_CB(cb)
+    bp = badmm_params(iters, tau, rho0, eps, rule, D2_INIT_CACHED, False)
+    op = ot_params(assign_iters, rho0, eps, False)
+    c0._chk(c0.lib.d2_cluster_multi(len(ctxs), _ctx_array(ctxs), rounds,
+                                    ctypes.byref(bp), ctypes.byref(op), ccb,
+                                    None))
+    return recs
 
 
 def ws_param_count(m, d, hidden):

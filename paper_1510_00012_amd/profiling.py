@@ -3,11 +3,13 @@
 Usage (after the rocprofv3 runs, on any machine):
   python -m paper_1510_00012_amd.profiling trace  <kernel_stats.csv> <out.md> <cmd>
   python -m paper_1510_00012_amd.profiling traffic <fetch_counter.csv> \
-      <write_counter.csv> <kernel-substring> <workload> <copy_mib> <out.json> <cmd>
+      <write_counter.csv> <kernel-substring> <workload> <copy_mib> <out.json> \
+      <cmd> [dispatches per timed launch]
 
 `traffic` scales the per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of the
 kernel by the factor that makes the same counters match a plain device copy
-of known size recorded in the same run (the bench's --copy-mib leg), and
+of known size recorded in the same run (the library's copy probe, which the
+bench runs with 4096 MiB; else the bench's --copy-mib runtime copy), and
 records the hash of the kernel sources so that a stale record is ignored.
 """
 from __future__ import annotations
@@ -24,7 +26,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("d2_kernels.hpp", "d2_api.hip"):
+    # the device code of the plan-update and auxiliary kernels
+    for f in ("d2_kernels.hpp", "d2_kinst.hpp"):
         with open(os.path.join(HERE, "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -60,15 +63,23 @@ def _per_kernel(counter_csv, counter):
 
 
 def traffic(fetch_csv, write_csv, kernel_sub, workload, copy_mib, out_json,
-            cmd):
+            cmd, group=1):
+    """group: dispatches of the kernel that make one unit of the bench's
+    per-launch timing (the slot-bucket launches of one B-ADMM iteration
+    are timed together), so the bytes are per group of dispatches."""
+    group = int(group)
     copy_kib = float(copy_mib) * 1024.0
     fetch = _per_kernel(fetch_csv, "FETCH_SIZE")
     write = _per_kernel(write_csv, "WRITE_SIZE")
 
     def copy_value(agg):
-        # the largest dispatch of the runtime copy is the calibration copy
-        vals = [v for k, vs in agg.items() if "copyBuffer" in k or "copy" in k
-                for v in vs]
+        # the calibration copy: the library's copy probe (every dispatch
+        # moves copy_mib MiB; median), else the largest runtime copy
+        vals = sorted(v for k, vs in agg.items() if "k_copy_probe" in k
+                      for v in vs)
+        if vals:
+            return vals[len(vals) // 2]
+        vals = [v for k, vs in agg.items() if "copyBuffer" in k for v in vs]
         return max(vals) if vals else None
 
     cf, cw = copy_value(fetch), copy_value(write)
@@ -77,11 +88,12 @@ def traffic(fetch_csv, write_csv, kernel_sub, workload, copy_mib, out_json,
 
     def kern(agg):
         vals = [v for k, vs in agg.items() if kernel_sub in k for v in vs]
-        return sum(vals) / len(vals) if vals else None
+        return group * sum(vals) / len(vals) if vals else None
 
     kf, kw = kern(fetch), kern(write)
     rec = {
         "kernel": kernel_sub,
+        "dispatches_per_launch": group,
         "workload": workload,
         "command": cmd,
         "kernel_source_hash": kernel_source_hash(),
@@ -105,6 +117,6 @@ if __name__ == "__main__":
     if sys.argv[1] == "trace":
         trace_summary(sys.argv[2], sys.argv[3], sys.argv[4])
     elif sys.argv[1] == "traffic":
-        print(json.dumps(traffic(*sys.argv[2:9]), indent=1))
+        print(json.dumps(traffic(*sys.argv[2:]), indent=1))
     else:
         raise SystemExit(__doc__)

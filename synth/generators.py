@@ -191,32 +191,40 @@ def protein_symbol_workload(seed, N, gram=1, n_family=10, len_lo=80,
                 df = emb[a, t] - emb[b, t]
                 acc += df * df
             D1[a, b] = acc
-    if gram == 1:
-        S = A
-        D = D1
-    elif gram == 3:
-        S = A ** 3
-        idx = np.arange(S)
-        a, b, c = idx // (A * A), (idx // A) % A, idx % A
-        D = D1[a][:, a] + D1[b][:, b] + D1[c][:, c]
-    else:
-        raise ValueError("gram must be 1 or 3")
-    syms, ws, sizes = [], [], []
-    for k in range(N):
-        s_ = seq[k, :lens[k]]
-        if gram == 3:
-            s_ = s_[:-2] * (A * A) + s_[1:-1] * A + s_[2:]
-        vals, cnt = np.unique(s_, return_counts=True)
-        order = np.lexsort((vals, -cnt))[:mk_cap]
-        vals, cnt = vals[order], cnt[order].astype(np.float64)
-        syms.append(vals)
-        ws.append(cnt / cnt.sum())
-        sizes.append(len(vals))
-    offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
-    return {"offsets": offsets,
-            "sym": np.concatenate(syms).astype(np.int32),
-            "W": np.concatenate(ws), "D": np.ascontiguousarray(D),
-            "classes": fam.astype(np.int64), "S": S}
+    def modality(gram):
+        if gram == 1:
+            S = A
+            D = D1
+        elif gram == 3:
+            S = A ** 3
+            idx = np.arange(S)
+            a, b, c = idx // (A * A), (idx // A) % A, idx % A
+            D = D1[a][:, a] + D1[b][:, b] + D1[c][:, c]
+        else:
+            raise ValueError("gram must be 1 or 3")
+        syms, ws, sizes = [], [], []
+        for k in range(N):
+            s_ = seq[k, :lens[k]]
+            if gram == 3:
+                s_ = s_[:-2] * (A * A) + s_[1:-1] * A + s_[2:]
+            vals, cnt = np.unique(s_, return_counts=True)
+            order = np.lexsort((vals, -cnt))[:mk_cap]
+            vals, cnt = vals[order], cnt[order].astype(np.float64)
+            syms.append(vals)
+            ws.append(cnt / cnt.sum())
+            sizes.append(len(vals))
+        offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+        return {"offsets": offsets,
+                "sym": np.concatenate(syms).astype(np.int32),
+                "W": np.concatenate(ws), "D": np.ascontiguousarray(D),
+                "classes": fam.astype(np.int64), "S": S}
+
+    if isinstance(gram, (tuple, list)):
+        # one instance = the histograms of several n-gram orders of the same
+        # sequence (multi-modal instances, Sec. 5)
+        return {"modalities": [modality(g) for g in gram],
+                "classes": fam.astype(np.int64)}
+    return modality(gram)
 
 
 def symbol_init_centroids(wl, labels, K, m):
@@ -271,6 +279,11 @@ WORKLOADS = {
                                   m=20, T=100, rounds=5, seed=6000),
     "protein_g3_n10742_k10": dict(kind="protein", N=10742, gram=3, K=10,
                                   m=32, T=100, rounds=5, seed=6100),
+    # multi-modal instances (Sec. 5): each sequence's amino-acid and
+    # tripeptide histograms, centroid sizes 20 and 32
+    "protein_g13_n10742_k10": dict(kind="protein", N=10742, gram=(1, 3),
+                                   K=10, m=(20, 32), T=100, rounds=5,
+                                   seed=6200),
 }
 
 

@@ -96,3 +96,18 @@ def test_counter_calibration(tmp_path):
     assert rec["fetch_scale"] == 2.0 and rec["write_scale"] == 1.0
     # mean raw per dispatch 200 KiB read (x2) and 100 KiB written
     assert rec["hbm_bytes_per_launch"] == (200.0 * 2.0 + 100.0) * 1024.0
+    # the library's copy probe takes precedence (median of its dispatches);
+    # two bucket dispatches per timed launch double the bytes per launch
+    write(fcsv, "FETCH_SIZE", [("__amd_rocclr_copyBuffer", 2048.0),
+                               ("k_copy_probe(float4*)", 4096.0),
+                               ("k_copy_probe(float4*)", 4000.0),
+                               ("k_copy_probe(float4*)", 4100.0),
+                               ("k_iter_ba<float>", 100.0),
+                               ("k_iter_ba<float>", 300.0)])
+    write(wcsv, "WRITE_SIZE", [("k_copy_probe(float4*)", 8192.0),
+                               ("k_iter_ba<float>", 50.0),
+                               ("k_iter_ba<float>", 150.0)])
+    rec = profiling.traffic(str(fcsv), str(wcsv), "k_iter_ba", "tiny", 8,
+                            str(tmp_path / "t.json"), "cmd", 2)
+    assert rec["fetch_scale"] == 2.0 and rec["write_scale"] == 1.0
+    assert rec["hbm_bytes_per_launch"] == 2 * (200.0 * 2.0 + 100.0) * 1024.0

@@ -216,8 +216,9 @@ def test_edge_shapes(d2):
 def test_large_d_cached_cost_path(d2, name, m):
     """d=64 (word-vector-bag shape, bf16-exact unit vectors), m=32, m_k in
     [8,64], and d=16 (m=16, m_k in [4,32]): the cost is cached per support
-    update instead of recomputed, and the support-update sums run on the
-    matrix cores."""
+    update instead of recomputed.  For d=64 the support-update sums and the
+    cost recomputation run on the matrix cores (FP32 MFMA, used for
+    32 <= d <= 64); for d=16 both run on the vector units."""
     print(f"[large_d {name}]", flush=True)
     wl = make_workload(name, N=1500)
     mem = pick_init_members(wl["offsets"], 3, m, 4)
