@@ -265,6 +265,54 @@ d2_status d2_cluster_multi(int32_t n_modal, d2_ctx* const* ctxs,
                            const d2_ot_params* op, d2_round_cb cb,
                            void* user);
 
+/* Parameters of the subgradient-descent centroid update (Appendix A,
+ * Algorithm "Centroid Update with Subgradient Descent").  Defaults: alpha
+ * 0.5, zeta 1, tau 10, iters 20, fixed_support 0, max_pivots 0. */
+typedef struct {
+  double alpha;          /* Eq. (stepsize): step length in log-weights    */
+  double zeta;           /* Eq. (stepsize): cap on alpha / ||gradient||   */
+  int32_t tau;           /* support update every tau iterations (>= 1)    */
+  int32_t iters;         /* iterations (>= 1)                             */
+  int32_t fixed_support; /* 1: never update the support                   */
+  int32_t max_pivots;    /* per transport LP; 0: 50 (m + max m_k)         */
+} d2_sg_params;
+
+typedef struct {
+  int32_t iters;     /* iterations run                                     */
+  int32_t lp_failed; /* transport LPs stopped by the pivot cap (summed)    */
+  int64_t pivots;    /* simplex pivots over all LPs                        */
+  int32_t launches;  /* kernel launches                                    */
+  int32_t pad;
+  double ms;         /* device time (HIP events)                           */
+} d2_sg_stats;
+
+/* Subgradient-descent centroid update for all K clusters of the current
+ * labels (Appendix A; the refinement the paper compares B-ADMM with, here
+ * usable from B-ADMM's centroids).  Every iteration n: the support update
+ * Eq. (updatex) from the previous iteration's plans when n > 0 and
+ * n % tau == 0 (never for symbolic supports or fixed_support = 1); for
+ * every instance the exact transport LP Eq. (primal) against its cluster's
+ * centroid (network simplex in FP64 on the device, one wavefront per
+ * instance) giving its plan and the duals of the row constraints; per
+ * cluster the mean over members of the duals minus their mean (Eq.
+ * (dualvar)), the gradient of the objective in s with w = softmax(s), the
+ * step Eq. (stepsize) sigma = min(alpha / ||grad_s||, zeta), s -= sigma
+ * grad_s, s -= mean(s), w = softmax(s).  At the start s = log w -
+ * mean(log w).  d2_objective then returns per iteration the exact
+ * objective (1/N_c) sum_k W^2 at that iteration's centroid (before its
+ * step); the last plans become the plan cache (Pi2 = Pi1 = the LP plans).
+ * An LP stopped by the pivot cap keeps its current basis (counted in
+ * stats->lp_failed).  stats may be NULL. */
+d2_status d2_subgradient(d2_ctx* ctx, const d2_sg_params* p,
+                         d2_sg_stats* stats);
+
+/* Hold rho at the given per-cluster values (K, finite, > 0) in the
+ * following d2_barycenter calls instead of Eq. (rho) (rho0 times the mean
+ * cost at the call's initial support; rho is the method's one
+ * hyper-parameter).  NULL returns to Eq. (rho).  New centroids of another
+ * K or m drop the values.  d2_objective reports the rho used. */
+d2_status d2_set_rho(d2_ctx* ctx, const double* rho);
+
 /* Objective trace of the last d2_barycenter: trace[n*K + c] =
  * (1/N_c) sum_k <C^(k), Pi1^(k)> of iteration n (0 for empty clusters);
  * `max_iters` bounds the rows written.  rho (K, may be NULL) gets each
@@ -309,6 +357,13 @@ d2_status d2_kernel_stats(d2_ctx* ctx, d2_kernel_stat* out, int32_t cap,
  * profiling on, launches are issued from the host so that each can be
  * bracketed by events. */
 d2_status d2_set_graph(d2_ctx* ctx, int32_t on);
+
+/* Cache policy of the plan state (Pi1, Lambda, cost cache) in the
+ * per-iteration kernel of FP32 contexts: 0 automatic (the default:
+ * non-temporal accesses when that state exceeds the 256 MiB last-level
+ * cache, else the default policy), 1 default policy, 2 non-temporal.
+ * Results do not depend on it (bitwise). */
+d2_status d2_set_cache_policy(d2_ctx* ctx, int32_t policy);
 
 /* Launch schedule of the barycenter kernels: instances per workgroup chunk
  * (1 .. 4096) and wavefronts per workgroup (1, 2 or 4).  Results do not
@@ -492,9 +547,14 @@ d2_status d2_ws_save(d2_ws* ws, const char* path);
 d2_status d2_ws_load(d2_ws* ws, const char* path);
 
 /* Attach a network for D2_INIT_LEARNED calls of d2_barycenter (NULL
- * detaches).  gate != 0 keeps the current centroid of a cluster unless the
- * proposal passes d2_ws_propose's gate.  The caller keeps the handle alive
- * while it is attached. */
+ * detaches).  gate 0: the proposal replaces every finite centroid; gate 1:
+ * the product-coupling bound of d2_ws_propose decides; gate >= 2: a probe
+ * decides -- B-ADMM runs `gate` iterations (product start) from the
+ * current centroid and from the proposal, and per cluster the start whose
+ * rounded-plan objective (d2_objective_feasible) is lower afterwards is
+ * kept (ties keep the current centroid); the call then starts from the
+ * kept centroids.  The caller keeps the handle alive while it is
+ * attached. */
 d2_status d2_set_warm_start(d2_ctx* ctx, d2_ws* ws, int32_t gate);
 
 /* Propose a centroid for every non-empty cluster of the context's current

@@ -42,8 +42,12 @@ def transport_lp(C, w, wy):
         A[i, i * mk:(i + 1) * mk] = 1.0
     for j in range(mk):
         A[m + j, j::mk] = 1.0
+    # feasibility tolerances far below HiGHS's defaults (1e-7), so that the
+    # plan and duals are exact to FP64 rounding
     res = linprog(C.ravel(), A_eq=A, b_eq=np.concatenate([w, wy]),
-                  bounds=(0, None), method="highs")
+                  bounds=(0, None), method="highs",
+                  options={"primal_feasibility_tolerance": 1e-10,
+                           "dual_feasibility_tolerance": 1e-10})
     if res.status != 0:
         raise RuntimeError("transport LP failed: " + res.message)
     return res.fun, res.x.reshape(m, mk), np.asarray(res.eqlin.marginals[:m])

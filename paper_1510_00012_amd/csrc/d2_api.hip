@@ -13,6 +13,7 @@
 #include "d2_ctx.hpp"
 #include "d2_kernels.hpp"
 #include "d2_lists.hpp"
+#include "d2_lp.hpp"
 
 static const char* kKindNames[kKinds] = {"rho_cost", "init_a", "iter_ba",
                                          "b_final", "xnum_only", "assign",
@@ -147,6 +148,9 @@ void free_centroids(d2_ctx* c) {
   free_bounds(c);
   dfree(c->d_csym);
   c->h_csym.clear();
+  dfree(c->d_rho_fix);
+  c->rho_fix_K = 0;
+  c->rho_fixed = false;
   dfree(c->d_cmu);
   dfree(c->d_crad);
   dfree(c->d_xct);
@@ -186,6 +190,13 @@ void free_instances(d2_ctx* c) {
   c->keys_cap = 0;
   dfree(c->d_dall);
   c->dall_cap = 0;
+  dfree(c->d_sgU);
+  dfree(c->d_sgval);
+  dfree(c->d_sgs);
+  dfree(c->d_sgfail);
+  dfree(c->d_sgpiv);
+  c->sg_N = 0;
+  c->sg_KMP = 0;
   c->hlab_ok = c->hcache_ok = true;
   c->cache_gen = ~0ull;
   dfree(c->d_labels);
@@ -858,6 +869,20 @@ d2_status join_side(d2_ctx* c, int n) {
   return D2_OK;
 }
 
+// Whether the hot kernel streams the plan state: per iteration it reads and
+// writes Pi1 and Lambda (and reads the cost cache for d > 4); beyond the
+// 256 MiB last-level cache the default policy only displaces lines that are
+// reused (measured: the d = 16, 2,000,000-instance workload 171.5 -> 146.8
+// ms per update, the d = 3, 65,536-instance one, whose state fits, 30 %
+// slower when streamed).
+bool stream_state(const d2_ctx* c) {
+  if (c->cache_policy == 1) return false;
+  if (c->cache_policy == 2) return true;
+  const double bytes = (double)c->h_pofs[c->N] * (double)c->esz() *
+                       (c->onfly ? 2.0 : 3.0);
+  return bytes > 256.0 * 1024.0 * 1024.0;
+}
+
 // One B-ADMM iteration: a launch per slot bucket, each kernel specialised
 // for its bucket's register slots (profiled as one "iter_ba" unit).
 template <typename T>
@@ -882,6 +907,9 @@ d2_status launch_ba(d2_ctx* c, const d2k::Args<T>& a, int& nl) {
                   c->d <= 64 && kt.bax[ilog2(c->MP) - 3][0] != nullptr;
   const bool cx = a.recost && xstage && !a.xout && c->d <= 64 &&
                   c->MP == 32 && kt.bcx[0] != nullptr;
+  // plan state far beyond the last-level cache (256 MiB on this part):
+  // the plain launches stream it (non-temporal)
+  const bool nt = stream_state(c) && kt.bapn[c->onfly ? 1 : 0][0][0] != nullptr;
   // the buckets' launches write disjoint chunk records: side by side
   {
     d2_status s = fork_side(c, c->nbk);
@@ -893,7 +921,8 @@ d2_status launch_ba(d2_ctx* c, const d2k::Args<T>& a, int& nl) {
               : cx      ? kt.bcx[rb]
               : (a.xout || a.recost)
                   ? kt.ba[c->onfly ? 1 : 0][ilog2(c->MP) - 3][rb]
-                  : kt.bap[c->onfly ? 1 : 0][ilog2(c->MP) - 3][rb];
+              : nt ? kt.bapn[c->onfly ? 1 : 0][ilog2(c->MP) - 3][rb]
+                   : kt.bap[c->onfly ? 1 : 0][ilog2(c->MP) - 3][rb];
     if (!fn) return c->fail(D2_EINVAL, "no kernel for this tile shape");
     d2k::Args<T> ab = a;
     ab.blist = c->d_blist;
@@ -935,6 +964,11 @@ d2_status issue_barycenter(d2_ctx* c, const d2_badmm_params* p, int& nl) {
   f.part = rec[1];
   if ((s = launch_aux<T>(c, a, d2k::kRho, nl))) return s;
   if ((s = launch_fin(c, f, d2k::kFinRho, nl))) return s;
+  if (c->rho_fixed && c->rho_fix_K == c->K) {
+    // rho held at the caller's values (d2_set_rho)
+    HIPCHK(c, hipMemcpyAsync(c->d_rho, c->d_rho_fix, sizeof(double) * K,
+                             hipMemcpyDeviceToDevice, c->stream));
+  }
   // A_0 from the initial plans and weights
   a.part = rec[0];
   a.xout = xupd(0) ? xrec[0] : nullptr;
@@ -972,7 +1006,9 @@ d2_status issue_barycenter(d2_ctx* c, const d2_badmm_params* p, int& nl) {
 }
 
 std::vector<double> graph_key(const d2_ctx* c, const d2_badmm_params* p) {
-  return {(double)p->iters, (double)p->tau, (double)p->fixed_support,
+  return {(double)c->rho_fixed, (double)stream_state(c), (double)p->iters,
+          (double)p->tau,
+          (double)p->fixed_support,
           (double)p->rule, p->eps, p->rho0, (double)c->waves,
           (double)c->nch_cap, (double)c->MP, (double)c->R, (double)c->onfly,
           (double)c->dt, (double)c->K, (double)c->nbk,
@@ -1941,6 +1977,43 @@ d2_status d2_assign_pairs(const d2_ctx* c, int64_t* evaluated,
   return D2_OK;
 }
 
+// Probe gate of the learned warm start: a short B-ADMM run (ws_gate
+// iterations, product start) from the current centroid and from the
+// network's proposal; per cluster the start whose rounded-plan objective
+// (an upper bound on Eq. (centroid), see d2_objective_feasible) is lower
+// after the probe is kept (ties keep the current centroid).  Leaves the
+// chosen starting centroids set and no plan cache.
+static d2_status probe_gate(d2_ctx* c, const d2_badmm_params* p) {
+  const int K = c->K, m = c->m, d = c->d;
+  d2_status s;
+  std::vector<double> X0((size_t)K * m * d), W0((size_t)K * m);
+  std::vector<double> X1(X0.size()), W1(W0.size()), F0(K), F1(K);
+  if ((s = d2_centroids_get(c, X0.data(), W0.data()))) return s;
+  d2_badmm_params q = *p;
+  q.iters = c->ws_gate;
+  q.init = D2_INIT_PRODUCT;
+  if ((s = d2_ws_propose(c->ws, c, 0, nullptr, nullptr, nullptr))) {
+    const char* e = d2_ws_last_error(c->ws);
+    return c->fail(s, std::string("warm-start proposal: ") + (e ? e : ""));
+  }
+  if ((s = d2_centroids_get(c, X1.data(), W1.data()))) return s;
+  if ((s = d2_barycenter(c, &q, nullptr))) return s;
+  if ((s = d2_objective_feasible(c, nullptr, F1.data()))) return s;
+  if ((s = centroids_set_impl(c, K, m, X0.data(), W0.data()))) return s;
+  if ((s = d2_barycenter(c, &q, nullptr))) return s;
+  if ((s = d2_objective_feasible(c, nullptr, F0.data()))) return s;
+  for (int q2 = 0; q2 < K; ++q2)
+    if (F1[q2] < F0[q2]) {
+      std::copy(&X1[(size_t)q2 * m * d], &X1[(size_t)(q2 + 1) * m * d],
+                &X0[(size_t)q2 * m * d]);
+      std::copy(&W1[(size_t)q2 * m], &W1[(size_t)(q2 + 1) * m],
+                &W0[(size_t)q2 * m]);
+    }
+  if ((s = centroids_set_impl(c, K, m, X0.data(), W0.data()))) return s;
+  c->have_cache = false;
+  return D2_OK;
+}
+
 d2_status d2_barycenter(d2_ctx* c, const d2_badmm_params* p,
                         d2_badmm_stats* st) {
   if (!c) return D2_EINVAL;
@@ -1961,8 +2034,10 @@ d2_status d2_barycenter(d2_ctx* c, const d2_badmm_params* p,
     // the network proposes each cluster's starting centroid from its
     // members (gated against the current centroid); plans start from the
     // product coupling
-    if ((s = d2_ws_propose(c->ws, c, c->ws_gate, nullptr, nullptr,
-                           nullptr))) {
+    if (c->ws_gate >= 2) {
+      if ((s = probe_gate(c, p))) return s;
+    } else if ((s = d2_ws_propose(c->ws, c, c->ws_gate, nullptr, nullptr,
+                                  nullptr))) {
       const char* e = d2_ws_last_error(c->ws);
       return c->fail(s, std::string("warm-start proposal: ") + (e ? e : ""));
     }
@@ -2163,6 +2238,173 @@ d2_status d2_cluster_multi(int32_t n_modal, d2_ctx* const* ctxs,
   return D2_OK;
 }
 
+d2_status d2_subgradient(d2_ctx* c, const d2_sg_params* p, d2_sg_stats* st) {
+  if (!c) return D2_EINVAL;
+  if (!c->N || !c->K) return c->fail(D2_ESTATE, "need instances, centroids");
+  if (!c->have_labels) return c->fail(D2_ESTATE, "need labels");
+  if (!p || p->iters < 1 || p->tau < 1 || !(p->alpha > 0.0) ||
+      !(p->zeta > 0.0) || p->max_pivots < 0)
+    return c->fail(D2_EINVAL, "bad subgradient parameters");
+  HIPCHK(c, hipSetDevice(c->device));
+  d2_status s;
+  if ((s = ensure_plans(c))) return s;
+  if ((s = build_lists(c, false))) return s;
+  const int K = c->K, MP = c->MP, T_ = p->iters;
+  const int64_t N = c->N;
+  if (c->sg_N != N || c->sg_KMP != K * MP) {
+    dfree(c->d_sgU);
+    dfree(c->d_sgval);
+    dfree(c->d_sgs);
+    dfree(c->d_sgfail);
+    dfree(c->d_sgpiv);
+    c->sg_N = 0;
+    if ((s = dalloc(c, (void**)&c->d_sgU, sizeof(double) * N * MP))) return s;
+    if ((s = dalloc(c, (void**)&c->d_sgval, sizeof(double) * N))) return s;
+    if ((s = dalloc(c, (void**)&c->d_sgs, sizeof(double) * K * MP))) return s;
+    if ((s = dalloc(c, (void**)&c->d_sgfail, sizeof(int)))) return s;
+    if ((s = dalloc(c, (void**)&c->d_sgpiv, sizeof(unsigned long long))))
+      return s;
+    c->sg_N = N;
+    c->sg_KMP = K * MP;
+  }
+  if (T_ > c->trace_cap) {
+    drop_graph(c);
+    dfree(c->d_trace);
+    dfree(c->d_rtrace);
+    c->trace_cap = 0;
+    if ((s = dalloc(c, (void**)&c->d_trace, sizeof(double) * T_ * K)))
+      return s;
+    if ((s = dalloc(c, (void**)&c->d_rtrace, sizeof(double) * T_ * K)))
+      return s;
+    c->trace_cap = T_;
+  }
+  HIPCHK(c, hipMemsetAsync(c->d_trace, 0, sizeof(double) * T_ * K, c->stream));
+  HIPCHK(c, hipMemsetAsync(c->d_rtrace, 0, sizeof(double) * T_ * K,
+                           c->stream));
+  HIPCHK(c, hipMemsetAsync(c->d_sgfail, 0, sizeof(int), c->stream));
+  HIPCHK(c, hipMemsetAsync(c->d_sgpiv, 0, sizeof(unsigned long long),
+                           c->stream));
+  const size_t xbytes = sizeof(double) * (size_t)K * MP * c->d;
+  const size_t wbytes = sizeof(double) * (size_t)K * MP;
+  HIPCHK(c, hipMemcpyAsync(c->d_xsave, c->d_xc, xbytes,
+                           hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->d_wsave, c->d_wc, wbytes,
+                           hipMemcpyDeviceToDevice, c->stream));
+  d2s::LpArgs la;
+  la.off = c->d_off;
+  la.pofs = c->d_pofs;
+  la.labels = c->d_labels;
+  la.xc = c->d_xc;
+  la.wc = c->d_wc;
+  la.X = c->d_X;
+  la.W = c->d_W;
+  la.dsym = c->sym ? c->d_D : nullptr;
+  la.isym = c->d_isym;
+  la.csym = c->d_csym;
+  la.S = c->S;
+  la.P1 = c->d_P1;
+  la.P2 = c->d_P2;
+  la.U = c->d_sgU;
+  la.val = c->d_sgval;
+  la.fail = c->d_sgfail;
+  la.pivots = c->d_sgpiv;
+  la.N = N;
+  la.m = c->m;
+  la.MP = MP;
+  la.d = c->d;
+  la.xs = c->xs;
+  la.mkmax = c->mk_max;
+  la.max_pivots = p->max_pivots > 0 ? p->max_pivots
+                                    : 50 * (c->m + c->mk_max);
+  la.f64 = c->dt == D2_F64 ? 1 : 0;
+  const size_t per = d2s::lp_lds_bytes(MP, c->mk_max);
+  int lw = 4;
+  while (lw > 1 && per * lw > 64 * 1024) --lw;
+  const unsigned lgrid = (unsigned)((N + lw - 1) / lw);
+  d2s::StepArgs sa;
+  sa.work = c->d_work;
+  sa.chunks = c->d_chunks;
+  sa.ctab = c->d_ctab;
+  sa.U = c->d_sgU;
+  sa.val = c->d_sgval;
+  sa.s = c->d_sgs;
+  sa.wc = c->d_wc;
+  sa.alpha = p->alpha;
+  sa.zeta = p->zeta;
+  sa.m = c->m;
+  sa.MP = MP;
+  const bool xupd = !p->fixed_support && !c->sym;
+  HIPCHK(c, hipEventRecord(c->ev0, c->stream));
+  hipLaunchKernelGGL(d2s::k_sg_init, dim3((K + 63) / 64), dim3(64), 0,
+                     c->stream, c->d_sgs, c->d_wc, K, c->m, MP);
+  HIPCHK(c, hipGetLastError());
+  int nl = 1;
+  for (int n = 0; n < T_; ++n) {
+    if (xupd && n > 0 && n % p->tau == 0) {
+      // Eq. (updatex) from the previous iteration's exact plans (Pi2)
+      if (c->dt == D2_F64) {
+        auto a = make_args<double>(c, nullptr);
+        a.xout = c->d_partx;
+        if ((s = launch_aux<double>(c, a, d2k::kXO, nl))) return s;
+      } else {
+        auto a = make_args<float>(c, nullptr);
+        a.xout = c->d_partx;
+        if ((s = launch_aux<float>(c, a, d2k::kXO, nl))) return s;
+      }
+      if ((s = launch_fin(c, make_fin(c, nullptr), d2k::kFinX, nl))) return s;
+    }
+    hipLaunchKernelGGL(d2s::k_lp_transport, dim3(lgrid), dim3(64 * lw),
+                       per * lw, c->stream, la);
+    HIPCHK(c, hipGetLastError());
+    sa.trace = c->d_trace + (size_t)n * K;
+    hipLaunchKernelGGL(d2s::k_sg_step, dim3(K), dim3(256), 0, c->stream, sa);
+    HIPCHK(c, hipGetLastError());
+    nl += 2;
+  }
+  HIPCHK(c, hipEventRecord(c->ev1, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  float ms = 0.f;
+  HIPCHK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+  int nfail = 0;
+  unsigned long long npiv = 0;
+  HIPCHK(c, hipMemcpy(&nfail, c->d_sgfail, sizeof(int), hipMemcpyDeviceToHost));
+  HIPCHK(c, hipMemcpy(&npiv, c->d_sgpiv, sizeof(npiv), hipMemcpyDeviceToHost));
+  std::vector<double> hx((size_t)K * MP * c->d), hw((size_t)K * MP);
+  HIPCHK(c, hipMemcpy(hx.data(), c->d_xc, hx.size() * 8,
+                      hipMemcpyDeviceToHost));
+  HIPCHK(c, hipMemcpy(hw.data(), c->d_wc, hw.size() * 8,
+                      hipMemcpyDeviceToHost));
+  if (!finite_all(hx.data(), hx.size()) || !finite_all(hw.data(), hw.size())) {
+    HIPCHK(c, hipMemcpy(c->d_xc, c->d_xsave, xbytes, hipMemcpyDeviceToDevice));
+    HIPCHK(c, hipMemcpy(c->d_wc, c->d_wsave, wbytes, hipMemcpyDeviceToDevice));
+    c->have_cache = false;
+    c->trace_rows = 0;
+    return c->fail(D2_ENUMERIC, "non-finite centroid support or weights "
+                                "(centroids restored)");
+  }
+  // the last iteration's exact plans are the plan cache (Pi2 rows sum to
+  // the weights used by that iteration); Lambda has no meaning here
+  HIPCHK(c, hipMemsetAsync(c->d_L, 0, (size_t)c->h_pofs[N] * c->esz(),
+                           c->stream));
+  c->trace_rows = T_;
+  HIPCHK(c, hipMemcpyAsync(c->d_cache_labels, c->d_labels,
+                           sizeof(int32_t) * N, hipMemcpyDeviceToDevice,
+                           c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->cache_gen = c->label_gen;
+  c->hcache_ok = c->hlab_ok;
+  if (c->hlab_ok) c->h_cache_labels = c->h_labels;
+  c->have_cache = true;
+  if (st) {
+    st->iters = T_;
+    st->lp_failed = nfail;
+    st->pivots = (int64_t)npiv;
+    st->launches = nl;
+    st->ms = ms;
+  }
+  return D2_OK;
+}
+
 d2_status d2_objective(d2_ctx* c, double* trace, int32_t max_iters,
                        double* rho) {
   if (!c) return D2_EINVAL;
@@ -2245,8 +2487,35 @@ d2_status d2_kernel_stats(d2_ctx* c, d2_kernel_stat* out, int32_t cap,
 
 d2_status d2_set_warm_start(d2_ctx* c, d2_ws* ws, int32_t gate) {
   if (!c) return D2_EINVAL;
+  if (gate < 0) return c->fail(D2_EINVAL, "gate must be >= 0");
   c->ws = ws;
-  c->ws_gate = gate ? 1 : 0;
+  c->ws_gate = gate;
+  return D2_OK;
+}
+
+d2_status d2_set_rho(d2_ctx* c, const double* rho) {
+  if (!c) return D2_EINVAL;
+  if (!rho) {
+    if (c->rho_fixed) drop_graph(c);
+    c->rho_fixed = false;
+    return D2_OK;
+  }
+  if (!c->K) return c->fail(D2_ESTATE, "set centroids first");
+  for (int q = 0; q < c->K; ++q)
+    if (!(rho[q] > 0.0) || !std::isfinite(rho[q]))
+      return c->fail(D2_EINVAL, "rho must be finite and > 0");
+  HIPCHK(c, hipSetDevice(c->device));
+  if (!c->d_rho_fix || c->rho_fix_K != c->K) {
+    dfree(c->d_rho_fix);
+    drop_graph(c);
+    d2_status s = dalloc(c, (void**)&c->d_rho_fix, sizeof(double) * c->K);
+    if (s) return s;
+    c->rho_fix_K = c->K;
+  }
+  HIPCHK(c, hipMemcpy(c->d_rho_fix, rho, sizeof(double) * c->K,
+                      hipMemcpyHostToDevice));
+  if (!c->rho_fixed) drop_graph(c);
+  c->rho_fixed = true;
   return D2_OK;
 }
 
@@ -2258,6 +2527,14 @@ d2_status d2_set_assign_bounds(d2_ctx* c, int32_t on) {
     free_bounds(c);
   }
   c->use_lbs = on != 0;
+  return D2_OK;
+}
+
+d2_status d2_set_cache_policy(d2_ctx* c, int32_t policy) {
+  if (!c) return D2_EINVAL;
+  if (policy < 0 || policy > 2)
+    return c->fail(D2_EINVAL, "cache policy must be 0, 1 or 2");
+  c->cache_policy = policy;
   return D2_OK;
 }
 

@@ -49,6 +49,10 @@ struct d2_ctx {
   double* d_xsave = nullptr;  // centroids at the start of a barycenter call
   double* d_wsave = nullptr;  // (restored if it fails numerically)
   double* d_rho = nullptr;
+  // rho held at caller values (d2_set_rho) instead of Eq. (rho)
+  double* d_rho_fix = nullptr;
+  int rho_fix_K = 0;
+  bool rho_fixed = false;
   int* d_cnt = nullptr;
   // labels: d_labels is authoritative; h_labels mirrors it when hlab_ok
   // (the assignment leaves the labels on the device).  d_cache_labels are
@@ -65,6 +69,15 @@ struct d2_ctx {
   int64_t* d_nchg = nullptr;         // label changes of the last assignment
   double* d_dall = nullptr;          // N x K summed multi-modal distances
   size_t dall_cap = 0;
+  // subgradient refinement: per-instance projected duals (N x MP) and LP
+  // values, per-cluster log-weights (K x MP), failure / pivot counters
+  double* d_sgU = nullptr;
+  double* d_sgval = nullptr;
+  double* d_sgs = nullptr;
+  int* d_sgfail = nullptr;
+  unsigned long long* d_sgpiv = nullptr;
+  int64_t sg_N = 0;
+  int sg_KMP = 0;
   double* d_best = nullptr;
   int32_t* d_pairs = nullptr;  // N x 2: per instance of the last assignment,
                                // transports run and cost blocks formed
@@ -111,6 +124,10 @@ struct d2_ctx {
   int* d_bcnt = nullptr;
   int blist_cap = 0;
   int bucket_min_pct = 100;
+  // cache policy of the plan state in the hot kernel: 0 automatic
+  // (streaming when the state per iteration exceeds the last-level
+  // cache), 1 default caching, 2 streaming (non-temporal)
+  int cache_policy = 0;
   // pinned staging for the per-call list uploads (one host copy, async
   // transfers; stage_ev marks the end of the last batch of transfers)
   uint8_t* h_stage = nullptr;

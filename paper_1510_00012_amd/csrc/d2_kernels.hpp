@@ -705,30 +705,42 @@ __device__ __forceinline__ Rsrc make_rsrc(const void* base, uint32_t bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0,
                                            (int)bytes, kRsrcWord3);
 }
-template <typename T> __device__ __forceinline__ T bload(Rsrc r, uint32_t o);
-template <> __device__ __forceinline__ float bload<float>(Rsrc r, uint32_t o) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, o, 0, 0));
-}
-template <> __device__ __forceinline__ double bload<double>(Rsrc r, uint32_t o) {
-  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, o, 0, 0));
-}
-template <> __device__ __forceinline__ float4 bload<float4>(Rsrc r, uint32_t o) {
-  return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, o, 0, 0));
-}
-template <> __device__ __forceinline__ double4 bload<double4>(Rsrc r, uint32_t o) {
+// 32-byte loads (double4) as two 16-byte loads
+template <typename T>
+__device__ __forceinline__ T bload_wide(Rsrc r, uint32_t o) {
   const double2 lo = __builtin_bit_cast(
       double2, __builtin_amdgcn_raw_buffer_load_b128(r, o, 0, 0));
   const double2 hi = __builtin_bit_cast(
       double2, __builtin_amdgcn_raw_buffer_load_b128(r, o + 16u, 0, 0));
   return make_double4(lo.x, lo.y, hi.x, hi.y);
 }
-__device__ __forceinline__ void bstore(float v, Rsrc r, uint32_t o) {
-  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, o, 0, 0);
+
+// Cache policy bits of buffer instructions: 0 = the default policy,
+// kCpolStream = non-temporal (the line is not kept for reuse).  The hot
+// kernel streams its plan state (Pi1, Lambda, cost cache) this way when the
+// state is far larger than the last-level cache, so that it does not
+// displace what is reused (supports, weights, records).
+constexpr int kCpolStream = 2;
+template <typename T, int CP = 0>
+__device__ __forceinline__ T bload(Rsrc r, uint32_t o) {
+  if constexpr (sizeof(T) == 4)
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, o, 0, CP));
+  else if constexpr (sizeof(T) == 8)
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, o, 0, CP));
+  else if constexpr (sizeof(T) == 16)
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b128(r, o, 0, CP));
+  else
+    return bload_wide<T>(r, o);
 }
+template <int CP = 0>
+__device__ __forceinline__ void bstore(float v, Rsrc r, uint32_t o) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, o, 0, CP);
+}
+template <int CP = 0>
 __device__ __forceinline__ void bstore(double v, Rsrc r, uint32_t o) {
   __builtin_amdgcn_raw_buffer_store_b64(
       __builtin_bit_cast(__attribute__((ext_vector_type(2))) uint32_t, v), r, o,
-      0, 0);
+      0, CP);
 }
 
 // Support-update sums on the matrix cores (FP32 MFMA, d <= 64, MP = 32 or
@@ -859,7 +871,7 @@ __device__ __forceinline__ void cost_mfma(const Args<float>& a,
   }
 }
 
-template <typename T, int MP, int NS, bool ONFLY, int VAR>
+template <typename T, int MP, int NS, bool ONFLY, int VAR, int CP>
 __device__ __forceinline__ void ba_tile(const Args<T>& a, const Tile<T, MP>& tl,
                                         const T (&xr)[4], const double* xrow,
                                         const T* xl, T xnorm, T wi, T rho,
@@ -885,16 +897,17 @@ __device__ __forceinline__ void ba_tile(const Args<T>& a, const Tile<T, MP>& tl,
     const uint32_t j = (uint32_t)tl.col(r);
     eo[r] = tl.rowok ? (j * (uint32_t)a.m + (uint32_t)tl.i) * es : kOob;
     el[r] = tl.valid(r) ? eps : T(0);
-    p[r] = bload<T>(rP, eo[r]);
-    l[r] = bload<T>(rL, eo[r]);
+    p[r] = bload<T, CP>(rP, eo[r]);
+    l[r] = bload<T, CP>(rL, eo[r]);
     wk[r] = bload<T>(rW, j * es);
     if constexpr (ONFLY) {
       cs[r] = cost4<T>(xr, bload<V4>(rX, j * (uint32_t)sizeof(V4)));
     } else if constexpr (VAR == kVarPlain) {
-      cs[r] = bload<T>(rC, eo[r]);  // plain launches never recompute
+      // plain launches never recompute
+      cs[r] = bload<T, CP>(rC, eo[r]);
     } else {
       if (!a.recost)
-        cs[r] = bload<T>(rC, eo[r]);
+        cs[r] = bload<T, CP>(rC, eo[r]);
       else if (VAR != kVarCost && !xl)
         cs[r] = cost_generic<T>(xrow, a.X + (tl.o + tl.colc(r)) * a.xs, a.d);
     }
@@ -914,8 +927,8 @@ __device__ __forceinline__ void ba_tile(const Args<T>& a, const Tile<T, MP>& tl,
   accf += (double)f;
 #pragma unroll
   for (int r = 0; r < NS; ++r) {
-    bstore(p[r], rP, eo[r]);
-    bstore(l[r], rL, eo[r]);
+    bstore<CP>(p[r], rP, eo[r]);
+    bstore<CP>(l[r], rL, eo[r]);
   }
   if constexpr (!ONFLY && VAR != kVarPlain) {
     if (a.recost) {
@@ -942,7 +955,8 @@ __device__ __forceinline__ void ba_tile(const Args<T>& a, const Tile<T, MP>& tl,
 // kernels leave out the support terms and the cost recomputation
 // altogether and serve the launches that do neither (most of them).  Separate kernels so that the
 // registers of the rarer launches do not lower the occupancy of the others.
-template <typename T, int MP, int R, bool ONFLY, int VAR = kVarNone>
+template <typename T, int MP, int R, bool ONFLY, int VAR = kVarNone,
+          int CP = 0>
 __global__ void __launch_bounds__(256) k_iter_ba(Args<T> a) {
   extern __shared__ double s_dyn[];  // [nwaves][MP][d+1] support terms
   __shared__ double s_w[MP];
@@ -1015,8 +1029,9 @@ __global__ void __launch_bounds__(256) k_iter_ba(Args<T> a) {
       tl.set(a.m, a.off[k], a.off[k + 1], a.pofs[k]);
     }
     with_slots<R>(tl.nsl, [&]<int NS>() {
-      ba_tile<T, MP, NS, ONFLY, VAR>(a, tl, xr, xrow, xl, xnorm, wi, rho, a2,
-                                     eps, accw, accf, accr, accx, sap, xa4);
+      ba_tile<T, MP, NS, ONFLY, VAR, CP>(a, tl, xr, xrow, xl, xnorm, wi, rho,
+                                         a2, eps, accw, accf, accr, accx, sap,
+                                         xa4);
     });
   }
   if constexpr (VAR == kVarSupport) sacc.flush(a.d, accx);
@@ -1743,6 +1758,7 @@ template <typename T> struct KernTable {
   using AS = void (*)(AssignArgs<T>);
   BA ba[2][4][6] = {};  // [onfly][mp][r]
   BA bap[2][4][6] = {}; // the same without support terms
+  BA bapn[2][4][6] = {}; // bap streaming its plan state (FP32)
   BA bax[4][6] = {};    // support-update launches, FP32, d > 4, MP 16 / 32
   BA bcx[6] = {};       // cost-recomputation launches, FP32, d <= 64, MP 32
   AX aux[4][6] = {};

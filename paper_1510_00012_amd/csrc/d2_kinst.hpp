@@ -14,6 +14,10 @@ void add_kernels(KernTable<T>& t) {
     // launches that form no support terms
     t.bap[0][a][b] = &k_iter_ba<T, MP, R, false, kVarPlain>;
     t.bap[1][a][b] = &k_iter_ba<T, MP, R, true, kVarPlain>;
+    if constexpr (sizeof(T) == 4) {
+      t.bapn[0][a][b] = &k_iter_ba<T, MP, R, false, kVarPlain, kCpolStream>;
+      t.bapn[1][a][b] = &k_iter_ba<T, MP, R, true, kVarPlain, kCpolStream>;
+    }
     t.auxm[0][a][b] = &k_aux<T, MP, R, kRho>;
     t.auxm[1][a][b] = &k_aux<T, MP, R, kA0>;
     t.auxm[2][a][b] = &k_aux<T, MP, R, kBF>;

@@ -37,7 +37,8 @@ EXPORTS = [
     "d2_ws_params_get", "d2_ws_targets_from", "d2_ws_grad",
     "d2_ws_train_step", "d2_ws_propose", "d2_assign_noalloc",
     "d2_load_instances_symbolic", "d2_centroids_set_symbolic",
-    "d2_assign_multi", "d2_cluster_multi",
+    "d2_assign_multi", "d2_cluster_multi", "d2_subgradient",
+    "d2_set_cache_policy", "d2_set_rho",
 ]
 
 
@@ -75,6 +76,19 @@ class WsOpt(ctypes.Structure):
     _fields_ = [("lr", ctypes.c_double), ("beta1", ctypes.c_double),
                 ("beta2", ctypes.c_double), ("eps", ctypes.c_double),
                 ("clip", ctypes.c_double)]
+
+
+class SgParams(ctypes.Structure):
+    _fields_ = [("alpha", ctypes.c_double), ("zeta", ctypes.c_double),
+                ("tau", ctypes.c_int32), ("iters", ctypes.c_int32),
+                ("fixed_support", ctypes.c_int32),
+                ("max_pivots", ctypes.c_int32)]
+
+
+class SgStats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("lp_failed", ctypes.c_int32),
+                ("pivots", ctypes.c_int64), ("launches", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("ms", ctypes.c_double)]
 
 
 class KernelStat(ctypes.Structure):
@@ -164,6 +178,10 @@ def load_library(path: str = LIB_PATH):
         "d2_load_instances_symbolic": ([_p, _i64, _p, _p, _p, _i32, _p],
                                        ctypes.c_int),
         "d2_centroids_set_symbolic": ([_p, _i32, _i32, _p, _p], ctypes.c_int),
+        "d2_set_cache_policy": ([_p, _i32], ctypes.c_int),
+        "d2_set_rho": ([_p, _p], ctypes.c_int),
+        "d2_subgradient": ([_p, ctypes.POINTER(SgParams),
+                            ctypes.POINTER(SgStats)], ctypes.c_int),
         "d2_assign_multi": ([_i32, _p, ctypes.POINTER(OtParams), _p, _p, _p],
                             ctypes.c_int),
         "d2_cluster_multi": ([_i32, _p, _i32, ctypes.POINTER(BadmmParams),
@@ -314,10 +332,13 @@ class D2Context:
         self.K, self.m = K.value, m.value
 
     def set_warm_start(self, ws, gate=True):
-        """Attach a D2WarmStart for init=D2_INIT_LEARNED (None detaches)."""
+        """Attach a D2WarmStart for init=D2_INIT_LEARNED (None detaches).
+        gate: False / 0 none, True / 1 the product-coupling bound, an int
+        >= 2 a B-ADMM probe of that many iterations."""
         self._ws = ws
+        g = int(gate) if not isinstance(gate, bool) else int(gate)
         self._chk(self.lib.d2_set_warm_start(
-            self.h, None if ws is None else ws.h, int(bool(gate))))
+            self.h, None if ws is None else ws.h, g))
 
     def centroids_set(self, Xc, Wc):
         Xc = _c(Xc, np.float64)
@@ -369,6 +390,17 @@ class D2Context:
                                          ctypes.byref(s)))
         return {"iters": s.iters, "n_empty": s.n_empty,
                 "launches": s.launches, "graph": s.graph, "ms": s.ms}
+
+    def subgradient(self, iters=20, tau=10, alpha=0.5, zeta=1.0,
+                    fixed_support=False, max_pivots=0):
+        """d2_subgradient (Appendix A refinement) on the current labels."""
+        p = SgParams(alpha=alpha, zeta=zeta, tau=tau, iters=iters,
+                     fixed_support=int(fixed_support), max_pivots=max_pivots)
+        s = SgStats()
+        self._chk(self.lib.d2_subgradient(self.h, ctypes.byref(p),
+                                          ctypes.byref(s)))
+        return {"iters": s.iters, "lp_failed": s.lp_failed,
+                "pivots": s.pivots, "launches": s.launches, "ms": s.ms}
 
     def assign_pairs(self):
         """(pairs iterated, total pairs) of the last assignment."""
@@ -435,6 +467,16 @@ class D2Context:
     def set_assign_bounds(self, on=True):
         """Cross-round lower bounds of the pruned assignment on / off."""
         self._chk(self.lib.d2_set_assign_bounds(self.h, int(bool(on))))
+
+    def set_rho(self, rho):
+        """Hold rho per cluster (K values) in later barycenter calls; None
+        returns to Eq. (rho)."""
+        r = None if rho is None else _c(rho, np.float64)
+        self._chk(self.lib.d2_set_rho(self.h, _ptr(r)))
+
+    def set_cache_policy(self, policy):
+        """0 automatic, 1 default caching, 2 streaming plan state."""
+        self._chk(self.lib.d2_set_cache_policy(self.h, int(policy)))
 
     def set_graph(self, on=True):
         self._chk(self.lib.d2_set_graph(self.h, int(bool(on))))

@@ -2,6 +2,8 @@
 
 Usage (after the rocprofv3 runs, on any machine):
   python -m paper_1510_00012_amd.profiling trace  <kernel_stats.csv> <out.md> <cmd>
+  python -m paper_1510_00012_amd.profiling counters <counter.csv> <out.md> \
+      <cmd> <kernel substrings, comma separated>
   python -m paper_1510_00012_amd.profiling traffic <fetch_counter.csv> \
       <write_counter.csv> <kernel-substring> <workload> <copy_mib> <out.json> \
       <cmd> [dispatches per timed launch]
@@ -113,10 +115,50 @@ def traffic(fetch_csv, write_csv, kernel_sub, workload, copy_mib, out_json,
     return rec
 
 
+def counters(counter_csv, out_md, cmd, kernels, cu_num=256, simd_per_cu=4):
+    """Per-kernel averages of the counters of one rocprofv3 --pmc run and
+    the derived utilisations: MFMA busy = SQ_VALU_MFMA_BUSY_CYCLES /
+    (GRBM_GUI_ACTIVE * SIMDs), VALU busy = SQ_ACTIVE_INST_VALU / (CUs *
+    GRBM_GUI_ACTIVE) (the definitions rocprofv3 lists for MfmaUtil and
+    VALUBusy).  kernels: comma-separated substrings of the kernels kept."""
+    subs = [k for k in kernels.split(",") if k]
+    agg = defaultdict(lambda: defaultdict(list))
+    for r in csv.DictReader(open(counter_csv)):
+        name = r["Kernel_Name"]
+        if subs and not any(k in name for k in subs):
+            continue
+        agg[name][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    names = sorted({c for v in agg.values() for c in v})
+    lines = ["# rocprofv3 counter summary", "", f"Command: `{cmd}`", "",
+             f"Kernel source hash: `{kernel_source_hash()}`", "",
+             "| kernel | dispatches | " + " | ".join(names) +
+             " | MFMA busy % | VALU busy % |",
+             "|---" * (len(names) + 4) + "|"]
+    rows = {}
+    for k in sorted(agg):
+        av = {c: sum(v) / len(v) for c, v in agg[k].items()}
+        n = max(len(v) for v in agg[k].values())
+        g = av.get("GRBM_GUI_ACTIVE")
+        mf = (100.0 * av["SQ_VALU_MFMA_BUSY_CYCLES"] / (g * cu_num * simd_per_cu)
+              if g and "SQ_VALU_MFMA_BUSY_CYCLES" in av else None)
+        vb = (100.0 * av["SQ_ACTIVE_INST_VALU"] / (cu_num * g)
+              if g and "SQ_ACTIVE_INST_VALU" in av else None)
+        rows[k] = {"dispatches": n, **av, "mfma_busy_pct": mf,
+                   "valu_busy_pct": vb}
+        fmt = lambda v: "-" if v is None else f"{v:.4g}"
+        lines.append(f"| `{k[:80]}` | {n} | " +
+                     " | ".join(fmt(av.get(c)) for c in names) +
+                     f" | {fmt(mf)} | {fmt(vb)} |")
+    open(out_md, "w").write("\n".join(lines) + "\n")
+    return rows
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "trace":
         trace_summary(sys.argv[2], sys.argv[3], sys.argv[4])
     elif sys.argv[1] == "traffic":
         print(json.dumps(traffic(*sys.argv[2:]), indent=1))
+    elif sys.argv[1] == "counters":
+        counters(*sys.argv[2:6])
     else:
         raise SystemExit(__doc__)

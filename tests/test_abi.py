@@ -37,6 +37,10 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(d2.OtParams) == 24
     assert ctypes.sizeof(d2.BadmmStats) == 24
     assert ctypes.sizeof(d2.RoundInfo) == 40
+    # d2_sg_params: 2 doubles + 4 int32; d2_sg_stats: 2 int32, int64,
+    # 2 int32, double
+    assert ctypes.sizeof(d2.SgParams) == 32
+    assert ctypes.sizeof(d2.SgStats) == 32
 
 
 def test_create_without_gpu_fails_cleanly():

@@ -687,3 +687,34 @@ def test_assignment_cross_round_bounds_exact(d2, name, N, K, m):
                 scale = 1e-3 * np.abs(Xc).mean()
             Xc = Xc + scale * rng.standard_normal(Xc.shape)
             Wc = Wc / Wc.sum(1, keepdims=True)
+
+
+@pytest.mark.parametrize("name,m", [("gmm_d3_n65536_k16", 16),
+                                    ("gmm_d16_n2000000_k256", 16)])
+def test_cache_policy_is_bitwise_neutral(d2, name, m):
+    """The streaming (non-temporal) plan-state accesses of the per-iteration
+    kernel change where lines are kept, not what is computed: forced on and
+    forced off give bitwise the same traces, centroids and plans (on the
+    on-the-fly cost path, d = 3, and the cached-cost path, d = 16)."""
+    print(f"[cache policy {name}]", flush=True)
+    wl = make_workload(name, N=3000)
+    mem = pick_init_members(wl["offsets"], 3, m, 9)
+    Xc, Wc = oracle.init_centroids(wl, mem, m)
+    lab, _, _ = oracle.assign(wl, Xc, Wc, T=20)
+    out = []
+    for policy in (1, 2):
+        with _ctx(d2, wl, "f32") as ctx:
+            ctx.set_cache_policy(policy)
+            ctx.centroids_set(Xc, Wc)
+            ctx.labels_set(lab)
+            ctx.barycenter(iters=25, tau=10, init=d2.D2_INIT_PRODUCT)
+            tr, _ = ctx.objective(25)
+            X, W = ctx.centroids_get()
+            P = [ctx.plans_get(k) for k in range(0, 3000, 97)]
+            out.append((tr, X, W, P))
+    (t1, x1, w1, p1), (t2, x2, w2, p2) = out
+    assert np.array_equal(t1, t2) and np.array_equal(x1, x2)
+    assert np.array_equal(w1, w2)
+    for a, b in zip(p1, p2):
+        for u, v in zip(a, b):
+            assert np.array_equal(u, v)

@@ -206,3 +206,79 @@ def test_objective_feasible_matches_oracle(d2, dtype, tol):
     ne = ref > 0
     assert np.max(np.abs(pc[ne] / ref[ne] - 1)) <= tol, (pc, ref)
     ctx.close()
+
+
+def test_probe_gate_rejects_a_collapsed_proposal(d2):
+    """A network whose output layer is zero proposes every support point at
+    the cluster mean with uniform weights.  Its product-coupling bound beats
+    the plain start's (the bound is smallest for supports collapsed onto
+    the mean), so the bound gate accepts it; the probe gate (10 B-ADMM
+    iterations from both starts, rounded-plan objectives compared) rejects
+    it, and the learned start then equals the plain one bitwise."""
+    print("[probe gate]", flush=True)
+    cl = warmstart_clusters("gmm3", 16, 5300, nc_hi=200)
+    K, m, d = cl["K"], 16, 3
+    theta = deepsets_init_params(m, d, H, 5).astype(np.float32)
+    shapes = list(ds.param_shapes(m, d, H))
+    tail = sum(int(np.prod(s)) for _, s in shapes[-2:])  # V3, e3
+    theta[-tail:] = 0.0
+    ws = d2.D2WarmStart(m, d, H, theta)
+    with d2.D2Context(0, "f32") as ctx:
+        ctx.load_instances(cl["offsets"], cl["X"], cl["W"])
+        ctx.centroids_init(cl["first"], m)
+        ctx.labels_set(cl["labels"])
+        X0, W0 = ctx.centroids_get()
+        acc, bp, bq = ws.propose(ctx, gate=True)
+        print(f"  bound gate accepts {int((acc == 1).sum())} of {K}",
+              flush=True)
+        assert (acc == 1).sum() >= K // 2
+        # plain start
+        ctx.centroids_set(X0, W0)
+        ctx.barycenter(iters=40, init=d2.D2_INIT_PRODUCT)
+        Xa, Wa = ctx.centroids_get()
+        Fa = ctx.objective_feasible()[1]
+        # learned start through the probe gate
+        ctx.centroids_set(X0, W0)
+        ctx.set_warm_start(ws, gate=10)
+        ctx.barycenter(iters=40, init=d2.D2_INIT_LEARNED)
+        Xb, Wb = ctx.centroids_get()
+        Fb = ctx.objective_feasible()[1]
+        ctx.set_warm_start(None)
+        assert np.array_equal(Xa, Xb) and np.array_equal(Wa, Wb)
+        assert np.array_equal(Fa, Fb)
+    ws.close()
+
+
+def test_rho_held_matches_oracle(d2):
+    """d2_set_rho holds rho per cluster: with rho set to 1.7 times Eq.
+    (rho)'s value the update equals the oracle's run with rho0 = 2 x 1.7
+    (same rho up to one rounding), FP64 bars; d2_objective reports the
+    values set, and NULL returns to Eq. (rho)."""
+    wl = make_workload("gmm_d3_n65536_k16", N=1500)
+    K, m = 3, 16
+    mem = pick_init_members(wl["offsets"], K, m, 7)
+    Xc, Wc = oracle.init_centroids(wl, mem, m)
+    lab, _, _ = oracle.assign(wl, Xc, Wc, T=30)
+    _, _, _, rhos, _ = oracle_barycenters(wl, lab, Xc, Wc, T=1, tau=10)
+    Xo, Wo, tr, rho_o, _ = oracle_barycenters(wl, lab, Xc, Wc, T=40, tau=10,
+                                              rho0=2.0 * 1.7)
+    with d2.D2Context(0, "f64") as ctx:
+        ctx.load_instances(wl["offsets"], wl["X"], wl["W"])
+        ctx.centroids_set(Xc, Wc)
+        ctx.labels_set(lab)
+        held = np.where(rhos > 0, 1.7 * rhos, 1.0)  # empty clusters: any
+        ctx.set_rho(held)
+        ctx.barycenter(iters=40, tau=10, init=d2.D2_INIT_PRODUCT)
+        g_tr, g_rho = ctx.objective(40)
+        Xg, Wg = ctx.centroids_get()
+        assert np.array_equal(g_rho[rhos > 0], held[rhos > 0])
+        for c in range(K):
+            if tr[c] is not None:
+                assert np.max(np.abs(g_tr[:, c] - tr[c]) / tr[c]) < 1e-10
+        assert np.abs(Wg - Wo).max() < 1e-10 and np.abs(Xg - Xo).max() < 1e-10
+        ctx.set_rho(None)
+        ctx.centroids_set(Xc, Wc)
+        ctx.barycenter(iters=2, tau=10, init=d2.D2_INIT_PRODUCT)
+        _, r2 = ctx.objective(2)
+        ne = rhos > 0
+        assert np.max(np.abs(r2[ne] / rhos[ne] - 1)) < 1e-12
