@@ -888,25 +888,34 @@ bool stream_state(const d2_ctx* c) {
 template <typename T>
 d2_status launch_ba(d2_ctx* c, const d2k::Args<T>& a, int& nl) {
   const auto& kt = kern<T>();
-  int waves = c->waves;
-  size_t per_wave = sizeof(double) * c->MP * (c->d + 1);
+  const int mi = ilog2(c->MP) - 3;
+  const size_t per_wave = sizeof(double) * c->MP * (c->d + 1);
+  // FP32, 32 <= d <= 64: the support sums (MP 16 / 32) and the cost at a
+  // new support (MP 32) come from matrix-core passes of their own beside a
+  // plain launch (k_sup_mfma after it, k_cost_mfma before it)
+  const bool mfma_d = !c->onfly && c->d >= 32 && c->d <= 64;
+  const bool xo = a.xout && !a.recost && mfma_d && kt.sup[0][mi][0] != nullptr;
+  const bool cx = a.recost && !a.xout && mfma_d && c->MP == 32 &&
+                  kt.cst[0] != nullptr;
   // large d, first launch after a support update: the cost is recomputed
   // from the centroid support staged in LDS after the support records
   const bool want_stage = a.recost && !c->onfly;
   const size_t stage =
       want_stage ? (size_t)c->MP * (c->xs + 4) * sizeof(T) : 0;
+  auto fits = [](size_t b) { return b <= 64 * 1024; };
+  // the full kernel forms what the passes do not; waves per workgroup are
+  // lowered until its (or k_sup_mfma's) support records fit in LDS
+  const bool full = (a.xout && !xo) || (a.recost && !cx);
   auto lds = [&](int wv) { return (a.xout ? per_wave * wv : 0) + stage; };
-  while (waves > 1 && lds(waves) > 64 * 1024) --waves;
-  const int xstage = (want_stage && lds(waves) <= 64 * 1024) ? 1 : 0;
-  size_t shm = a.xout ? per_wave * waves : 0;
+  int waves = c->waves;
+  if (full)
+    while (waves > 1 && !fits(lds(waves))) --waves;
+  const int xstage = (full && want_stage && fits(lds(waves))) ? 1 : 0;
+  size_t shm = full && a.xout ? per_wave * waves : 0;
   if (xstage) shm += stage;
+  int wsup = c->waves;
+  while (wsup > 1 && !fits(per_wave * wsup)) --wsup;
   hipEvent_t pe = prof_begin(c);
-  // support-update launches (d >= 32) and cost-recomputation launches
-  // (MP = 32, d <= 64) of large-d FP32 contexts use the MFMA kernels
-  const bool xo = a.xout && !a.recost && !c->onfly && c->d >= 32 &&
-                  c->d <= 64 && kt.bax[ilog2(c->MP) - 3][0] != nullptr;
-  const bool cx = a.recost && xstage && !a.xout && c->d <= 64 &&
-                  c->MP == 32 && kt.bcx[0] != nullptr;
   // plan state far beyond the last-level cache (256 MiB on this part):
   // the plain launches stream it (non-temporal)
   const bool nt = stream_state(c) && kt.bapn[c->onfly ? 1 : 0][0][0] != nullptr;
@@ -917,22 +926,38 @@ d2_status launch_ba(d2_ctx* c, const d2k::Args<T>& a, int& nl) {
   }
   for (int b = 0; b < c->nbk; ++b) {
     const int rb = ilog2(c->bk_R[b]);
-    auto fn = xo        ? kt.bax[ilog2(c->MP) - 3][rb]
-              : cx      ? kt.bcx[rb]
-              : (a.xout || a.recost)
-                  ? kt.ba[c->onfly ? 1 : 0][ilog2(c->MP) - 3][rb]
-              : nt ? kt.bapn[c->onfly ? 1 : 0][ilog2(c->MP) - 3][rb]
-                   : kt.bap[c->onfly ? 1 : 0][ilog2(c->MP) - 3][rb];
+    const int oi = c->onfly ? 1 : 0;
+    auto fn = full ? kt.ba[oi][mi][rb]
+              : nt ? kt.bapn[oi][mi][rb]
+                   : kt.bap[oi][mi][rb];
     if (!fn) return c->fail(D2_EINVAL, "no kernel for this tile shape");
     d2k::Args<T> ab = a;
     ab.blist = c->d_blist;
     ab.xstage = xstage;
     ab.bidx = b;
     ab.boff = c->bk_off[b];
-    hipLaunchKernelGGL(fn, dim3(c->bk_cap[b]), dim3(64 * waves), shm,
-                       stream_of(c, b), ab);
+    hipStream_t st = stream_of(c, b);
+    if (cx) {
+      hipLaunchKernelGGL(kt.cst[rb], dim3(c->bk_cap[b]), dim3(64 * c->waves),
+                         d2k::cost_mfma_lds_bytes(c->xs, c->waves), st, ab);
+      HIPCHK(c, hipGetLastError());
+      ++nl;
+      ab.recost = 0;
+    }
+    if (xo) ab.xout = nullptr;
+    hipLaunchKernelGGL(fn, dim3(c->bk_cap[b]), dim3(64 * waves), shm, st,
+                       ab);
     HIPCHK(c, hipGetLastError());
     ++nl;
+    if (xo) {
+      auto fs = kt.sup[nt ? 1 : 0][mi][rb];
+      if (!fs) return c->fail(D2_EINVAL, "no kernel for this tile shape");
+      ab.xout = a.xout;
+      hipLaunchKernelGGL(fs, dim3(c->bk_cap[b]), dim3(64 * wsup),
+                         per_wave * wsup, st, ab);
+      HIPCHK(c, hipGetLastError());
+      ++nl;
+    }
   }
   {
     d2_status s = join_side(c, c->nbk);

@@ -754,7 +754,7 @@ __device__ __forceinline__ void bstore(double v, Rsrc r, uint32_t o) {
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int kMfmaMaxD = 64;
-constexpr int kVarNone = 0, kVarSupport = 1, kVarCost = 2, kVarPlain = 3;
+constexpr int kVarNone = 0, kVarPlain = 3;
 
 // Per-wavefront FP32 accumulators of the support sums (MFMA layout) and of
 // the row indicators, added to the wavefront's FP64 LDS record once after
@@ -791,94 +791,110 @@ template <int MP> struct SupAcc {
   }
 };
 
-template <int MP, int NS>
-__device__ __forceinline__ void support_mfma(const Args<float>& a,
-                                             const Tile<float, MP>& tl,
-                                             const float (&b)[NS], float rr,
-                                             Rsrc rX, SupAcc<MP>& sa) {
-  static_assert(MP == 16 || MP == 32, "MFMA support sums: MP 16 or 32");
+// The support coordinates of the B operands of slots r0 .. r0 + G - 1 of a
+// tile, all loaded before their products (one 256-byte row pair per slot
+// and block of coordinates), so that the loads are in flight together
+// instead of one per product.
+template <int MP, int G>
+__device__ __forceinline__ void support_operands(
+    const Args<float>& a, const Tile<float, MP>& tl, Rsrc rX, int r0,
+    float (&yv)[G][SupAcc<MP>::NT]) {
   constexpr int NT = SupAcc<MP>::NT;
-  const int lane = threadIdx.x & (kWave - 1);
-  const int d = a.d;
-  const float ir = rcp_sum(rr);
-  const int tn = lane % MP;
+  const int tn = (threadIdx.x & (kWave - 1)) % MP;
 #pragma unroll
-  for (int r = 0; r < NS; ++r) {
-    const float av = b[r] * ir;
-    const uint32_t j = (uint32_t)tl.col(r);
+  for (int r = 0; r < G; ++r) {
+    const uint32_t j = (uint32_t)tl.col(r0 + r);
 #pragma unroll
     for (int q = 0; q < NT; ++q) {
-      if (q * MP < d) {
-        const int t = q * MP + tn;
-        const uint32_t o =
-            t < d ? (j * (uint32_t)a.xs + (uint32_t)t) * 4u : kOob;
-        const float yv = bload<float>(rX, o);
+      const int t = q * MP + tn;
+      yv[r][q] = 0.0f;
+      if (q * MP < a.d)
+        yv[r][q] = bload<float>(
+            rX, t < a.d ? (j * (uint32_t)a.xs + (uint32_t)t) * 4u : kOob);
+    }
+  }
+}
+
+// The products of slots r0 .. r0 + G - 1: u_i += sum_j (Pi1~_ij / r_i) y_j
+// (ir = 1 / r_i).
+template <int MP, int G, int NS>
+__device__ __forceinline__ void support_mfma(
+    const Args<float>& a, const float (&b)[NS], int r0, float ir,
+    const float (&yv)[G][SupAcc<MP>::NT], SupAcc<MP>& sa) {
+  static_assert(MP == 16 || MP == 32, "MFMA support sums: MP 16 or 32");
+  constexpr int NT = SupAcc<MP>::NT;
+#pragma unroll
+  for (int r = 0; r < G; ++r) {
+    const float av = b[r0 + r] * ir;
+#pragma unroll
+    for (int q = 0; q < NT; ++q) {
+      if (q * MP < a.d) {
         if constexpr (MP == 32)
-          sa.s[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, yv, sa.s[q], 0, 0,
-                                                         0);
+          sa.s[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, yv[r][q], sa.s[q],
+                                                         0, 0, 0);
         else
-          sa.s[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, yv, sa.s[q], 0, 0,
-                                                         0);
+          sa.s[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, yv[r][q], sa.s[q],
+                                                         0, 0, 0);
       }
     }
   }
-  if (lane < MP && rr > 0.0f) sa.den += 1.0f;
 }
 
 // Cost recomputation on the matrix cores (FP32 MFMA 32x32x2, MP = 32,
-// d <= 64): C_ij = |x_i|^2 + |y_j|^2 - 2 x_i . y_j for a 32-column block
-// as D^T = Y' X^T with Y' = the block's points in a permuted order, chosen
-// so that the accumulator layout (lane: row i = l % 32; register v: column
-// 8 (v/4) + 4 (l/32) + v % 4 of the block) is the tile's slot layout
-// (register v holds slot 16 b + v, column 32 b + l / 32 + 2 v).  The point
-// norms are summed from the loaded coordinates; one more MFMA step with
-// K = (|y|^2, 1) x (1, |x|^2) adds the norms.  Negative rounding residue is
-// clamped to 0.
-template <int NS>
-__device__ __forceinline__ void cost_mfma(const Args<float>& a,
-                                          const Tile<float, 32>& tl,
-                                          const float* xl, float xnorm,
-                                          Rsrc rX, float (&cs)[NS]) {
+// d <= 64) for one 32-column block of a tile: C_ij = |x_i|^2 + |y_j|^2 -
+// 2 x_i . y_j as D^T = Y' X^T with Y' = the block's points in a permuted
+// order, chosen so that the accumulator layout (lane: row i = l % 32;
+// register v: column 8 (v/4) + 4 (l/32) + v % 4 of the block) is the
+// tile's slot layout (register v holds slot 16 b + v, column 32 b + l / 32
+// + 2 v).  The block's points sit in LDS (yl, rows of xsl floats, staged
+// with coalesced loads); the two lane halves h take the coordinates
+// [h H, h H + H) (H = xs / 2 rounded up to 4; the row padding is zero), so
+// each lane reads its operands as 16-byte LDS words.  xh holds the lane's
+// half of x_i, i = l % 32, in registers.  The squared norms of the points
+// are summed from the same operands; one more MFMA step with K = (|y|^2,
+// 1) x (1, |x|^2) adds the norms.  Negative rounding residue is clamped to
+// 0.
+__device__ __forceinline__ f32x16 cost_block_mfma(const float* yl, int xsl,
+                                                  int H, const float (&xh)[32],
+                                                  float xnorm) {
   const int lane = threadIdx.x & (kWave - 1);
   const int n = lane & 31, h = lane >> 5;
-  const int xsl = a.xs + 4;
-  const float* xrow = xl + n * xsl;  // B operand: x_i, i = lane % 32
-  constexpr int NB = (NS + 15) / 16;
+  // A operand row n: column g + 8 q + 2 s of the block
+  const int jl = ((n >> 2) & 1) + 8 * (n >> 3) + 2 * (n & 3);
+  const float* yrow = yl + jl * xsl + h * H;
+  f32x16 acc;
 #pragma unroll
-  for (int bk = 0; bk < NB; ++bk) {
-    // A operand row n: column 32 bk + g + 8 q + 2 s of the tile
-    const int q = n >> 3, g = (n >> 2) & 1, sI = n & 3;
-    const uint32_t jn = (uint32_t)(32 * bk + g + 8 * q + 2 * sI);
-    const uint32_t base = jn * (uint32_t)a.xs * 4u;
-    f32x16 acc;
+  for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
+  float yy = 0.0f;
 #pragma unroll
-    for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
-    float yy = 0.0f;
-    for (int k0 = 0; k0 < a.d; k0 += 2) {
-      const int t = k0 + h;
-      const float y = bload<float>(rX, base + (uint32_t)t * 4u);
-      yy = fmaf(y, y, yy);
-      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(-2.0f * y, xrow[t], acc, 0,
-                                                 0, 0);
+  for (int s4 = 0; s4 < 8; ++s4) {
+    if (4 * s4 < H) {
+      const f32x4 y4 = *reinterpret_cast<const f32x4*>(yrow + 4 * s4);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        yy = fmaf(y4[u], y4[u], yy);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(-2.0f * y4[u],
+                                                   xh[4 * s4 + u], acc, 0, 0,
+                                                   0);
+      }
     }
-    yy += __shfl_xor(yy, 32);
-    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(h == 0 ? yy : 1.0f,
-                                               h == 0 ? 1.0f : xnorm, acc, 0,
-                                               0, 0);
-#pragma unroll
-    for (int v = 0; v < 16; ++v)
-      if (16 * bk + v < NS) cs[16 * bk + v] = fmaxf(acc[v], 0.0f);
   }
+  yy += __shfl_xor(yy, 32);
+  acc = __builtin_amdgcn_mfma_f32_32x32x2f32(h == 0 ? yy : 1.0f,
+                                             h == 0 ? 1.0f : xnorm, acc, 0, 0,
+                                             0);
+#pragma unroll
+  for (int v = 0; v < 16; ++v) acc[v] = fmaxf(acc[v], 0.0f);
+  return acc;
 }
 
 template <typename T, int MP, int NS, bool ONFLY, int VAR, int CP>
 __device__ __forceinline__ void ba_tile(const Args<T>& a, const Tile<T, MP>& tl,
                                         const T (&xr)[4], const double* xrow,
-                                        const T* xl, T xnorm, T wi, T rho,
+                                        const T* xl, T wi, T rho,
                                         T a2, T eps, double& accw,
                                         double& accf, double& accr,
-                                        double* accx, SupAcc<MP>* sa,
-                                        XAcc4& xa4) {
+                                        double* accx, XAcc4& xa4) {
   using V4 = typename Vec4<T>::type;
   constexpr uint32_t es = sizeof(T);
   // one resource per array over this tile (uniform), 32-bit lane offsets;
@@ -908,14 +924,11 @@ __device__ __forceinline__ void ba_tile(const Args<T>& a, const Tile<T, MP>& tl,
     } else {
       if (!a.recost)
         cs[r] = bload<T, CP>(rC, eo[r]);
-      else if (VAR != kVarCost && !xl)
+      else if (!xl)
         cs[r] = cost_generic<T>(xrow, a.X + (tl.o + tl.colc(r)) * a.xs, a.d);
     }
   }
-  if constexpr (VAR == kVarCost) {
-    // cost recomputation launch of a d <= 64 FP32 context (matrix cores)
-    cost_mfma<NS>(a, tl, xl, xnorm, rX, cs);
-  } else if constexpr (!ONFLY && VAR != kVarPlain) {
+  if constexpr (!ONFLY && VAR != kVarPlain) {
     if (a.recost && xl) cost_tile<T, MP, NS>(a, tl, xl, cs);
   }
   T res = T(0);
@@ -936,10 +949,7 @@ __device__ __forceinline__ void ba_tile(const Args<T>& a, const Tile<T, MP>& tl,
       for (int r = 0; r < NS; ++r) bstore(cs[r], rC, eo[r]);
     }
   }
-  if constexpr (VAR == kVarSupport) {
-    // support-update launch of a large-d FP32 context (matrix cores)
-    support_mfma<MP, NS>(a, tl, b, rr, rX, *sa);
-  } else if constexpr (VAR != kVarPlain) {
+  if constexpr (VAR != kVarPlain) {
     if (a.xout) {
       if constexpr (ONFLY)
         add_support_terms4<T, MP, NS>(a, tl, b, rr, xa4);
@@ -949,12 +959,12 @@ __device__ __forceinline__ void ba_tile(const Args<T>& a, const Tile<T, MP>& tl,
   }
 }
 
-// VAR: kVarSupport / kVarCost are kernels only for the launches that form
-// the support-update sums / recompute the cost (each once per tau
-// iterations) of FP32 contexts with large d, on the matrix cores; kVarPlain
-// kernels leave out the support terms and the cost recomputation
-// altogether and serve the launches that do neither (most of them).  Separate kernels so that the
-// registers of the rarer launches do not lower the occupancy of the others.
+// VAR: kVarPlain kernels leave out the support terms and the cost
+// recomputation altogether and serve the launches that do neither (most of
+// them), so that the registers of the rarer launches do not lower their
+// occupancy.  (FP32 contexts with 32 <= d <= 64 form the support sums and
+// the new cost in passes of their own on the matrix cores, k_sup_mfma and
+// k_cost_mfma below, beside plain launches.)
 template <typename T, int MP, int R, bool ONFLY, int VAR = kVarNone,
           int CP = 0>
 __global__ void __launch_bounds__(256) k_iter_ba(Args<T> a) {
@@ -999,28 +1009,14 @@ __global__ void __launch_bounds__(256) k_iter_ba(Args<T> a) {
   }
   const double* xrow = a.xc + ((int64_t)c * MP + (rowok ? i : 0)) * a.d;
   T* xl = nullptr;
-  T xnorm = T(0);
   if constexpr (!ONFLY && VAR != kVarPlain) {
     if (a.recost && a.xstage) {
       xl = reinterpret_cast<T*>(s_dyn + (a.xout ? nwaves * nrec : 0));
       stage_support<T, MP>(a, c, xl);
-      if constexpr (VAR == kVarCost) {
-        // |x_i|^2 of the lane's row, in index order
-        for (int t = 0; t < a.d; ++t) {
-          const T v = xl[i * (a.xs + 4) + t];
-          xnorm = fma(v, v, xnorm);
-        }
-      }
     }
   }
   double accw = 0.0, accf = 0.0, accr = 0.0;
   XAcc4 xa4;  // support terms of d <= 4 launches, in registers
-  SupAcc<(MP == 16 || MP == 32) ? MP : 32> sacc;
-  SupAcc<MP>* sap = nullptr;
-  if constexpr (VAR == kVarSupport) {
-    sacc.zero();
-    sap = &sacc;
-  }
   // (fetching the next tile's offsets one pass ahead measured no faster)
   for (int pos = cj.begin + wave; pos < cj.end; pos += nwaves) {
     Tile<T, MP> tl;
@@ -1029,16 +1025,191 @@ __global__ void __launch_bounds__(256) k_iter_ba(Args<T> a) {
       tl.set(a.m, a.off[k], a.off[k + 1], a.pofs[k]);
     }
     with_slots<R>(tl.nsl, [&]<int NS>() {
-      ba_tile<T, MP, NS, ONFLY, VAR, CP>(a, tl, xr, xrow, xl, xnorm, wi, rho,
-                                         a2, eps, accw, accf, accr, accx, sap,
-                                         xa4);
+      ba_tile<T, MP, NS, ONFLY, VAR, CP>(a, tl, xr, xrow, xl, wi, rho, a2,
+                                         eps, accw, accf, accr, accx, xa4);
     });
   }
-  if constexpr (VAR == kVarSupport) sacc.flush(a.d, accx);
   if constexpr (ONFLY && VAR != kVarPlain)
     if (a.xout) flush_support4<MP>(xa4, a.d, accx);
   write_w_record<MP>(accw, accf, accr, a.part, a.ps, ch);
   if (a.xout) write_x_record(s_dyn, nrec, a.xout, ch);
+}
+
+// ---------------------------------------------------------------------------
+// Matrix-core passes of FP32 contexts with 32 <= d <= 64, launched per slot
+// bucket beside a plain plan-update launch, over the same chunks and work
+// list (one wavefront per tile, as there):
+//   k_cost_mfma (MP = 32): the cost cache at a new support, written before
+//     the launch that first reads it (Eq. (updatex) moved the support);
+//   k_sup_mfma (MP = 16 or 32): the support-update sums of the launch just
+//     made, from its stored Pi1 and Lambda.  Pi1~ = Pi1 exp(Lambda / rho) +
+//     eps and its row sums r_i are formed again with the operations of
+//     phase A in the same order (Pi1 and Lambda are stored as computed), so
+//     the sums are those of phase A.
+// Kept out of the plan-update kernel so that neither the accumulators nor
+// the support loads share its registers: with them it held one wavefront
+// per SIMD for the widest tiles instead of two.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ bool chunk_of(const Args<T>& a, int& ch) {
+  ch = blockIdx.x;
+  if (a.blist) {
+    if (ch >= a.bcnt[a.bidx]) return false;
+    ch = uni(a.blist[a.boff + ch]);
+    return true;
+  }
+  return ch < *a.nch;
+}
+
+// LDS floats of k_cost_mfma: the cluster's support, then one staged block
+// of 32 support points per wavefront, rows of xs + 4 floats
+__host__ __device__ inline size_t cost_mfma_lds_bytes(int xs, int nwaves) {
+  return sizeof(float) * 32 * (size_t)(xs + 4) * (size_t)(1 + nwaves);
+}
+
+// LDS writes of a wavefront visible to its other lanes (and its earlier
+// LDS reads complete) before it goes on
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+}
+
+template <int R>
+__global__ void __launch_bounds__(256) k_cost_mfma(Args<float> a) {
+  extern __shared__ f32x4 s_cost[];  // 16-byte aligned rows
+  int ch;
+  if (!chunk_of(a, ch)) return;
+  const Chunk cj = a.chunks[ch];
+  const int wave = uni(threadIdx.x / kWave), nwaves = blockDim.x / kWave;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int n = lane & 31, h = lane >> 5;
+  const int xsl = a.xs + 4;
+  float* xl = reinterpret_cast<float*>(s_cost);
+  float* yl = xl + (1 + wave) * 32 * xsl;
+  // the block rows' padding [xs, xs + 4) stays zero
+  for (int q = lane; q < 32 * 4; q += kWave) yl[(q >> 2) * xsl + a.xs + (q & 3)] = 0.0f;
+  stage_support<float, 32>(a, cj.cluster, xl);
+  // |x_i|^2 of the lane's row, in index order, and the lane's half of x_i
+  float xnorm = 0.0f;
+  for (int t = 0; t < a.d; ++t) {
+    const float v = xl[n * xsl + t];
+    xnorm = fmaf(v, v, xnorm);
+  }
+  const int H = ((a.xs >> 1) + 3) & ~3;
+  float xh[32];
+#pragma unroll
+  for (int s4 = 0; s4 < 32; ++s4) xh[s4] = s4 < H ? xl[n * xsl + h * H + s4] : 0.0f;
+  const int n16 = 8 * a.xs;  // 16-byte words of one block (<= 8 per lane)
+  for (int pos = cj.begin + wave; pos < cj.end; pos += nwaves) {
+    Tile<float, 32> tl;
+    {
+      const int k = uni(a.work[pos]);
+      tl.set(a.m, a.off[k], a.off[k + 1], a.pofs[k]);
+    }
+    with_slots<R>(tl.nsl, [&]<int NS>() {
+      const uint32_t tb = (uint32_t)(a.m * tl.mk) * 4u;
+      const Rsrc rC = make_rsrc(a.Cc + tl.base, tb);
+      const Rsrc rX =
+          make_rsrc(a.X + tl.o * a.xs, (uint32_t)(tl.mk * a.xs) * 4u);
+      constexpr int NB = (NS + 15) / 16;
+#pragma unroll
+      for (int bk = 0; bk < NB; ++bk) {
+        // stage points 32 bk .. 32 bk + 31 (zero past the tile): the block
+        // is contiguous, 32 xs floats, read as 16-byte words
+        const uint32_t b0 = (uint32_t)(32 * bk * a.xs) * 4u;
+        f32x4 v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (u * kWave + lane < n16)
+            v[u] = bload<f32x4>(rX, b0 + (uint32_t)((u * kWave + lane) * 16));
+        wave_lds_sync();  // the previous block's operand reads are done
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          if (u * kWave + lane < n16) {
+            const int f = (u * kWave + lane) * 4;
+            const int row = f / a.xs;
+            *reinterpret_cast<f32x4*>(yl + row * xsl + (f - row * a.xs)) = v[u];
+          }
+        }
+        wave_lds_sync();
+        const f32x16 acc = cost_block_mfma(yl, xsl, H, xh, xnorm);
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          const int r = 16 * bk + u;
+          if (r < NS) {
+            const uint32_t j = (uint32_t)tl.col(r);
+            bstore(acc[u], rC,
+                   tl.rowok ? (j * (uint32_t)a.m + (uint32_t)tl.i) * 4u
+                            : kOob);
+          }
+        }
+      }
+    });
+  }
+}
+
+template <int MP, int R, int CP>
+__global__ void __launch_bounds__(256, 2) k_sup_mfma(Args<float> a) {
+  extern __shared__ double s_dyn[];  // [nwaves][MP][d+1] support terms
+  constexpr int NT = SupAcc<MP>::NT;
+  int ch;
+  if (!chunk_of(a, ch)) return;
+  const Chunk cj = a.chunks[ch];
+  const int c = cj.cluster;
+  const int wave = uni(threadIdx.x / kWave), nwaves = blockDim.x / kWave;
+  const int lane = threadIdx.x & (kWave - 1);
+  const float a2 = (float)(kLog2e / a.rho[c]);
+  const float eps = (float)a.eps;
+  const int nrec = MP * (a.d + 1);
+  double* accx = s_dyn + (int64_t)wave * nrec;
+  for (int q = lane; q < nrec; q += kWave) accx[q] = 0.0;
+  SupAcc<MP> sacc;
+  sacc.zero();
+  for (int pos = cj.begin + wave; pos < cj.end; pos += nwaves) {
+    Tile<float, MP> tl;
+    {
+      const int k = uni(a.work[pos]);
+      tl.set(a.m, a.off[k], a.off[k + 1], a.pofs[k]);
+    }
+    with_slots<R>(tl.nsl, [&]<int NS>() {
+      const uint32_t tb = (uint32_t)(a.m * tl.mk) * 4u;
+      const Rsrc rP = make_rsrc(a.P1 + tl.base, tb);
+      const Rsrc rL = make_rsrc(a.L + tl.base, tb);
+      const Rsrc rX =
+          make_rsrc(a.X + tl.o * a.xs, (uint32_t)(tl.mk * a.xs) * 4u);
+      // slots in groups of G: the operands of group g + 1 load while the
+      // products of group g run
+      constexpr int G = NS <= 16 ? NS : 4, NG = NS / G;
+      static_assert(NS % G == 0, "slot groups");
+      float p[NS], l[NS], b[NS], yv[2][G][NT];
+#pragma unroll
+      for (int r = 0; r < NS; ++r) {
+        const uint32_t j = (uint32_t)tl.col(r);
+        const uint32_t eo =
+            tl.rowok ? (j * (uint32_t)a.m + (uint32_t)tl.i) * 4u : kOob;
+        p[r] = bload<float, CP>(rP, eo);
+        l[r] = bload<float, CP>(rL, eo);
+      }
+      support_operands<MP, G>(a, tl, rX, 0, yv[0]);
+      float rr = 0.0f;
+#pragma unroll
+      for (int r = 0; r < NS; ++r) {
+        b[r] = fmaf(p[r], dexp2(l[r] * a2), tl.valid(r) ? eps : 0.0f);
+        rr += b[r];
+      }
+      rr = sum_row<MP>(rr);
+      const float ir = rcp_sum(rr);
+#pragma unroll
+      for (int g = 0; g < NG; ++g) {
+        if (g + 1 < NG)
+          support_operands<MP, G>(a, tl, rX, (g + 1) * G, yv[(g + 1) & 1]);
+        support_mfma<MP, G, NS>(a, b, g * G, ir, yv[g & 1], sacc);
+      }
+      if ((threadIdx.x & (kWave - 1)) < MP && rr > 0.0f) sacc.den += 1.0f;
+    });
+  }
+  sacc.flush(a.d, accx);
+  write_x_record(s_dyn, nrec, a.xout, ch);
 }
 
 // ---------------------------------------------------------------------------
@@ -1759,8 +1930,8 @@ template <typename T> struct KernTable {
   BA ba[2][4][6] = {};  // [onfly][mp][r]
   BA bap[2][4][6] = {}; // the same without support terms
   BA bapn[2][4][6] = {}; // bap streaming its plan state (FP32)
-  BA bax[4][6] = {};    // support-update launches, FP32, d > 4, MP 16 / 32
-  BA bcx[6] = {};       // cost-recomputation launches, FP32, d <= 64, MP 32
+  BA sup[2][4][6] = {}; // k_sup_mfma [stream][mp][r], FP32, MP 16 / 32
+  BA cst[6] = {};       // k_cost_mfma, FP32, MP 32
   AX aux[4][6] = {};
   AX auxm[3][4][6] = {};  // fixed to kRho, kA0, kBF
   AS asg[4][6] = {};

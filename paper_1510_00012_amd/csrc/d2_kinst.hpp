@@ -24,10 +24,11 @@ void add_kernels(KernTable<T>& t) {
   } else {
     t.ba[0][a][b] = &k_iter_ba<T, MP, R, false>;
     t.ba[1][a][b] = &k_iter_ba<T, MP, R, true>;
-    if constexpr (sizeof(T) == 4 && (MP == 16 || MP == 32))
-      t.bax[a][b] = &k_iter_ba<T, MP, R, false, kVarSupport>;
-    if constexpr (sizeof(T) == 4 && MP == 32)
-      t.bcx[b] = &k_iter_ba<T, MP, R, false, kVarCost>;
+    if constexpr (sizeof(T) == 4 && (MP == 16 || MP == 32)) {
+      t.sup[0][a][b] = &k_sup_mfma<MP, R, 0>;
+      t.sup[1][a][b] = &k_sup_mfma<MP, R, kCpolStream>;
+    }
+    if constexpr (sizeof(T) == 4 && MP == 32) t.cst[b] = &k_cost_mfma<R>;
     t.aux[a][b] = &k_aux<T, MP, R>;
     t.asg[a][b] = &k_assign<T, MP, R>;
   }
