@@ -1238,6 +1238,10 @@ d2_status run_assign(d2_ctx* c, const d2_ot_params* p, float* ms_out,
   a.xs = c->xs;
   a.K = c->K;
   a.iters = p->iters;
+  // candidate bounds one per lane where a centroid row fits in registers
+  // and the centroids fill the lanes (FP32 vectors, d <= 16, K >= 32)
+  const bool batch = sizeof(T) == 4 && a.prune && !c->sym && c->d <= 16 &&
+                     c->K >= 32;
   if (c->alist_MP != c->MP) {
     // Instance ids grouped by slot class (stable).  The classes run as
     // separate launches only when the largest needs 8 or more slots (its
@@ -1298,9 +1302,11 @@ d2_status run_assign(d2_ctx* c, const d2_ot_params* p, float* ms_out,
     d2k::AssignArgs<T> aq = a;
     aq.list = c->d_alist + c->aofs[q];
     aq.N = c->acnt[q];
+    aq.batch = batch && (64 / c->MP) * (1 << q) <= 32 ? 1 : 0;
     const int64_t blocks = (aq.N + wpb - 1) / wpb;
-    // per wave: the instance mean, then |y_j - mu_P| and w_j per column
-    const size_t lds = sizeof(T) * wpb * (c->d + 2 * (64 / c->MP) * (1 << q));
+    const size_t lds = (size_t)wpb * d2k::assign_lds(c->d, c->MP, 1 << q,
+                                                     c->xs, (int)sizeof(T),
+                                                     aq.batch).bytes;
     hipLaunchKernelGGL(fq, dim3((unsigned)blocks), dim3(64 * wpb), lds,
                        stream_of(c, qi++), aq);
     HIPCHK(c, hipGetLastError());

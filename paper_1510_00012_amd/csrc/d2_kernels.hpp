@@ -1487,7 +1487,27 @@ template <typename T> struct AssignArgs {
   int64_t N;            // instances in this launch
   double rho0, eps;
   int m, d, xs, K, iters, prune, prev_valid;
+  // 1: the exact column bounds of up to 64 candidate centroids at a time,
+  // one per lane (FP32, d <= 16, no symbols, kernels whose tiles have at
+  // most 32 columns); 0: one candidate at a time across the wavefront
+  int batch;
 };
+
+// LDS of one assignment wavefront (byte offsets): the instance mean (d
+// values), |y_j - mu_P| and w_j per column (2 CPS R values), then for the
+// batched bounds a candidate list (128 ints) and the instance's points
+// (CPS R rows of xs floats).
+struct AssignLds {
+  int list, ys, bytes;
+};
+__host__ __device__ inline AssignLds assign_lds(int d, int MP, int R, int xs,
+                                                int esz, int batch) {
+  AssignLds L;
+  L.list = ((d + 2 * (64 / MP) * R) * esz + 15) & ~15;
+  L.ys = L.list + (batch ? 128 * 4 : 0);
+  L.bytes = L.ys + (batch ? (64 / MP) * R * xs * 4 : 0);
+  return L;
+}
 
 // value of v in lane `src` (src uniform), for 32- and 64-bit types
 __device__ __forceinline__ float lane_value(float v, int src) {
@@ -1686,10 +1706,65 @@ __device__ __forceinline__ T cheap_bound(const AssignArgs<T>& a, int c,
   return acc;
 }
 
+// Column-relaxed lower bound sum_j w_j min_i C_ij of the pair (this
+// wavefront's instance, centroid c), one centroid per lane: every cost
+// entry is formed with the operations of pair_costs in the same order (so
+// the minima are those of the tile-layout bound), the instance's points
+// and weights come from the wavefront's LDS (the same words for all lanes),
+// the centroid rows are the lane's own.  d <= 16, m_k <= MK.
+template <int MP, int MK>
+__device__ __forceinline__ float lane_column_bound(const AssignArgs<float>& a,
+                                                   const float* ys,
+                                                   const float* swj, int mk,
+                                                   int c) {
+  const float big = 3.0e38f;
+  const int n4 = a.xs >> 2;
+  float mn[MK];
+#pragma unroll
+  for (int j = 0; j < MK; ++j) mn[j] = big;
+  for (int i = 0; i < a.m; ++i) {
+    const float4* xp =
+        reinterpret_cast<const float4*>(a.xct + ((int64_t)c * MP + i) * a.xs);
+    float4 xv[4];
+#pragma unroll
+    for (int t4 = 0; t4 < 4; ++t4)
+      if (t4 < n4) xv[t4] = xp[t4];
+#pragma unroll
+    for (int j = 0; j < MK; ++j) {
+      if (j < mk) {
+        const float4* yp = reinterpret_cast<const float4*>(ys + j * a.xs);
+        float acc = 0.0f;
+#pragma unroll
+        for (int t4 = 0; t4 < 4; ++t4) {
+          if (t4 < n4) {
+            const float4 y = yp[t4];
+            float df = xv[t4].x - y.x;
+            acc = fmaf(df, df, acc);
+            df = xv[t4].y - y.y;
+            acc = fmaf(df, df, acc);
+            df = xv[t4].z - y.z;
+            acc = fmaf(df, df, acc);
+            df = xv[t4].w - y.w;
+            acc = fmaf(df, df, acc);
+          }
+        }
+        mn[j] = fminf(mn[j], acc);
+      }
+    }
+  }
+  float lb = 0.0f;
+#pragma unroll
+  for (int j = 0; j < MK; ++j)
+    if (j < mk)
+      lb = fmaf(swj[j] > 0.0f ? swj[j] : 0.0f, mn[j] < big ? mn[j] : 0.0f, lb);
+  return lb;
+}
+
 template <typename T, int MP, int NS>
 __device__ __forceinline__ void assign_tile(const AssignArgs<T>& a,
                                             const Tile<T, MP>& tl,
-                                            int64_t kinst, T* sw, int prev,
+                                            int64_t kinst, T* sw, int* slist,
+                                            float* sys, int prev,
                                             double& bestv, int& bestc,
                                             int& nevals, int& ncost) {
   const int d = a.d;
@@ -1788,6 +1863,96 @@ __device__ __forceinline__ void assign_tile(const AssignArgs<T>& a,
   // dlt and the w-weighted 2-norm over j by at most dlt), else the cheap
   // bound; the survivors in index order, each checked again against the
   // best value at its turn.
+  if constexpr (sizeof(T) == 4 && NS * Tile<T, MP>::CPS <= 32) {
+    if (a.batch) {
+      // Batched: the candidates of each group of 64 centroids (those whose
+      // stored / cheap bound does not clear the best value) join a list;
+      // every 64 of them (and at the end) their exact column bounds are
+      // formed one per lane, then taken in index order: the cost block and
+      // transport where the bound does not clear the best value at its turn
+      // (the same decisions as one candidate at a time, on bounds formed
+      // from the same cost entries).
+      constexpr int MK = NS * Tile<T, MP>::CPS;
+      for (int f = 4 * lane; f < tl.mk * a.xs; f += 4 * kWave)
+        *reinterpret_cast<float4*>(sys + f) =
+            *reinterpret_cast<const float4*>(a.X + tl.o * a.xs + f);
+      int nb = 0;
+      for (int b0 = 0; b0 < a.K; b0 += kWave) {
+        const int c = b0 + lane;
+        const double cut0 = bestv * (1.0 + 1e-4);
+        T lb = big;
+        float nu = 0.0f;
+        if (c < a.K) {
+          T sb = T(0);
+          if (a.lbs && a.lbs_in) {
+            const T u = (T)a.lbs[lrow + c] - (T)a.dlt[c];
+            sb = u > T(0) ? u : T(0);
+          }
+          lb = sb * sb;
+          if ((double)lb <= cut0) {
+            const T cb = cheap_bound(a, c, smu, srj, swj, tl.mk);
+            lb = cb > lb ? cb : lb;
+          }
+          nu = (float)dsqrt(lb) * (1.0f - 1e-6f);
+          if (c == c0) nu = stored(lb0);
+        }
+        const bool lv = c < a.K && c != c0 && (double)lb <= cut0;
+        const unsigned long long live = __ballot(lv);
+        // bounds of the centroids that are no candidates are final
+        if (a.lbs && c < a.K && !lv) a.lbs[lrow + c] = nu;
+        const int rank = __builtin_amdgcn_mbcnt_hi(
+            (unsigned)(live >> 32),
+            __builtin_amdgcn_mbcnt_lo((unsigned)live, 0u));
+        wave_lds_sync();
+        if (lv) slist[nb + rank] = c;
+        nb += __builtin_popcountll(live);
+        wave_lds_sync();
+        const bool last = b0 + kWave >= a.K;
+        while (nb >= kWave || (last && nb > 0)) {
+          const int nq = nb < kWave ? nb : kWave;
+          const int cq = lane < nq ? slist[lane] : -1;
+          const double lbq =
+              cq >= 0 ? (double)lane_column_bound<MP, MK>(
+                            a, sys, reinterpret_cast<const float*>(swj),
+                            tl.mk, cq)
+                      : 0.0;
+          if (a.lbs && cq >= 0) a.lbs[lrow + cq] = stored(lbq);
+          ncost += nq;
+          // in increasing order of the bound (ties: list order, i.e.
+          // centroid index), so that the best value falls early; once the
+          // smallest bound left clears the best value, so do all the rest
+          double open = cq >= 0 ? lbq : 1.0e300;
+          for (int it = 0; it < nq; ++it) {
+            double mv = open;
+            int ml = lane;
+#pragma unroll
+            for (int o = 1; o < kWave; o <<= 1) {
+              const double ov = __shfl_xor(mv, o, kWave);
+              const int ol = __shfl_xor(ml, o, kWave);
+              if (ov < mv || (ov == mv && ol < ml)) {
+                mv = ov;
+                ml = ol;
+              }
+            }
+            ml = uni(ml);
+            if (!(lane_value(mv, 0) <= bestv * (1.0 + 1e-4))) break;
+            const int cc = __builtin_amdgcn_readlane(cq, ml);
+            if (lane == ml) open = 1.0e300;
+            pair_costs<T, MP, NS>(a, tl, cc, cs);
+            consider(cc);
+          }
+          // the unprocessed rest moves to the front of the list
+          const int rest = nb - nq;
+          const int mv = lane < rest ? slist[nq + lane] : 0;
+          wave_lds_sync();
+          if (lane < rest) slist[lane] = mv;
+          wave_lds_sync();
+          nb = rest;
+        }
+      }
+      return;
+    }
+  }
   for (int b0 = 0; b0 < a.K; b0 += kWave) {
     const int c = b0 + lane;
     const double cut0 = bestv * (1.0 + 1e-4);
@@ -1829,14 +1994,15 @@ __device__ __forceinline__ void assign_tile(const AssignArgs<T>& a,
 template <typename T, int MP, int R>
 __global__ void __launch_bounds__(256) k_assign(AssignArgs<T> a) {
   // per wave: d values (mu_P), then |y_j - mu_P| and w_j per column
-  extern __shared__ unsigned char s_raw[];
+  extern __shared__ __attribute__((aligned(16))) unsigned char s_raw[];
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = uni(threadIdx.x / kWave);
   const int64_t q = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave;
   if (q >= a.N) return;  // whole wavefront exits together
   const int64_t k = a.list ? uni(a.list[q]) : q;
-  T* sw = reinterpret_cast<T*>(s_raw) +
-          (int64_t)wave * (a.d + 2 * (kWave / MP) * R);
+  const AssignLds L = assign_lds(a.d, MP, R, a.xs, (int)sizeof(T), a.batch);
+  unsigned char* wl = s_raw + (int64_t)wave * L.bytes;
+  T* sw = reinterpret_cast<T*>(wl);
   Tile<T, MP> tl;
   tl.setup(a.off, nullptr, a.m, (int)k);
   if (tl.mk < 1 || tl.nsl > R) {
@@ -1852,7 +2018,9 @@ __global__ void __launch_bounds__(256) k_assign(AssignArgs<T> a) {
   double bestv = 0.0;
   int bestc = -1, nevals = 0, ncost = 0;
   with_slots<R>(tl.nsl, [&]<int NS>() {
-    assign_tile<T, MP, NS>(a, tl, k, sw, prev, bestv, bestc, nevals, ncost);
+    assign_tile<T, MP, NS>(a, tl, k, sw, reinterpret_cast<int*>(wl + L.list),
+                           reinterpret_cast<float*>(wl + L.ys), prev, bestv,
+                           bestc, nevals, ncost);
   });
   if (lane == 0) {
     a.labels[k] = bestc;

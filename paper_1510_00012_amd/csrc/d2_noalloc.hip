@@ -155,9 +155,16 @@ d2_status launch(hipStream_t st, unsigned char* base, const Layout& L,
   a.iters = p->iters;
   a.prune = p->prune ? 1 : 0;
   a.prev_valid = 0;
+  // candidate bounds one per lane as in d2_assign
+  a.batch = sizeof(T) == 4 && a.prune && d <= 16 && K >= 32 &&
+                    (64 / MP) * R <= 32
+                ? 1
+                : 0;
   const int wpb = 4;
   const int64_t blocks = (N + wpb - 1) / wpb;
-  const size_t lds = sizeof(T) * wpb * (d + 2 * (64 / MP) * R);
+  const size_t lds = (size_t)wpb * d2k::assign_lds(d, MP, R, xs,
+                                                   (int)sizeof(T), a.batch)
+                                       .bytes;
   hipLaunchKernelGGL(fn, dim3((unsigned)blocks), dim3(64 * wpb), lds, st, a);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess)
