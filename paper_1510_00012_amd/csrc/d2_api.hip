@@ -1302,7 +1302,7 @@ d2_status run_assign(d2_ctx* c, const d2_ot_params* p, float* ms_out,
     d2k::AssignArgs<T> aq = a;
     aq.list = c->d_alist + c->aofs[q];
     aq.N = c->acnt[q];
-    aq.batch = batch && (64 / c->MP) * (1 << q) <= 32 ? 1 : 0;
+    aq.batch = batch && c->MP <= 16 && (64 / c->MP) * (1 << q) <= 32 ? 1 : 0;
     const int64_t blocks = (aq.N + wpb - 1) / wpb;
     const size_t lds = (size_t)wpb * d2k::assign_lds(c->d, c->MP, 1 << q,
                                                      c->xs, (int)sizeof(T),

@@ -1488,8 +1488,9 @@ template <typename T> struct AssignArgs {
   double rho0, eps;
   int m, d, xs, K, iters, prune, prev_valid;
   // 1: the exact column bounds of up to 64 candidate centroids at a time,
-  // one per lane (FP32, d <= 16, no symbols, kernels whose tiles have at
-  // most 32 columns); 0: one candidate at a time across the wavefront
+  // one per lane (FP32, d <= 16, no symbols, kernels for pad(m) <= 16 whose
+  // tiles have at most 32 columns); 0: one candidate at a time across the
+  // wavefront
   int batch;
 };
 
@@ -1863,7 +1864,7 @@ __device__ __forceinline__ void assign_tile(const AssignArgs<T>& a,
   // dlt and the w-weighted 2-norm over j by at most dlt), else the cheap
   // bound; the survivors in index order, each checked again against the
   // best value at its turn.
-  if constexpr (sizeof(T) == 4 && NS * Tile<T, MP>::CPS <= 32) {
+  if constexpr (sizeof(T) == 4 && MP <= 16 && NS * Tile<T, MP>::CPS <= 32) {
     if (a.batch) {
       // Batched: the candidates of each group of 64 centroids (those whose
       // stored / cheap bound does not clear the best value) join a list;

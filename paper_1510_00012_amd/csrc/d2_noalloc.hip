@@ -156,7 +156,7 @@ d2_status launch(hipStream_t st, unsigned char* base, const Layout& L,
   a.prune = p->prune ? 1 : 0;
   a.prev_valid = 0;
   // candidate bounds one per lane as in d2_assign
-  a.batch = sizeof(T) == 4 && a.prune && d <= 16 && K >= 32 &&
+  a.batch = sizeof(T) == 4 && a.prune && d <= 16 && K >= 32 && MP <= 16 &&
                     (64 / MP) * R <= 32
                 ? 1
                 : 0;

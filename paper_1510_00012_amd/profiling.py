@@ -68,8 +68,13 @@ def traffic(fetch_csv, write_csv, kernel_sub, workload, copy_mib, out_json,
             cmd, group=1):
     """group: dispatches of the kernel that make one unit of the bench's
     per-launch timing (the slot-bucket launches of one B-ADMM iteration
-    are timed together), so the bytes are per group of dispatches."""
+    are timed together), so the bytes are per group of dispatches.
+    kernel_sub may list several comma-separated substrings: the first names
+    the kernel that every unit launches (its dispatches count the units),
+    the others kernels launched within some units (the matrix-core passes
+    beside the plan-update kernel), whose bytes are added to those units."""
     group = int(group)
+    subs = [k for k in kernel_sub.split(",") if k]
     copy_kib = float(copy_mib) * 1024.0
     fetch = _per_kernel(fetch_csv, "FETCH_SIZE")
     write = _per_kernel(write_csv, "WRITE_SIZE")
@@ -89,12 +94,15 @@ def traffic(fetch_csv, write_csv, kernel_sub, workload, copy_mib, out_json,
     sw = copy_kib / cw if cw else None
 
     def kern(agg):
-        vals = [v for k, vs in agg.items() if kernel_sub in k for v in vs]
-        return group * sum(vals) / len(vals) if vals else None
+        prim = [v for k, vs in agg.items() if subs[0] in k for v in vs]
+        allv = [v for k, vs in agg.items() if any(q in k for q in subs)
+                for v in vs]
+        return group * sum(allv) / len(prim) if prim else None
 
     kf, kw = kern(fetch), kern(write)
     rec = {
-        "kernel": kernel_sub,
+        "kernel": subs[0],
+        "kernels_summed": subs,
         "dispatches_per_launch": group,
         "workload": workload,
         "command": cmd,

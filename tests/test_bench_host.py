@@ -111,3 +111,30 @@ def test_counter_calibration(tmp_path):
                             str(tmp_path / "t.json"), "cmd", 2)
     assert rec["fetch_scale"] == 2.0 and rec["write_scale"] == 1.0
     assert rec["hbm_bytes_per_launch"] == 2 * (200.0 * 2.0 + 100.0) * 1024.0
+
+
+def test_traffic_adds_the_passes_beside_the_plan_update(tmp_path):
+    """Matrix-core passes launched within some iterations add their bytes
+    to those iterations; the plan-update dispatches count the iterations."""
+    def write(path, counter, rows):
+        with open(path, "w", newline="") as f:
+            w = csv.DictWriter(f, fieldnames=["Kernel_Name", "Counter_Name",
+                                              "Counter_Value"])
+            w.writeheader()
+            for name, v in rows:
+                w.writerow({"Kernel_Name": name, "Counter_Name": counter,
+                            "Counter_Value": v})
+    fcsv, wcsv = tmp_path / "f.csv", tmp_path / "w.csv"
+    # 4 iterations of one dispatch each, one k_sup_mfma and one k_cost_mfma
+    write(fcsv, "FETCH_SIZE", [("k_copy_probe(float4*)", 2048.0)] +
+          [("k_iter_ba<float>", 100.0)] * 4 +
+          [("k_sup_mfma<32>", 40.0), ("k_cost_mfma<8>", 20.0)])
+    write(wcsv, "WRITE_SIZE", [("k_copy_probe(float4*)", 4096.0)] +
+          [("k_iter_ba<float>", 50.0)] * 4 + [("k_cost_mfma<8>", 8.0)])
+    rec = profiling.traffic(str(fcsv), str(wcsv),
+                            "k_iter_ba,k_sup_mfma,k_cost_mfma", "tiny", 4,
+                            str(tmp_path / "t.json"), "cmd")
+    assert rec["kernel"] == "k_iter_ba"
+    reads = (400.0 + 60.0) / 4 * 2.0
+    writes = (200.0 + 8.0) / 4
+    assert rec["hbm_bytes_per_launch"] == (reads + writes) * 1024.0
