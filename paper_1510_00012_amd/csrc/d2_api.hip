@@ -890,13 +890,14 @@ d2_status launch_ba(d2_ctx* c, const d2k::Args<T>& a, int& nl) {
   const auto& kt = kern<T>();
   const int mi = ilog2(c->MP) - 3;
   const size_t per_wave = sizeof(double) * c->MP * (c->d + 1);
-  // FP32, 32 <= d <= 64: the support sums (MP 16 / 32) and the cost at a
-  // new support (MP 32) come from matrix-core passes of their own beside a
-  // plain launch (k_sup_mfma after it, k_cost_mfma before it)
-  const bool mfma_d = !c->onfly && c->d >= 32 && c->d <= 64;
-  const bool xo = a.xout && !a.recost && mfma_d && kt.sup[0][mi][0] != nullptr;
-  const bool cx = a.recost && !a.xout && mfma_d && c->MP == 32 &&
-                  kt.cst[0] != nullptr;
+  // FP32: the support sums (MP 16 / 32, 16 <= d <= 64) and the cost at a
+  // new support (MP 32, 32 <= d <= 64) come from matrix-core passes of
+  // their own beside a plain launch (k_sup_mfma after it, k_cost_mfma
+  // before it)
+  const bool xo = a.xout && !a.recost && !c->onfly && c->d >= 16 &&
+                  c->d <= 64 && kt.sup[0][mi][0] != nullptr;
+  const bool cx = a.recost && !a.xout && !c->onfly && c->d >= 32 &&
+                  c->d <= 64 && c->MP == 32 && kt.cst[0] != nullptr;
   // large d, first launch after a support update: the cost is recomputed
   // from the centroid support staged in LDS after the support records
   const bool want_stage = a.recost && !c->onfly;
@@ -917,7 +918,7 @@ d2_status launch_ba(d2_ctx* c, const d2k::Args<T>& a, int& nl) {
   while (wsup > 1 && !fits(per_wave * wsup)) --wsup;
   hipEvent_t pe = prof_begin(c);
   // plan state far beyond the last-level cache (256 MiB on this part):
-  // the plain launches stream it (non-temporal)
+  // the launches stream it (non-temporal)
   const bool nt = stream_state(c) && kt.bapn[c->onfly ? 1 : 0][0][0] != nullptr;
   // the buckets' launches write disjoint chunk records: side by side
   {
@@ -927,7 +928,8 @@ d2_status launch_ba(d2_ctx* c, const d2k::Args<T>& a, int& nl) {
   for (int b = 0; b < c->nbk; ++b) {
     const int rb = ilog2(c->bk_R[b]);
     const int oi = c->onfly ? 1 : 0;
-    auto fn = full ? kt.ba[oi][mi][rb]
+    auto fn = full ? (nt && !c->onfly && kt.ban[mi][rb] ? kt.ban[mi][rb]
+                                                        : kt.ba[oi][mi][rb])
               : nt ? kt.bapn[oi][mi][rb]
                    : kt.bap[oi][mi][rb];
     if (!fn) return c->fail(D2_EINVAL, "no kernel for this tile shape");

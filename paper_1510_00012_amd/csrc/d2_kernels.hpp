@@ -946,7 +946,7 @@ __device__ __forceinline__ void ba_tile(const Args<T>& a, const Tile<T, MP>& tl,
   if constexpr (!ONFLY && VAR != kVarPlain) {
     if (a.recost) {
 #pragma unroll
-      for (int r = 0; r < NS; ++r) bstore(cs[r], rC, eo[r]);
+      for (int r = 0; r < NS; ++r) bstore<CP>(cs[r], rC, eo[r]);
     }
   }
   if constexpr (VAR != kVarPlain) {
@@ -2099,6 +2099,7 @@ template <typename T> struct KernTable {
   BA ba[2][4][6] = {};  // [onfly][mp][r]
   BA bap[2][4][6] = {}; // the same without support terms
   BA bapn[2][4][6] = {}; // bap streaming its plan state (FP32)
+  BA ban[4][6] = {};    // ba streaming its plan state (FP32, d > 4)
   BA sup[2][4][6] = {}; // k_sup_mfma [stream][mp][r], FP32, MP 16 / 32
   BA cst[6] = {};       // k_cost_mfma, FP32, MP 32
   AX aux[4][6] = {};

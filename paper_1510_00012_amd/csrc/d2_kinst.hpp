@@ -24,6 +24,8 @@ void add_kernels(KernTable<T>& t) {
   } else {
     t.ba[0][a][b] = &k_iter_ba<T, MP, R, false>;
     t.ba[1][a][b] = &k_iter_ba<T, MP, R, true>;
+    if constexpr (sizeof(T) == 4)
+      t.ban[a][b] = &k_iter_ba<T, MP, R, false, kVarNone, kCpolStream>;
     if constexpr (sizeof(T) == 4 && (MP == 16 || MP == 32)) {
       t.sup[0][a][b] = &k_sup_mfma<MP, R, 0>;
       t.sup[1][a][b] = &k_sup_mfma<MP, R, kCpolStream>;
