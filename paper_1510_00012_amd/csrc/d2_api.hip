@@ -925,7 +925,10 @@ d2_status launch_ba(d2_ctx* c, const d2k::Args<T>& a, int& nl) {
     d2_status s = fork_side(c, c->nbk);
     if (s) return s;
   }
-  for (int b = 0; b < c->nbk; ++b) {
+  // widest slot class first: its launch has the fewest wavefronts per SIMD
+  // and the longest tiles, so it sets the end of the group
+  for (int bi = 0; bi < c->nbk; ++bi) {
+    const int b = c->nbk - 1 - bi;
     const int rb = ilog2(c->bk_R[b]);
     const int oi = c->onfly ? 1 : 0;
     auto fn = full ? (nt && !c->onfly && kt.ban[mi][rb] ? kt.ban[mi][rb]
@@ -938,7 +941,7 @@ d2_status launch_ba(d2_ctx* c, const d2k::Args<T>& a, int& nl) {
     ab.xstage = xstage;
     ab.bidx = b;
     ab.boff = c->bk_off[b];
-    hipStream_t st = stream_of(c, b);
+    hipStream_t st = stream_of(c, bi);
     if (cx) {
       hipLaunchKernelGGL(kt.cst[rb], dim3(c->bk_cap[b]), dim3(64 * c->waves),
                          d2k::cost_mfma_lds_bytes(c->xs, c->waves), st, ab);
