@@ -1496,8 +1496,9 @@ template <typename T> struct AssignArgs {
 
 // LDS of one assignment wavefront (byte offsets): the instance mean (d
 // values), |y_j - mu_P| and w_j per column (2 CPS R values), then for the
-// batched bounds a candidate list (128 ints) and the instance's points
-// (CPS R rows of xs floats).
+// batched bounds a candidate list (128 ints), the instance's points
+// centred on mu_P (CPS R rows of xs floats), their squared norms (CPS R)
+// and mu_P padded to xs.
 struct AssignLds {
   int list, ys, bytes;
 };
@@ -1506,7 +1507,7 @@ __host__ __device__ inline AssignLds assign_lds(int d, int MP, int R, int xs,
   AssignLds L;
   L.list = ((d + 2 * (64 / MP) * R) * esz + 15) & ~15;
   L.ys = L.list + (batch ? 128 * 4 : 0);
-  L.bytes = L.ys + (batch ? (64 / MP) * R * xs * 4 : 0);
+  L.bytes = L.ys + (batch ? ((64 / MP) * R * (xs + 1) + xs) * 4 : 0);
   return L;
 }
 
@@ -1708,14 +1709,22 @@ __device__ __forceinline__ T cheap_bound(const AssignArgs<T>& a, int c,
 }
 
 // Column-relaxed lower bound sum_j w_j min_i C_ij of the pair (this
-// wavefront's instance, centroid c), one centroid per lane: every cost
-// entry is formed with the operations of pair_costs in the same order (so
-// the minima are those of the tile-layout bound), the instance's points
-// and weights come from the wavefront's LDS (the same words for all lanes),
-// the centroid rows are the lane's own.  d <= 16, m_k <= MK.
+// wavefront's instance, centroid c), one centroid per lane, from the Gram
+// form of the cost over points centred on the instance mean mu:
+// C_ij = |x'_i|^2 + |y'_j|^2 - 2 x'_i . y'_j with x' = x - mu, y' = y - mu;
+// the column's own term |y'_j|^2 is constant over i and added after the
+// minimum.  Every FP32 step (centring, the three sums of at most 16
+// products, the last additions) errs by well under 64 u (|x'_i|^2 +
+// |y'_j|^2) in total (u = 2^-24); both squared norms are scaled by
+// 1 - 1e-5, a margin of about 168 u, so each entry stays below the exact
+// cost and the result a lower bound of the sum of exact minima.  The centred points y', their squared norms and mu are
+// in the wavefront's LDS (the same words for every lane); the centroid
+// rows are the lane's own.  d <= 16, m_k <= MK.
 template <int MP, int MK>
 __device__ __forceinline__ float lane_column_bound(const AssignArgs<float>& a,
                                                    const float* ys,
+                                                   const float* yy,
+                                                   const float* mu,
                                                    const float* swj, int mk,
                                                    int c) {
   const float big = 3.0e38f;
@@ -1727,38 +1736,49 @@ __device__ __forceinline__ float lane_column_bound(const AssignArgs<float>& a,
     const float4* xp =
         reinterpret_cast<const float4*>(a.xct + ((int64_t)c * MP + i) * a.xs);
     float4 xv[4];
+    float xx = 0.0f;
 #pragma unroll
-    for (int t4 = 0; t4 < 4; ++t4)
-      if (t4 < n4) xv[t4] = xp[t4];
+    for (int t4 = 0; t4 < 4; ++t4) {
+      if (t4 < n4) {
+        const float4 x = xp[t4];
+        const float4 u = reinterpret_cast<const float4*>(mu)[t4];
+        xv[t4] = make_float4(x.x - u.x, x.y - u.y, x.z - u.z, x.w - u.w);
+        xx = fmaf(xv[t4].x, xv[t4].x, xx);
+        xx = fmaf(xv[t4].y, xv[t4].y, xx);
+        xx = fmaf(xv[t4].z, xv[t4].z, xx);
+        xx = fmaf(xv[t4].w, xv[t4].w, xx);
+      }
+    }
+    const float xxm = xx * (1.0f - 1.0e-5f);
 #pragma unroll
     for (int j = 0; j < MK; ++j) {
       if (j < mk) {
         const float4* yp = reinterpret_cast<const float4*>(ys + j * a.xs);
-        float acc = 0.0f;
+        float dot = 0.0f;
 #pragma unroll
         for (int t4 = 0; t4 < 4; ++t4) {
           if (t4 < n4) {
             const float4 y = yp[t4];
-            float df = xv[t4].x - y.x;
-            acc = fmaf(df, df, acc);
-            df = xv[t4].y - y.y;
-            acc = fmaf(df, df, acc);
-            df = xv[t4].z - y.z;
-            acc = fmaf(df, df, acc);
-            df = xv[t4].w - y.w;
-            acc = fmaf(df, df, acc);
+            dot = fmaf(xv[t4].x, y.x, dot);
+            dot = fmaf(xv[t4].y, y.y, dot);
+            dot = fmaf(xv[t4].z, y.z, dot);
+            dot = fmaf(xv[t4].w, y.w, dot);
           }
         }
-        mn[j] = fminf(mn[j], acc);
+        mn[j] = fminf(mn[j], fmaf(-2.0f, dot, xxm));
       }
     }
   }
   float lb = 0.0f;
 #pragma unroll
-  for (int j = 0; j < MK; ++j)
-    if (j < mk)
-      lb = fmaf(swj[j] > 0.0f ? swj[j] : 0.0f, mn[j] < big ? mn[j] : 0.0f, lb);
-  return lb;
+  for (int j = 0; j < MK; ++j) {
+    if (j < mk) {
+      // the column's own term, constant over i, after the minimum
+      const float v = mn[j] < big ? mn[j] + yy[j] * (1.0f - 1.0e-5f) : 0.0f;
+      lb = fmaf(swj[j] > 0.0f ? swj[j] : 0.0f, v > 0.0f ? v : 0.0f, lb);
+    }
+  }
+  return lb * (1.0f - 4.0e-6f);  // at most 32 terms: FP32 sum within 32 u
 }
 
 template <typename T, int MP, int NS>
@@ -1874,9 +1894,24 @@ __device__ __forceinline__ void assign_tile(const AssignArgs<T>& a,
       // (the same decisions as one candidate at a time, on bounds formed
       // from the same cost entries).
       constexpr int MK = NS * Tile<T, MP>::CPS;
-      for (int f = 4 * lane; f < tl.mk * a.xs; f += 4 * kWave)
+      // the instance's points centred on mu_P, their squared norms and mu_P
+      // (padded with zeros to xs) into the wavefront's LDS
+      float* syy = sys + MK * a.xs;
+      float* smp = syy + MK;
+      for (int t = lane; t < a.xs; t += kWave) smp[t] = t < d ? smu[t] : 0.0f;
+      wave_lds_sync();
+      for (int f = 4 * lane; f < tl.mk * a.xs; f += 4 * kWave) {
+        const float4 y = *reinterpret_cast<const float4*>(a.X + tl.o * a.xs + f);
+        const float4 u = *reinterpret_cast<const float4*>(smp + f % a.xs);
         *reinterpret_cast<float4*>(sys + f) =
-            *reinterpret_cast<const float4*>(a.X + tl.o * a.xs + f);
+            make_float4(y.x - u.x, y.y - u.y, y.z - u.z, y.w - u.w);
+      }
+      wave_lds_sync();
+      for (int j = lane; j < tl.mk; j += kWave) {
+        float q = 0.0f;
+        for (int t = 0; t < a.xs; ++t) q = fmaf(sys[j * a.xs + t], sys[j * a.xs + t], q);
+        syy[j] = q;
+      }
       int nb = 0;
       for (int b0 = 0; b0 < a.K; b0 += kWave) {
         const int c = b0 + lane;
@@ -1914,8 +1949,8 @@ __device__ __forceinline__ void assign_tile(const AssignArgs<T>& a,
           const int cq = lane < nq ? slist[lane] : -1;
           const double lbq =
               cq >= 0 ? (double)lane_column_bound<MP, MK>(
-                            a, sys, reinterpret_cast<const float*>(swj),
-                            tl.mk, cq)
+                            a, sys, syy, smp,
+                            reinterpret_cast<const float*>(swj), tl.mk, cq)
                       : 0.0;
           if (a.lbs && cq >= 0) a.lbs[lrow + cq] = stored(lbq);
           ncost += nq;
