@@ -718,3 +718,35 @@ def test_cache_policy_is_bitwise_neutral(d2, name, m):
     for a, b in zip(p1, p2):
         for u, v in zip(a, b):
             assert np.array_equal(u, v)
+
+
+@pytest.mark.parametrize("shift", [0.0, 1000.0])
+def test_assignment_batched_bounds_far_from_origin(d2, shift):
+    """The batched candidate bounds (FP32, d <= 16, K >= 32) use the Gram
+    form of the cost over points centred on the instance mean, with a
+    rounding margin.  With every point and centroid shifted far from the
+    origin (where the uncentred expansion would cancel), pruned = exhaustive
+    bitwise, from the smallest-bound start and from the previous labels."""
+    print(f"[assign batched bounds shift={shift}]", flush=True)
+    wl = make_workload("gmm_d16_n2000000_k256", N=1200)
+    K, m = 48, 16
+    rng = np.random.Generator(np.random.PCG64(77))
+    Xc = wl["X"][rng.choice(len(wl["X"]), size=(K, m))]
+    Wc = rng.random((K, m)) + 0.05
+    Wc /= Wc.sum(1, keepdims=True)
+    wl = dict(wl, X=wl["X"] + shift)
+    Xc = Xc + shift
+    with _ctx(d2, wl, "f32") as ctx:
+        ctx.centroids_set(Xc, Wc)
+        lab_a, best_a, _ = ctx.assign(iters=60, prune=False)
+        lab_c, best_c, _ = ctx.assign(iters=60, prune=True)
+        ev_c, tot = ctx.assign_pairs()
+    with _ctx(d2, wl, "f32") as ctx:
+        ctx.centroids_set(Xc, Wc)
+        lab_b, best_b, _ = ctx.assign(iters=60, prune=True)
+        ev_b, _ = ctx.assign_pairs()
+    print(f"  pairs iterated: {ev_b} / {ev_c} of {tot}", flush=True)
+    assert ev_b < tot and ev_c < tot
+    for lab, best in ((lab_b, best_b), (lab_c, best_c)):
+        assert np.array_equal(lab, lab_a)
+        assert np.array_equal(best, best_a)
