@@ -898,6 +898,10 @@ d2_status launch_ba(d2_ctx* c, const d2k::Args<T>& a, int& nl) {
                   c->d <= 64 && kt.sup[0][mi][0] != nullptr;
   const bool cx = a.recost && !a.xout && !c->onfly && c->d >= 32 &&
                   c->d <= 64 && c->MP == 32 && kt.cst[0] != nullptr;
+  // otherwise (FP32, cost cached) the cost at a new support comes from a
+  // VALU pass before the plain launch
+  const bool cv = a.recost && !a.xout && !c->onfly && !cx &&
+                  kt.cstv[mi][0] != nullptr;
   // large d, first launch after a support update: the cost is recomputed
   // from the centroid support staged in LDS after the support records
   const bool want_stage = a.recost && !c->onfly;
@@ -906,7 +910,7 @@ d2_status launch_ba(d2_ctx* c, const d2k::Args<T>& a, int& nl) {
   auto fits = [](size_t b) { return b <= 64 * 1024; };
   // the full kernel forms what the passes do not; waves per workgroup are
   // lowered until its (or k_sup_mfma's) support records fit in LDS
-  const bool full = (a.xout && !xo) || (a.recost && !cx);
+  const bool full = (a.xout && !xo) || (a.recost && !cx && !cv);
   auto lds = [&](int wv) { return (a.xout ? per_wave * wv : 0) + stage; };
   int waves = c->waves;
   if (full)
@@ -945,6 +949,13 @@ d2_status launch_ba(d2_ctx* c, const d2k::Args<T>& a, int& nl) {
     if (cx) {
       hipLaunchKernelGGL(kt.cst[rb], dim3(c->bk_cap[b]), dim3(64 * c->waves),
                          d2k::cost_mfma_lds_bytes(c->xs, c->waves), st, ab);
+      HIPCHK(c, hipGetLastError());
+      ++nl;
+      ab.recost = 0;
+    } else if (cv) {
+      hipLaunchKernelGGL(kt.cstv[mi][rb], dim3(c->bk_cap[b]),
+                         dim3(64 * c->waves),
+                         (size_t)c->MP * (c->xs + 4) * sizeof(float), st, ab);
       HIPCHK(c, hipGetLastError());
       ++nl;
       ab.recost = 0;

@@ -1148,6 +1148,42 @@ __global__ void __launch_bounds__(256) k_cost_mfma(Args<float> a) {
   }
 }
 
+// Cost recomputation pass on the VALU (FP32, cost cached, where the
+// matrix-core pass does not apply): the cost of every tile at the new
+// support, by cost_tile from the support staged in LDS (the arithmetic of
+// the plan-update kernel's own recomputation), written to the cost cache
+// before the plain launch that first reads it.  Few registers, so that many
+// wavefronts hide the support loads.
+template <int MP, int R>
+__global__ void __launch_bounds__(256) k_cost_valu(Args<float> a) {
+  extern __shared__ double s_dyn[];  // the cluster's support, [MP][xs + 4]
+  int ch;
+  if (!chunk_of(a, ch)) return;
+  const Chunk cj = a.chunks[ch];
+  const int wave = uni(threadIdx.x / kWave), nwaves = blockDim.x / kWave;
+  float* xl = reinterpret_cast<float*>(s_dyn);
+  stage_support<float, MP>(a, cj.cluster, xl);
+  for (int pos = cj.begin + wave; pos < cj.end; pos += nwaves) {
+    Tile<float, MP> tl;
+    {
+      const int k = uni(a.work[pos]);
+      tl.set(a.m, a.off[k], a.off[k + 1], a.pofs[k]);
+    }
+    with_slots<R>(tl.nsl, [&]<int NS>() {
+      float cs[NS];
+      cost_tile<float, MP, NS>(a, tl, xl, cs);
+      const Rsrc rC =
+          make_rsrc(a.Cc + tl.base, (uint32_t)(a.m * tl.mk) * 4u);
+#pragma unroll
+      for (int r = 0; r < NS; ++r) {
+        const uint32_t j = (uint32_t)tl.col(r);
+        bstore(cs[r], rC,
+               tl.rowok ? (j * (uint32_t)a.m + (uint32_t)tl.i) * 4u : kOob);
+      }
+    });
+  }
+}
+
 template <int MP, int R, int CP>
 __global__ void __launch_bounds__(256, 2) k_sup_mfma(Args<float> a) {
   extern __shared__ double s_dyn[];  // [nwaves][MP][d+1] support terms
@@ -2137,6 +2173,7 @@ template <typename T> struct KernTable {
   BA ban[4][6] = {};    // ba streaming its plan state (FP32, d > 4)
   BA sup[2][4][6] = {}; // k_sup_mfma [stream][mp][r], FP32, MP 16 / 32
   BA cst[6] = {};       // k_cost_mfma, FP32, MP 32
+  BA cstv[4][6] = {};   // k_cost_valu [mp][r], FP32
   AX aux[4][6] = {};
   AX auxm[3][4][6] = {};  // fixed to kRho, kA0, kBF
   AS asg[4][6] = {};

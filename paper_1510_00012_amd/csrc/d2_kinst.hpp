@@ -31,6 +31,7 @@ void add_kernels(KernTable<T>& t) {
       t.sup[1][a][b] = &k_sup_mfma<MP, R, kCpolStream>;
     }
     if constexpr (sizeof(T) == 4 && MP == 32) t.cst[b] = &k_cost_mfma<R>;
+    if constexpr (sizeof(T) == 4) t.cstv[a][b] = &k_cost_valu<MP, R>;
     t.aux[a][b] = &k_aux<T, MP, R>;
     t.asg[a][b] = &k_assign<T, MP, R>;
   }
