@@ -183,6 +183,132 @@ def cpu_baseline(wl, Xc, Wc, labels, T, tau, T_assign, target_s=20.0):
                           f"instances (-> {ta1:.1f}s), extrapolated as above"}}
 
 
+def time_subgradient(ctx, N, iters, tau=10):
+    """The subgradient-descent refinement (Appendix A) on the context's
+    current labels and centroids: one exact transport LP per instance and
+    iteration (device network simplex), timed with HIP events by the
+    library."""
+    st = ctx.subgradient(iters=iters, tau=tau)
+    lps = N * iters
+    return {"iters": iters, "lps": lps, "ms": st["ms"],
+            "lp_per_s": lps / (st["ms"] / 1000.0),
+            "pivots_per_lp": st["pivots"] / lps,
+            "lp_failed": st["lp_failed"], "launches": st["launches"]}
+
+
+def symbolic_bytes(mods, ms, esz=4):
+    """Algorithmic bytes of one plan-update iteration over symbolic
+    supports (every modality): Pi1 and Lambda read and written and the cost
+    cache read per plan entry, symbol id and weight per support point,
+    offsets and work id per instance."""
+    b = 0
+    for md, m in zip(mods, ms):
+        n = int(md["offsets"][-1])
+        E = m * n
+        b += 5 * E * esz + n * (4 + esz) + (len(md["offsets"]) - 1) * 20
+    return b
+
+
+def bench_symbolic(args, wl, d2, torch):
+    """Rounds of D2-clustering over symbolic supports (Sec. 5: a symbol-to-
+    symbol cost table, no support step); several modalities (Sec. 5, last
+    paragraph) assign by the summed distance and update each modality's
+    centroids.  Initial centroids: the heaviest symbols of a seeded random
+    partition."""
+    from synth.generators import symbol_init_centroids
+    mods = wl.get("modalities") or [wl]
+    ms = wl["m"] if isinstance(wl["m"], tuple) else (wl["m"],)
+    K = wl["K"]
+    T = args.iters or wl["T"]
+    tau, T_assign = 10, 100
+    N = len(mods[0]["offsets"]) - 1
+    stream = torch.cuda.Stream()
+    rng = np.random.Generator(np.random.PCG64(wl["seed"] + 1))
+    lab0 = rng.integers(0, K, size=N).astype(np.int32)
+    ctxs = []
+    for md, m in zip(mods, ms):
+        ctx = d2.D2Context(0, "f32", stream=stream.cuda_stream)
+        ctx.load_instances_symbolic(md["offsets"], md["sym"], md["W"], md["D"])
+        csym, Wc = symbol_init_centroids(md, lab0, K, m)
+        ctx.centroids_set_symbolic(csym, Wc)
+        ctxs.append(ctx)
+    log(f"[bench] symbolic workload {args.workload}: N={N} modalities="
+        f"{len(ctxs)} K={K} m={ms} S={[md['S'] for md in mods]} T={T}")
+
+    def step(first):
+        if len(ctxs) == 1:
+            ctxs[0].assign(iters=T_assign, outputs=False)
+        else:
+            lab, _, _ = d2.assign_multi(ctxs, iters=T_assign)
+            for c in ctxs:
+                c.labels_set(lab)
+        tot = 0.0
+        for c in ctxs:
+            st = c.barycenter(iters=T, tau=tau,
+                              init=d2.D2_INIT_PRODUCT if first
+                              else d2.D2_INIT_CACHED)
+            tot += st["ms"]
+        return tot
+
+    for w in range(args.warmup):
+        step(w == 0)
+    bary_ms = []
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    for s_ in range(args.steps):
+        bary_ms.append(step(args.warmup == 0 and s_ == 0))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - ts
+    ks = {}
+    for c in ctxs:
+        c.set_profiling(True)
+        c.kernel_stats(reset=True)
+    for _ in range(args.profile_rounds):
+        step(False)
+    torch.cuda.synchronize()
+    for c in ctxs:
+        c.set_profiling(False)
+        for k, v in c.kernel_stats(reset=True).items():
+            n0, t0 = ks.get(k, (0, 0.0))
+            ks[k] = (n0 + v[0], t0 + v[1])
+    M = len(ctxs)
+    value = N * T * M * args.steps / elapsed
+    rec = {
+        "metric": "B-ADMM instance-iterations/s", "value": value,
+        "unit": "instance-iterations/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1000.0 * elapsed / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{args.workload}: one D2-clustering round "
+                               f"over symbolic supports ({M} modalities) = "
+                               f"assignment ({T_assign} transport iterations "
+                               f"per pair) + batched barycenter ({T} "
+                               f"iterations, support fixed) per modality",
+                   "N": N, "K": K, "m": list(ms),
+                   "S": [md["S"] for md in mods], "T": T,
+                   "T_assign": T_assign, "seed": wl["seed"]},
+        "barycenter_ms_mean": float(np.mean(bary_ms)),
+        "kernel_ms": {k: {"launches": v[0], "total_ms": v[1]}
+                      for k, v in ks.items()},
+    }
+    if "iter_ba" in ks:
+        launches, tot = ks["iter_ba"]
+        # one plan-update launch per modality and iteration
+        avg_s = tot / (launches / M) / 1000.0
+        b = symbolic_bytes(mods, ms)
+        rec["roofline_plan_update"] = {
+            "bound": "hbm", "achieved": b / avg_s / 1e9,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": b / avg_s / 1e9 / HBM_PEAK_GBS, "traffic": None,
+            "kernel": "k_iter_ba", "avg_iteration_ms": 1000 * avg_s,
+            "bytes_per_iteration": b}
+    if args.subgradient and M == 1:
+        rec["subgradient"] = time_subgradient(ctxs[0], N, args.subgradient)
+    for c in ctxs:
+        c.close()
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -200,6 +326,9 @@ def main():
                          "recorded one")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--subgradient", type=int, default=0,
+                    help="after the rounds, time this many iterations of "
+                         "the subgradient-descent refinement (exact LPs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the multi-GPU path (sharding "
@@ -216,6 +345,9 @@ def main():
         sys.exit(1)
     t0 = time.perf_counter()
     wl = make_workload(args.workload)
+    if "sym" in wl or "modalities" in wl:
+        bench_symbolic(args, wl, d2, torch)
+        return
     K, m = wl["K"], wl["m"]
     T = args.iters or wl["T"]
     tau, T_assign = 10, 100
@@ -362,6 +494,10 @@ def main():
     if not args.no_cpu_baseline:
         Xc, Wc = ctx.centroids_get()
         labels = ctx.labels_get()
+    if args.subgradient:
+        rec["subgradient"] = time_subgradient(ctx, N, args.subgradient)
+        log(f"[bench] subgradient: {rec['subgradient']}")
+    if not args.no_cpu_baseline:
         log("[bench] timing the FP64 CPU oracle on slices of the workload")
         rec["cpu_baseline"] = cpu_baseline(wl, Xc, Wc, labels, T, tau,
                                            T_assign,
