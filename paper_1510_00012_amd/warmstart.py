@@ -247,10 +247,12 @@ def evaluate(ws, family, cfg, seed, tau=10, ladder=LADDER, fix=50,
 
 
 def run(family, seed=0, steps=None, out=None, t_target=1000, tau=10,
-        save_params=None, params=None, untrained=True, fix=50):
+        save_params=None, params=None, untrained=True, fix=50, n_train=None):
     cfg = dict(FAMILIES[family])
     if steps is not None:
         cfg["steps"] = steps
+    if n_train is not None:
+        cfg["n_train"] = n_train
     m = cfg["m"]
     H = 128
     d = 3 if family == "gmm3" else 64
@@ -300,6 +302,8 @@ def main(argv=None):
     ap.add_argument("--family", default="gmm3", choices=sorted(FAMILIES))
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--n-train", type=int, default=None,
+                    help="training clusters (default: the family's)")
     ap.add_argument("--out", default=None)
     ap.add_argument("--save-params", default=None)
     ap.add_argument("--params", default=None,
@@ -308,7 +312,8 @@ def main(argv=None):
     ap.add_argument("--fix", type=int, default=50)
     a = ap.parse_args(argv)
     rep = run(a.family, a.seed, a.steps, a.out, save_params=a.save_params,
-              params=a.params, untrained=not a.no_untrained, fix=a.fix)
+              params=a.params, untrained=not a.no_untrained, fix=a.fix,
+              n_train=a.n_train)
     ev = rep["eval"]
     print(json.dumps({"family": rep["family"], "plain": ev["plain"],
                       "warm_probe": ev.get("warm_probe10"),
