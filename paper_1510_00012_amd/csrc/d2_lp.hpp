@@ -7,14 +7,24 @@
 // transportation problem in FP64, one wavefront per instance:
 //   * initial basis: the north-west corner rule (m + m_k - 1 basic cells,
 //     degenerate zero flows where a row and a column run out together);
-//   * potentials u_i + v_j = C_ij on the basic cells (u_0 = 0), spread over
-//     the basis tree from the root by parallel relaxation over its arcs,
-//     which also gives every node its tree parent and depth;
+//   * potentials u_i + v_j = C_ij on the basic cells (u_0 = 0) and the
+//     basis tree rooted at row 0 (parent, parent arc, depth of every node):
+//     once, spread from the root by parallel relaxation over the arcs;
 //   * pricing: the cell of most negative reduced cost C_ij - u_i - v_j
 //     (ties to the lowest cell) enters, until none is below -1e-12 max C;
 //   * the cycle it closes in the basis tree (the tree paths of its row and
 //     column up to their common ancestor) alternates -/+ from the entering
-//     cell; the "-" cell of least flow (first along the paths) leaves.
+//     cell; the "-" cell of least flow (first along the column's path, then
+//     the row's, each from the entering cell) leaves;
+//   * the tree is then kept instead of rebuilt: with ancestor tables
+//     (binary lifting, 7 levels for at most 128 nodes) every node finds in
+//     a fixed number of steps whether it lies on the cycle and whether it
+//     hangs below the leaving arc; that subtree is re-hung from the
+//     entering cell (the tree path from its endpoint up to the leaving arc
+//     reverses, depths follow from the common ancestors), and its
+//     potentials shift by the entering cell's reduced cost (+ on its
+//     endpoint's side, - on the other), so that every basic cell keeps a
+//     zero reduced cost.
 // The cost block lives in LDS (m x m_k doubles), the basis (cells, flows,
 // costs) and the tree (parent arc, depth) too.  Outputs per instance: the
 // optimal plan (in the plan layout of the context), the LP value, and the
@@ -30,6 +40,7 @@
 namespace d2s {
 
 constexpr int kArcs = 128;  // basis size m + m_k - 1 <= 127
+constexpr int kLevels = 7;  // ancestor table levels: depth < 128
 
 struct LpArgs {
   const int64_t* off;
@@ -62,11 +73,10 @@ struct LpLds {
   int16_t ai[kArcs];  // arc row
   int16_t aj[kArcs];  // arc column
   int16_t parc[kArcs];  // tree: arc to the parent (-1 at the root)
+  int16_t par[kArcs];   // tree: parent node (-1 at the root)
   int16_t dep[kArcs];   // tree depth
   int8_t known[kArcs];
-  int16_t cyc[kArcs];   // cycle arcs (a side, then b side)
-  int16_t pb[kArcs];    // b-side path while it is walked
-  int8_t sgn[kArcs];    // their signs (-1 / +1)
+  int16_t anc[7][kArcs];  // ancestor 2^k levels up (the root: itself)
   int broken;           // the basis stopped being a spanning tree
 };
 
@@ -159,37 +169,66 @@ __global__ void __launch_bounds__(256) k_lp_transport(LpArgs a) {
   wsync();
   int piv = 0;
   bool capped = false;
-  for (;;) {
-    // potentials and the basis tree, spread from the root (row 0)
-    for (int q = lane; q < nn; q += 64) {
-      s.known[q] = (int8_t)(q == 0);
-      s.dep[q] = 0;
-      s.parc[q] = -1;
-    }
-    if (lane == 0) s.u[0] = 0.0;
-    wsync();
-    for (;;) {
-      bool ch = false;
-      for (int e = lane; e < na; e += 64) {
-        const int i = s.ai[e], j = s.aj[e], cj = m + j;
-        const bool ki = s.known[i] != 0, kj = s.known[cj] != 0;
-        if (ki && !kj) {
-          s.v[j] = s.ac[e] - s.u[i];
-          s.parc[cj] = (int16_t)e;
-          s.dep[cj] = (int16_t)(s.dep[i] + 1);
-          s.known[cj] = 1;
-          ch = true;
-        } else if (kj && !ki) {
-          s.u[i] = s.ac[e] - s.v[j];
-          s.parc[i] = (int16_t)e;
-          s.dep[i] = (int16_t)(s.dep[cj] + 1);
-          s.known[i] = 1;
-          ch = true;
-        }
+  // potentials and the basis tree, spread from the root (row 0), once
+  for (int q = lane; q < nn; q += 64) {
+    s.known[q] = (int8_t)(q == 0);
+    s.dep[q] = 0;
+    s.parc[q] = -1;
+    s.par[q] = -1;
+  }
+  if (lane == 0) s.u[0] = 0.0;
+  wsync();
+  for (int pass = 0; pass < nn; ++pass) {
+    bool ch = false;
+    for (int e = lane; e < na; e += 64) {
+      const int i = s.ai[e], j = s.aj[e], cj = m + j;
+      const bool ki = s.known[i] != 0, kj = s.known[cj] != 0;
+      if (ki && !kj) {
+        s.v[j] = s.ac[e] - s.u[i];
+        s.parc[cj] = (int16_t)e;
+        s.par[cj] = (int16_t)i;
+        s.dep[cj] = (int16_t)(s.dep[i] + 1);
+        s.known[cj] = 1;
+        ch = true;
+      } else if (kj && !ki) {
+        s.u[i] = s.ac[e] - s.v[j];
+        s.parc[i] = (int16_t)e;
+        s.par[i] = (int16_t)cj;
+        s.dep[i] = (int16_t)(s.dep[cj] + 1);
+        s.known[i] = 1;
+        ch = true;
       }
-      wsync();
-      if (!__any(ch)) break;
     }
+    wsync();
+    if (!__any(ch)) break;
+  }
+  // the ancestor of q `up` levels above (0 <= up < 128), by the tables
+  auto lift = [&](int q, int up) {
+#pragma unroll
+    for (int k = 0; k < kLevels; ++k)
+      if ((up >> k) & 1) q = s.anc[k][q];
+    return q;
+  };
+  // the common ancestor of a and b
+  auto lca = [&](int x, int y) {
+    if (s.dep[x] < s.dep[y]) {
+      const int t = x;
+      x = y;
+      y = t;
+    }
+    x = lift(x, s.dep[x] - s.dep[y]);
+    if (x == y) return x;
+#pragma unroll
+    for (int k = kLevels - 1; k >= 0; --k) {
+      const int ax = s.anc[k][x], ay = s.anc[k][y];
+      if (ax != ay) {
+        x = ax;
+        y = ay;
+      }
+    }
+    return (int)s.anc[0][x];
+  };
+  for (;;) {
     // pricing: most negative reduced cost, ties to the lowest cell
     double best = 0.0;
     int bc = 0x7fffffff;
@@ -215,73 +254,128 @@ __global__ void __launch_bounds__(256) k_lp_transport(LpArgs a) {
       break;
     }
     ++piv;
-    // the cycle closed by the entering cell, and the pivot (one lane).
-    // Every walk is bounded by the node count and checks its arcs, so a
-    // basis that is not a spanning tree ends the solve (counted as
-    // failed) instead of looping.
-    if (lane == 0) {
-      const int ie = bc % m, je = bc / m;
-      int x = m + je, y = ie, nx = 0, ny = 0;
-      int16_t* pb = s.pb;
-      bool ok = s.known[x] && s.known[y];
-      auto up = [&](int node) {
-        const int e = s.parc[node];
-        if (e < 0 || e >= na) {
-          ok = false;
-          return 0;
-        }
-        return node < m ? m + (int)s.aj[e] : (int)s.ai[e];
-      };
-      while (ok && s.dep[x] > s.dep[y] && nx < na) {
-        s.cyc[nx++] = s.parc[x];
-        x = up(x);
-      }
-      while (ok && s.dep[y] > s.dep[x] && ny < na) {
-        pb[ny++] = s.parc[y];
-        y = up(y);
-      }
-      while (ok && x != y && nx < na && ny < na) {
-        s.cyc[nx++] = s.parc[x];
-        x = up(x);
-        pb[ny++] = s.parc[y];
-        y = up(y);
-      }
-      // one side is empty when the entering cell's row is an ancestor of
-      // its column in the tree (or the reverse)
-      ok = ok && x == y && nx + ny >= 1 && nx + ny <= kArcs;
-      int lv = -1;
-      double th = 1e300;
-      if (ok) {
-        for (int q = 0; q < nx; ++q) s.sgn[q] = (q & 1) ? 1 : -1;
-        for (int q = 0; q < ny; ++q) {
-          s.cyc[nx + q] = pb[q];
-          s.sgn[nx + q] = (q & 1) ? 1 : -1;
-        }
-        for (int q = 0; q < nx + ny; ++q)
-          if (s.sgn[q] < 0 && s.af[s.cyc[q]] < th) {
-            th = s.af[s.cyc[q]];
-            lv = s.cyc[q];
-          }
-        ok = lv >= 0;
-      }
-      if (ok) {
-        for (int q = 0; q < nx + ny; ++q) {
-          const int e = s.cyc[q];
-          const double f = s.af[e] + (double)s.sgn[q] * th;
-          s.af[e] = f > 0.0 ? f : 0.0;
-        }
-        s.ai[lv] = (int16_t)ie;
-        s.aj[lv] = (int16_t)je;
-        s.af[lv] = th;
-        s.ac[lv] = C[bc];
-      }
-      s.broken = ok ? 0 : 1;
-    }
+    const int ie = bc % m, je = bc / m;
+    // ancestor tables of the current tree
+    for (int q = lane; q < nn; q += 64)
+      s.anc[0][q] = s.par[q] < 0 ? (int16_t)q : s.par[q];
     wsync();
-    if (s.broken) {
+#pragma unroll
+    for (int k = 1; k < kLevels; ++k) {
+      for (int q = lane; q < nn; q += 64) s.anc[k][q] = s.anc[k - 1][s.anc[k - 1][q]];
+      wsync();
+    }
+    // the cycle: nodes strictly below the common ancestor on the paths from
+    // the entering cell's column (side 0) and row (side 1); a node's arc to
+    // its parent is on the cycle, "-" at even positions from the cell
+    const int nA = m + je, nB = ie;
+    const int top = lca(nA, nB);
+    const int dtop = s.dep[top];
+    int side[2] = {-1, -1}, pos[2] = {0, 0};
+    double lf = 1e300;
+    int lkey = 0x7fffffff, lnode = -1;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int q = lane + 64 * h;
+      if (q >= nn) continue;
+      const int dq = s.dep[q];
+      if (dq > dtop) {
+        if (dq <= s.dep[nA] && lift(nA, s.dep[nA] - dq) == q) {
+          side[h] = 0;
+          pos[h] = s.dep[nA] - dq;
+        } else if (dq <= s.dep[nB] && lift(nB, s.dep[nB] - dq) == q) {
+          side[h] = 1;
+          pos[h] = s.dep[nB] - dq;
+        }
+      }
+      if (side[h] >= 0 && (pos[h] & 1) == 0) {
+        const double f = s.af[s.parc[q]];
+        const int key = side[h] * 256 + pos[h];
+        if (f < lf || (f == lf && key < lkey)) {
+          lf = f;
+          lkey = key;
+          lnode = q;
+        }
+      }
+    }
+    // leaving cell: least flow among the "-" cells, first along the paths
+    for (int off2 = 32; off2 > 0; off2 >>= 1) {
+      const double of = __shfl_xor(lf, off2);
+      const int ok = __shfl_xor(lkey, off2);
+      const int on = __shfl_xor(lnode, off2);
+      if (of < lf || (of == lf && ok < lkey)) {
+        lf = of;
+        lkey = ok;
+        lnode = on;
+      }
+    }
+    if (lnode < 0) {  // no "-" cell: the basis is not a spanning tree
       capped = true;
       break;
     }
+    const double th = lf;
+    const int cl = lnode;                 // the leaving arc's lower node
+    const int lside = lkey >> 8, lpos = lkey & 255;
+    const int lv = s.parc[cl];
+    const int es = lside == 0 ? nA : nB;  // entering endpoint below it
+    const int other = lside == 0 ? nB : nA;
+    const int dcl = s.dep[cl], des = s.dep[es], dot = s.dep[other];
+    // phase 1 (reads of the old tree): flows, subtree, new depths, the
+    // re-hung path
+    int wpar[2] = {-1, -1}, wparc[2] = {-1, -1}, ndep[2] = {-1, -1};
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int q = lane + 64 * h;
+      if (q >= nn) continue;
+      const int dq = s.dep[q];
+      if (dq >= dcl && lift(q, dq - dcl) == cl)
+        ndep[h] = dot + 1 + dq + des - 2 * s.dep[lca(q, es)];
+      if (side[h] == lside && pos[h] <= lpos && q != cl) {
+        wpar[h] = s.par[q];
+        wparc[h] = s.parc[q];
+      }
+    }
+    wsync();
+    // phase 2 (writes): flows on the cycle, potentials and depths of the
+    // subtree, parents along the re-hung path, then the entering cell in
+    // the leaving cell's slot
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int q = lane + 64 * h;
+      if (q >= nn) continue;
+      if (side[h] >= 0) {
+        const int e = s.parc[q];
+        const double f = s.af[e] + ((pos[h] & 1) ? th : -th);
+        s.af[e] = f > 0.0 ? f : 0.0;
+      }
+      if (ndep[h] >= 0) {
+        // the entering endpoint's side moves by +best, the other by -best
+        const bool rowq = q < m;
+        const double sh = (rowq == (es < m)) ? best : -best;
+        if (rowq)
+          s.u[q] += sh;
+        else
+          s.v[q - m] += sh;
+        s.dep[q] = (int16_t)ndep[h];
+      }
+    }
+    wsync();
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      if (wpar[h] >= 0) {
+        const int q = lane + 64 * h;
+        s.par[wpar[h]] = (int16_t)q;
+        s.parc[wpar[h]] = (int16_t)wparc[h];
+      }
+    }
+    if (lane == 0) {
+      s.par[es] = (int16_t)other;
+      s.parc[es] = (int16_t)lv;
+      s.ai[lv] = (int16_t)ie;
+      s.aj[lv] = (int16_t)je;
+      s.af[lv] = th;
+      s.ac[lv] = C[bc];
+    }
+    wsync();
   }
   // plan (basic cells carry their flow), value and projected row duals
   const int64_t pb0 = a.pofs[k];
