@@ -76,8 +76,7 @@ struct LpLds {
   int16_t par[kArcs];   // tree: parent node (-1 at the root)
   int16_t dep[kArcs];   // tree depth
   int8_t known[kArcs];
-  int16_t anc[7][kArcs];  // ancestor 2^k levels up (the root: itself)
-  int broken;           // the basis stopped being a spanning tree
+  int16_t anc[kLevels][kArcs];  // ancestor 2^k levels up (root: itself)
 };
 
 // Order this wavefront's LDS accesses across lanes (the wavefront's LDS
