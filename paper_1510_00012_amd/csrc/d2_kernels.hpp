@@ -46,6 +46,7 @@
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
+#include <utility>
 #include <stdint.h>
 
 namespace d2k {
@@ -160,6 +161,120 @@ __device__ __forceinline__ void sum_col_n(T (&v)[NS]) {
 #pragma unroll
     for (int r = 0; r < NS; ++r) v[r] += x32(v[r]);
   }
+}
+
+// Column sums by reduce-scatter (column groups of MP >= 16 lanes).  A
+// lane's NS slots go in chunks of C = 8, 4, 2 or 1 slots, and register t of
+// a chunk holds slot t ^ mask(lane & 3).  An exchange with the quad lane of
+// the other parity adds, for the half of the chunk a lane keeps, the
+// partner's values of the same slots; an exchange with the other pair of
+// the quad halves the kept part again.  Each quad lane so ends with the
+// quad sums of max(1, C/4) slots, which are then summed over the quads of
+// the column group (row rotations by 8 and by 4, then across rows).  The
+// mask places what a lane sends at the register index its partner keeps,
+// so the exchanges need no selects.  Each sum is formed in one lane per
+// quad and is bitwise the same in every quad of the group: the exchanges
+// pair lanes symmetrically (xor 1, 2, 8), and the last one, the rotation by
+// 4, adds two values that are already equal across lanes 8 apart.
+constexpr int rs_chunk_size(int left) {
+  return left >= 8 ? 8 : (left >= 4 ? 4 : (left >= 2 ? 2 : 1));
+}
+template <int C> struct RsChunk {
+  static constexpr int kept = C >= 8 ? 2 : 1;
+  static constexpr int mask(int ql) {
+    return C >= 4 ? (ql & 1) * (C / 2) + ((ql >> 1) & 1) * (C / 4)
+                  : (C == 2 ? (ql & 1) : 0);
+  }
+  // quad_perm control by which each lane reads, for its chunk register t,
+  // the value of that register's slot from the quad lane holding its sum
+  // (at that lane's register t & (kept - 1))
+  static constexpr int bcast(int t) {
+    int ctrl = 0;
+    for (int j = 0; j < 4; ++j) {
+      const int want = (t ^ mask(j)) & ~(kept - 1);
+      int o = j;
+      if (C > 1)
+        for (int ql = 3; ql >= 0; --ql)
+          if (mask(ql) == want && (C != 2 || ((ql ^ j) & 2) == 0)) o = ql;
+      ctrl |= o << (2 * j);
+    }
+    return ctrl;
+  }
+};
+// kept registers of the chunks before slot c0 (c0 a chunk start; c0 = NS:
+// all of them)
+constexpr int rs_kept_before(int c0) {
+  int n = 0;
+  for (int c = 0; c < c0;) {
+    const int C = rs_chunk_size(c0 - c);
+    n += C >= 8 ? 2 : 1;
+    c += C;
+  }
+  return n;
+}
+// f.template operator()<C0, C>() for every chunk, in slot order
+template <int NS, int C0 = 0, typename F>
+__device__ __forceinline__ void rs_chunks(F&& f) {
+  if constexpr (C0 < NS) {
+    constexpr int C = rs_chunk_size(NS - C0);
+    f.template operator()<C0, C>();
+    rs_chunks<NS, C0 + C>(f);
+  }
+}
+// Slot value x[C0 + (t ^ mask(ql))] of chunk register t, from a lane's
+// values in slot order.  The candidates pass through an empty asm statement
+// first, so that the selects stay selects between registers instead of
+// becoming a lane-dependent index into the array (which would live in
+// scratch memory).
+template <int C0, int C, int t, int NS, typename T>
+__device__ __forceinline__ T rs_pick(const T (&x)[NS], int ql) {
+  if constexpr (C == 1) {
+    return x[C0 + t];
+  } else if constexpr (C == 2) {
+    T v0 = x[C0 + t], v1 = x[C0 + (t ^ 1)];
+    asm volatile("" : "+v"(v0), "+v"(v1));
+    return (ql & 1) ? v1 : v0;
+  } else {
+    T v0 = x[C0 + t], v1 = x[C0 + (t ^ (C / 2))];
+    T v2 = x[C0 + (t ^ (C / 4))], v3 = x[C0 + (t ^ (C / 4) ^ (C / 2))];
+    asm volatile("" : "+v"(v0), "+v"(v1), "+v"(v2), "+v"(v3));
+    const T lo = (ql & 1) ? v1 : v0;
+    const T hi = (ql & 1) ? v3 : v2;
+    return (ql & 2) ? hi : lo;
+  }
+}
+// Sums over the column group of the chunk's C values s[0, C): on return
+// s[0, kept) hold the sums of the slots of this lane's first kept
+// registers.
+template <int MP, int C, typename T>
+__device__ __forceinline__ void rs_sum(T (&s)[C]) {
+  static_assert(MP >= 16, "reduce-scatter spans whole DPP rows");
+  constexpr int K = RsChunk<C>::kept;
+  if constexpr (C >= 2) {
+#pragma unroll
+    for (int k = 0; k < C / 2; ++k) s[k] += xdpp<0xB1>(s[k + C / 2]);
+  }
+  if constexpr (C >= 4) {
+#pragma unroll
+    for (int k = 0; k < C / 4; ++k) s[k] += xdpp<0x4E>(s[k + C / 4]);
+  }
+  if constexpr (C == 1) s[0] += xdpp<0xB1>(s[0]);
+  if constexpr (C <= 2) s[0] += xdpp<0x4E>(s[0]);
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    s[k] += xdpp<0x128>(s[k]);  // row_ror:8 (lane ^ 8)
+    s[k] += xdpp<0x124>(s[k]);  // row_ror:4
+    if constexpr (MP >= 32) s[k] += xswz16(s[k]);
+    if constexpr (MP >= 64) s[k] += x32(s[k]);
+  }
+}
+// value of chunk register t's slot from the quad lane that holds it
+template <int C, int T_, typename T>
+__device__ __forceinline__ T rs_get(const T (&f)[RsChunk<C>::kept]) {
+  constexpr int ctrl = RsChunk<C>::bcast(T_);
+  const T v = f[T_ & (RsChunk<C>::kept - 1)];
+  if constexpr (ctrl == 0xE4) return v;  // quad_perm [0,1,2,3]
+  else return xdpp<ctrl>(v);
 }
 
 // support point of a column for the on-the-fly cost (d <= 4, stride 4)
@@ -1672,11 +1787,84 @@ __device__ __forceinline__ double pair_value(const AssignArgs<T>& a,
   T ca[NS], p2[NS], l[NS], q[NS];
 #pragma unroll
   for (int r = 0; r < NS; ++r) {
-    // exp2(-1e30) = 0: an entry outside the tile never takes mass
-    ca[r] = tl.valid(r) ? cs[r] * a2 : T(1.0e30);
-    p2[r] = wi * wk[r];
     l[r] = T(0);
     q[r] = T(0);
+  }
+  // exp2(-1e30) = 0: an entry outside the tile never takes mass
+  if constexpr (sizeof(T) == 4 && MP >= 16 && NS <= 8) {
+    // Column normalisation by reduce-scatter: the column sums and the
+    // factors w_j / sum are formed once per quad instead of in every lane
+    // (about a quarter fewer instructions per entry and iteration; past 8
+    // slots the compiler needs more registers for it, which would lower the
+    // occupancy of the kernels for wide tiles).
+    const int ql = threadIdx.x & 3;
+    // weights of the slots whose sums this lane holds (the chunks' kept
+    // registers), in chunk order, taken from the first lane of the quad:
+    // rows past m hold zero weights, and a quad with any row below m has
+    // its first row below m
+    T wq[NS], wr[rs_kept_before(NS)];
+#pragma unroll
+    for (int r = 0; r < NS; ++r)
+      wq[r] = xdpp<0x00>(wk[r]);  // quad_perm [0,0,0,0]
+    rs_chunks<NS>([&]<int C0, int C>() {
+      constexpr int n = rs_kept_before(C0);
+      wr[n] = rs_pick<C0, C, 0>(wq, ql);
+      if constexpr (RsChunk<C>::kept == 2) wr[n + 1] = rs_pick<C0, C, 1>(wq, ql);
+    });
+    // scaled costs and Pi2 of the slots in this lane's register order
+    rs_chunks<NS>([&]<int C0, int C>() {
+      [&]<int... U>(std::integer_sequence<int, U...>) {
+        ((ca[C0 + U] =
+              tl.rowok && tl.g + Tile<T, MP>::CPS *
+                                     (C0 + (U ^ RsChunk<C>::mask(ql))) <
+                              tl.mk
+                  ? rs_pick<C0, C, U>(cs, ql) * a2
+                  : T(1.0e30),
+          p2[C0 + U] = wi * rs_pick<C0, C, U>(wk, ql)),
+         ...);
+      }(std::make_integer_sequence<int, C>{});
+    });
+    for (int it = 0; it < a.iters; ++it) {
+      T rr = T(0);
+      rs_chunks<NS>([&]<int C0, int C>() {
+        constexpr int K = RsChunk<C>::kept;
+        T E[C], s[C];
+#pragma unroll
+        for (int u = 0; u < C; ++u) {
+          const int r = C0 + u;
+          E[u] = dexp2(l[r] * a2);
+          q[r] = fma(p2[r], dexp2(-fma(l[r], a2, ca[r])), elr);
+          s[u] = q[r];
+        }
+        rs_sum<MP, C>(s);
+        T f[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+          f[k] = wr[rs_kept_before(C0) + k] * rcp_sum(s[k]);
+        [&]<int... U>(std::integer_sequence<int, U...>) {
+          ((q[C0 + U] *= rs_get<C, U>(f),
+            p2[C0 + U] = fma(q[C0 + U], E[U], elr), rr += p2[C0 + U]),
+           ...);
+        }(std::make_integer_sequence<int, C>{});
+      });
+      rr = sum_row<MP>(rr) - pad;
+      const T coef = wi * rcp_sum(rr);
+#pragma unroll
+      for (int r = 0; r < NS; ++r) {
+        const T u = p2[r] * coef;
+        l[r] = fma(rho, q[r] - u, l[r]);
+        p2[r] = u;
+      }
+    }
+    T fv = T(0);
+#pragma unroll
+    for (int r = 0; r < NS; ++r) fv = fma(ca[r], q[r], fv);
+    return sum_wave((double)fv) * (rhod / kLog2e);
+  }
+#pragma unroll
+  for (int r = 0; r < NS; ++r) {
+    ca[r] = tl.valid(r) ? cs[r] * a2 : T(1.0e30);
+    p2[r] = wi * wk[r];
   }
   // slots in chunks of CH: exp(Lambda/rho) and the column sums are held
   // for one chunk at a time
