@@ -221,26 +221,32 @@ __device__ __forceinline__ void rs_chunks(F&& f) {
     rs_chunks<NS, C0 + C>(f);
   }
 }
-// Slot value x[C0 + (t ^ mask(ql))] of chunk register t, from a lane's
-// values in slot order.  The candidates pass through an empty asm statement
-// first, so that the selects stay selects between registers instead of
-// becoming a lane-dependent index into the array (which would live in
-// scratch memory).
-template <int C0, int C, int t, int NS, typename T>
-__device__ __forceinline__ T rs_pick(const T (&x)[NS], int ql) {
+// Per-lane select written as one v_cndmask_b32 (lanes whose bit in m is set
+// take b): as plain code, a select between elements of an array is folded
+// into a lane-dependent index into the array, which then lives in scratch.
+__device__ __forceinline__ float lane_sel(float a, float b,
+                                          unsigned long long m) {
+  float r;
+  asm("v_cndmask_b32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(m));
+  return r;
+}
+// Slot value x[C0 + (t ^ mask(lane & 3))] of chunk register t, from a
+// lane's values in slot order (Q0: those of the first lane of its quad).
+template <int C0, int C, int t, bool Q0 = false, int NS>
+__device__ __forceinline__ float rs_pick(const float (&x)[NS]) {
+  constexpr unsigned long long kOdd = 0xAAAAAAAAAAAAAAAAull;   // lane & 1
+  constexpr unsigned long long kPair = 0xCCCCCCCCCCCCCCCCull;  // lane & 2
+  auto val = [&](int r) { return Q0 ? xdpp<0x00>(x[r]) : x[r]; };
   if constexpr (C == 1) {
-    return x[C0 + t];
+    return val(C0 + t);
   } else if constexpr (C == 2) {
-    T v0 = x[C0 + t], v1 = x[C0 + (t ^ 1)];
-    asm volatile("" : "+v"(v0), "+v"(v1));
-    return (ql & 1) ? v1 : v0;
+    return lane_sel(val(C0 + t), val(C0 + (t ^ 1)), kOdd);
   } else {
-    T v0 = x[C0 + t], v1 = x[C0 + (t ^ (C / 2))];
-    T v2 = x[C0 + (t ^ (C / 4))], v3 = x[C0 + (t ^ (C / 4) ^ (C / 2))];
-    asm volatile("" : "+v"(v0), "+v"(v1), "+v"(v2), "+v"(v3));
-    const T lo = (ql & 1) ? v1 : v0;
-    const T hi = (ql & 1) ? v3 : v2;
-    return (ql & 2) ? hi : lo;
+    const float lo =
+        lane_sel(val(C0 + t), val(C0 + (t ^ (C / 2))), kOdd);
+    const float hi = lane_sel(val(C0 + (t ^ (C / 4))),
+                              val(C0 + (t ^ (C / 4) ^ (C / 2))), kOdd);
+    return lane_sel(lo, hi, kPair);
   }
 }
 // Sums over the column group of the chunk's C values s[0, C): on return
@@ -1791,25 +1797,23 @@ __device__ __forceinline__ double pair_value(const AssignArgs<T>& a,
     q[r] = T(0);
   }
   // exp2(-1e30) = 0: an entry outside the tile never takes mass
-  if constexpr (sizeof(T) == 4 && MP >= 16 && NS <= 8) {
+  if constexpr (sizeof(T) == 4 && MP >= 16 && NS <= (MP >= 32 ? 32 : 8)) {
     // Column normalisation by reduce-scatter: the column sums and the
     // factors w_j / sum are formed once per quad instead of in every lane
-    // (about a quarter fewer instructions per entry and iteration; past 8
-    // slots the compiler needs more registers for it, which would lower the
-    // occupancy of the kernels for wide tiles).
+    // (about a quarter fewer instructions per entry and iteration).  Tiles
+    // of 16 rows use it up to 8 slots only: the 16-slot kernel of that row
+    // padding would need 20 more registers and lose a wavefront per SIMD.
     const int ql = threadIdx.x & 3;
     // weights of the slots whose sums this lane holds (the chunks' kept
     // registers), in chunk order, taken from the first lane of the quad:
     // rows past m hold zero weights, and a quad with any row below m has
     // its first row below m
-    T wq[NS], wr[rs_kept_before(NS)];
-#pragma unroll
-    for (int r = 0; r < NS; ++r)
-      wq[r] = xdpp<0x00>(wk[r]);  // quad_perm [0,0,0,0]
+    T wr[rs_kept_before(NS)];
     rs_chunks<NS>([&]<int C0, int C>() {
       constexpr int n = rs_kept_before(C0);
-      wr[n] = rs_pick<C0, C, 0>(wq, ql);
-      if constexpr (RsChunk<C>::kept == 2) wr[n + 1] = rs_pick<C0, C, 1>(wq, ql);
+      wr[n] = rs_pick<C0, C, 0, true>(wk);
+      if constexpr (RsChunk<C>::kept == 2)
+        wr[n + 1] = rs_pick<C0, C, 1, true>(wk);
     });
     // scaled costs and Pi2 of the slots in this lane's register order
     rs_chunks<NS>([&]<int C0, int C>() {
@@ -1818,9 +1822,9 @@ __device__ __forceinline__ double pair_value(const AssignArgs<T>& a,
               tl.rowok && tl.g + Tile<T, MP>::CPS *
                                      (C0 + (U ^ RsChunk<C>::mask(ql))) <
                               tl.mk
-                  ? rs_pick<C0, C, U>(cs, ql) * a2
+                  ? rs_pick<C0, C, U>(cs) * a2
                   : T(1.0e30),
-          p2[C0 + U] = wi * rs_pick<C0, C, U>(wk, ql)),
+          p2[C0 + U] = wi * rs_pick<C0, C, U>(wk)),
          ...);
       }(std::make_integer_sequence<int, C>{});
     });
