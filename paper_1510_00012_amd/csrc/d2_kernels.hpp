@@ -1828,6 +1828,12 @@ __device__ __forceinline__ double pair_value(const AssignArgs<T>& a,
          ...);
       }(std::make_integer_sequence<int, C>{});
     });
+    // For 16-row tiles l holds Lambda / rho in base-2 units (Lambda * a2):
+    // its update rho * (Pi1 - Pi2) becomes log2(e) * (Pi1 - Pi2), and the
+    // exponents need no multiply (measured 2-5 % faster there, 2 % slower
+    // for 32-row tiles, which keep Lambda itself)
+    constexpr bool SL = MP == 16;
+    const T lu = SL ? T(kLog2e) : rho;
     for (int it = 0; it < a.iters; ++it) {
       T rr = T(0);
       rs_chunks<NS>([&]<int C0, int C>() {
@@ -1836,8 +1842,10 @@ __device__ __forceinline__ double pair_value(const AssignArgs<T>& a,
 #pragma unroll
         for (int u = 0; u < C; ++u) {
           const int r = C0 + u;
-          E[u] = dexp2(l[r] * a2);
-          q[r] = fma(p2[r], dexp2(-fma(l[r], a2, ca[r])), elr);
+          E[u] = dexp2(SL ? l[r] : l[r] * a2);
+          q[r] = fma(p2[r],
+                     dexp2(SL ? -(l[r] + ca[r]) : -fma(l[r], a2, ca[r])),
+                     elr);
           s[u] = q[r];
         }
         rs_sum<MP, C>(s);
@@ -1856,7 +1864,7 @@ __device__ __forceinline__ double pair_value(const AssignArgs<T>& a,
 #pragma unroll
       for (int r = 0; r < NS; ++r) {
         const T u = p2[r] * coef;
-        l[r] = fma(rho, q[r] - u, l[r]);
+        l[r] = fma(lu, q[r] - u, l[r]);
         p2[r] = u;
       }
     }
