@@ -608,10 +608,12 @@ def test_matrix_core_paths_ragged(d2, d, m, mk_hi):
 
 
 @pytest.mark.parametrize("d,m,mk_hi", [(5, 16, 30), (37, 20, 40),
-                                       (13, 9, 60)])
+                                       (13, 9, 60), (7, 40, 30), (6, 5, 50)])
 def test_assignment_bound_odd_shapes(d2, d, m, mk_hi):
     """Pruned assignment with odd d (stride padding), m below its tile
-    padding, ragged m_k up to 60 and more centroids than lanes, on points
+    padding (tiles of 64, 32, 16 and 8 rows: the transport's column sums by
+    reduce-scatter and per lane), ragged m_k up to mk_hi and more centroids
+    than lanes, on points
     far from the origin: pruning stays exact (labels and distances bitwise
     those of the exhaustive search) and labels / distances match the oracle
     as in test_assignment."""
@@ -619,8 +621,16 @@ def test_assignment_bound_odd_shapes(d2, d, m, mk_hi):
     print(f"[assign bound d={d} m={m} mk_hi={mk_hi}]", flush=True)
     wl = gaussian_mixture_workload(91 + d, 300, d, 4, mk_hi, 24, 6, 0.1, 1.0)
     K = 70
-    mem = pick_init_members(wl["offsets"], K, m, 13)
-    Xc, Wc = oracle.init_centroids(wl, mem, m)
+    if m <= mk_hi:
+        mem = pick_init_members(wl["offsets"], K, m, 13)
+        Xc, Wc = oracle.init_centroids(wl, mem, m)
+    else:
+        # centroids with more support points than any instance: points
+        # drawn from the whole workload, Dirichlet weights
+        rng = np.random.default_rng(17 + m)
+        X = wl["X"]
+        Xc = X[rng.integers(0, len(X), size=K * m)].reshape(K, m, d)
+        Wc = rng.dirichlet(np.ones(m), size=K)
     with _ctx(d2, wl, "f32") as ctx:
         ctx.centroids_set(Xc, Wc)
         lab_a, best_a, _ = ctx.assign(iters=50, prune=False)
