@@ -163,19 +163,20 @@ __device__ __forceinline__ void sum_col_n(T (&v)[NS]) {
   }
 }
 
-// Column sums by reduce-scatter (column groups of MP >= 16 lanes).  A
+// Column sums by reduce-scatter (column groups of MP >= 8 lanes).  A
 // lane's NS slots go in chunks of C = 8, 4, 2 or 1 slots, and register t of
 // a chunk holds slot t ^ mask(lane & 3).  An exchange with the quad lane of
 // the other parity adds, for the half of the chunk a lane keeps, the
 // partner's values of the same slots; an exchange with the other pair of
 // the quad halves the kept part again.  Each quad lane so ends with the
 // quad sums of max(1, C/4) slots, which are then summed over the quads of
-// the column group (row rotations by 8 and by 4, then across rows).  The
+// the column group (row rotations by 8 and by 4, then across rows; for
+// MP = 8 one swizzle with lane ^ 4).  The
 // mask places what a lane sends at the register index its partner keeps,
 // so the exchanges need no selects.  Each sum is formed in one lane per
 // quad and is bitwise the same in every quad of the group: the exchanges
-// pair lanes symmetrically (xor 1, 2, 8), and the last one, the rotation by
-// 4, adds two values that are already equal across lanes 8 apart.
+// pair lanes symmetrically (xor 1, 2, 8 or 4), and the rotation by 4 adds
+// two values that are already equal across lanes 8 apart.
 constexpr int rs_chunk_size(int left) {
   return left >= 8 ? 8 : (left >= 4 ? 4 : (left >= 2 ? 2 : 1));
 }
@@ -254,7 +255,7 @@ __device__ __forceinline__ float rs_pick(const float (&x)[NS]) {
 // registers.
 template <int MP, int C, typename T>
 __device__ __forceinline__ void rs_sum(T (&s)[C]) {
-  static_assert(MP >= 16, "reduce-scatter spans whole DPP rows");
+  static_assert(MP >= 8, "reduce-scatter needs two quads per column");
   constexpr int K = RsChunk<C>::kept;
   if constexpr (C >= 2) {
 #pragma unroll
@@ -268,8 +269,14 @@ __device__ __forceinline__ void rs_sum(T (&s)[C]) {
   if constexpr (C <= 2) s[0] += xdpp<0x4E>(s[0]);
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    s[k] += xdpp<0x128>(s[k]);  // row_ror:8 (lane ^ 8)
-    s[k] += xdpp<0x124>(s[k]);  // row_ror:4
+    if constexpr (MP == 8) {
+      // lane ^ 4 (a rotation by 4 would leave the 8-lane column group)
+      s[k] += __int_as_float(
+          __builtin_amdgcn_ds_swizzle(__float_as_int(s[k]), 0x101F));
+    } else {
+      s[k] += xdpp<0x128>(s[k]);  // row_ror:8 (lane ^ 8)
+      s[k] += xdpp<0x124>(s[k]);  // row_ror:4
+    }
     if constexpr (MP >= 32) s[k] += xswz16(s[k]);
     if constexpr (MP >= 64) s[k] += x32(s[k]);
   }
@@ -1797,12 +1804,13 @@ __device__ __forceinline__ double pair_value(const AssignArgs<T>& a,
     q[r] = T(0);
   }
   // exp2(-1e30) = 0: an entry outside the tile never takes mass
-  if constexpr (sizeof(T) == 4 && MP >= 16 && NS <= (MP >= 32 ? 32 : 8)) {
+  if constexpr (sizeof(T) == 4 && MP >= 8 && NS <= (MP >= 32 ? 32 : 8)) {
     // Column normalisation by reduce-scatter: the column sums and the
     // factors w_j / sum are formed once per quad instead of in every lane
     // (about a quarter fewer instructions per entry and iteration).  Tiles
-    // of 16 rows use it up to 8 slots only: the 16-slot kernel of that row
-    // padding would need 20 more registers and lose a wavefront per SIMD.
+    // of 8 and 16 rows use it up to 8 slots only: the 16-slot kernel of the
+    // 16-row padding would need 20 more registers and lose a wavefront per
+    // SIMD.
     const int ql = threadIdx.x & 3;
     // weights of the slots whose sums this lane holds (the chunks' kept
     // registers), in chunk order, taken from the first lane of the quad:
@@ -1828,11 +1836,12 @@ __device__ __forceinline__ double pair_value(const AssignArgs<T>& a,
          ...);
       }(std::make_integer_sequence<int, C>{});
     });
-    // For 16-row tiles l holds Lambda / rho in base-2 units (Lambda * a2):
+    // For 16-row tiles (and 8-row ones) l holds Lambda / rho in base-2
+    // units (Lambda * a2):
     // its update rho * (Pi1 - Pi2) becomes log2(e) * (Pi1 - Pi2), and the
     // exponents need no multiply (measured 2-5 % faster there, 2 % slower
     // for 32-row tiles, which keep Lambda itself)
-    constexpr bool SL = MP == 16;
+    constexpr bool SL = MP <= 16;
     const T lu = SL ? T(kLog2e) : rho;
     for (int it = 0; it < a.iters; ++it) {
       T rr = T(0);
