@@ -231,10 +231,29 @@ __device__ __forceinline__ float lane_sel(float a, float b,
   asm("v_cndmask_b32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(m));
   return r;
 }
+__device__ __forceinline__ double lane_sel(double a, double b,
+                                           unsigned long long m) {
+  const long long ab = __double_as_longlong(a), bb = __double_as_longlong(b);
+  const float lo = lane_sel(__int_as_float((int)ab), __int_as_float((int)bb), m);
+  const float hi = lane_sel(__int_as_float((int)(ab >> 32)),
+                            __int_as_float((int)(bb >> 32)), m);
+  return __longlong_as_double(((long long)__float_as_int(hi) << 32) |
+                              (unsigned int)__float_as_int(lo));
+}
+// exchange with lane ^ 4 (ds_swizzle, bit mode)
+__device__ __forceinline__ float xswz4(float v) {
+  return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x101F));
+}
+__device__ __forceinline__ double xswz4(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_ds_swizzle((int)(b & 0xffffffffLL), 0x101F);
+  const int hi = __builtin_amdgcn_ds_swizzle((int)(b >> 32), 0x101F);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
 // Slot value x[C0 + (t ^ mask(lane & 3))] of chunk register t, from a
 // lane's values in slot order (Q0: those of the first lane of its quad).
-template <int C0, int C, int t, bool Q0 = false, int NS>
-__device__ __forceinline__ float rs_pick(const float (&x)[NS]) {
+template <int C0, int C, int t, bool Q0 = false, int NS, typename T>
+__device__ __forceinline__ T rs_pick(const T (&x)[NS]) {
   constexpr unsigned long long kOdd = 0xAAAAAAAAAAAAAAAAull;   // lane & 1
   constexpr unsigned long long kPair = 0xCCCCCCCCCCCCCCCCull;  // lane & 2
   auto val = [&](int r) { return Q0 ? xdpp<0x00>(x[r]) : x[r]; };
@@ -243,10 +262,9 @@ __device__ __forceinline__ float rs_pick(const float (&x)[NS]) {
   } else if constexpr (C == 2) {
     return lane_sel(val(C0 + t), val(C0 + (t ^ 1)), kOdd);
   } else {
-    const float lo =
-        lane_sel(val(C0 + t), val(C0 + (t ^ (C / 2))), kOdd);
-    const float hi = lane_sel(val(C0 + (t ^ (C / 4))),
-                              val(C0 + (t ^ (C / 4) ^ (C / 2))), kOdd);
+    const T lo = lane_sel(val(C0 + t), val(C0 + (t ^ (C / 2))), kOdd);
+    const T hi = lane_sel(val(C0 + (t ^ (C / 4))),
+                          val(C0 + (t ^ (C / 4) ^ (C / 2))), kOdd);
     return lane_sel(lo, hi, kPair);
   }
 }
@@ -271,8 +289,7 @@ __device__ __forceinline__ void rs_sum(T (&s)[C]) {
   for (int k = 0; k < K; ++k) {
     if constexpr (MP == 8) {
       // lane ^ 4 (a rotation by 4 would leave the 8-lane column group)
-      s[k] += __int_as_float(
-          __builtin_amdgcn_ds_swizzle(__float_as_int(s[k]), 0x101F));
+      s[k] += xswz4(s[k]);
     } else {
       s[k] += xdpp<0x128>(s[k]);  // row_ror:8 (lane ^ 8)
       s[k] += xdpp<0x124>(s[k]);  // row_ror:4
@@ -1804,13 +1821,18 @@ __device__ __forceinline__ double pair_value(const AssignArgs<T>& a,
     q[r] = T(0);
   }
   // exp2(-1e30) = 0: an entry outside the tile never takes mass
-  if constexpr (sizeof(T) == 4 && MP >= 8 && NS <= (MP >= 32 ? 32 : 8)) {
+  if constexpr (sizeof(T) == 4 ? MP >= 8 && NS <= (MP >= 32 ? 32 : 8)
+                                : MP >= 16 && NS <= 4) {
     // Column normalisation by reduce-scatter: the column sums and the
     // factors w_j / sum are formed once per quad instead of in every lane
-    // (about a quarter fewer instructions per entry and iteration).  Tiles
-    // of 8 and 16 rows use it up to 8 slots only: the 16-slot kernel of the
+    // (about a quarter fewer instructions per entry and iteration; in FP64
+    // one division per column and quad instead of one per entry).  Tiles of
+    // 8 and 16 rows use it up to 8 slots only: the 16-slot kernel of the
     // 16-row padding would need 20 more registers and lose a wavefront per
-    // SIMD.
+    // SIMD.  FP64 uses it for tiles of 16 rows or more up to 4 slots (its
+    // 8-row 8-slot kernel would lose a wavefront, its wider-slot kernels
+    // spill more, and with 5-8 slots the later rounds on d = 16 measured
+    // slower).
     const int ql = threadIdx.x & 3;
     // weights of the slots whose sums this lane holds (the chunks' kept
     // registers), in chunk order, taken from the first lane of the quad:
